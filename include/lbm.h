@@ -1,0 +1,160 @@
+/*
+ * lbm.h - C ABI of the MI355X lattice Boltzmann particle-resolved library.
+ *
+ * The library advances a D3Q19 multiple-relaxation-time lattice Boltzmann
+ * flow on one GPU, with the two no-slip treatments for moving resolved
+ * spheres compared in Peng, Ayala, Brandle de Motta & Wang (arXiv 1906.05448):
+ * interpolated bounce-back with refilling, and the immersed boundary method
+ * with a 4-point delta. Section references below are to that paper.
+ *
+ * Conventions (every entry point):
+ *  - Return an int status: LBM_OK (0) or a negative lbm_status. Nothing
+ *    throws, aborts or exits across this boundary; lbm_strerror() gives text.
+ *  - Device memory is owned by the caller: one workspace of
+ *    lbm_workspace_size() bytes, 256-byte aligned, handed to lbm_init() and
+ *    kept alive until lbm_destroy(). The library never allocates device
+ *    memory itself.
+ *  - All GPU work is enqueued on the HIP stream given to lbm_init(). Calls
+ *    marked "async" return before the work finishes; calls marked "sync"
+ *    wait for the stream and report errors latched by earlier async calls.
+ *  - Host pointers are read or written before the call returns and are
+ *    never retained.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Lattice arrays are laid out [component][z][y][x], x fastest; node
+ *    (x, y, z) sits at coordinate (x, y, z); N = nx*ny*nz. The box is
+ *    periodic in all three directions (Sec. 2.1, Sec. 3.1).
+ *  - Units are lattice units: dx = dt = 1, reference density 1.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_ARG = -1,      /* invalid argument or configuration              */
+  LBM_E_HIP = -2,      /* a HIP runtime call failed                       */
+  LBM_E_SIZE = -3,     /* workspace too small, or a capacity exceeded     */
+  LBM_E_STATE = -4,    /* call not valid in the context's current state   */
+  LBM_E_UNSTABLE = -5, /* non-finite density/velocity or |u| above 0.35   */
+  LBM_E_OVERLAP = -6   /* two particles overlap by more than half a radius*/
+} lbm_status;
+
+/* No-slip treatment on particle surfaces and walls (Sec. 2.1, Sec. 3.1). */
+enum { LBM_BC_NONE = 0, LBM_BC_IBB = 1, LBM_BC_IBM = 2 };
+/* Population storage: FP32 or IEEE half of the shifted value f_i - w_i.
+ * Collision arithmetic is FP32 in both cases. */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16S = 1 };
+/* Static wall: none, or a pipe with its axis along z (Sec. 2.1). */
+enum { LBM_WALL_NONE = 0, LBM_WALL_PIPE_Z = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;        /* lattice size, each >= 4                      */
+  double tau;                /* shear relaxation time, > 0.5;
+                                nu = (tau - 1/2)/3, rate s_nu = 1/tau        */
+  double s_e, s_eps, s_q, s_pi, s_m; /* remaining d'Humieres MRT rates,
+                                each in (0, 2); Sec. 3.1 names the model,
+                                usual values 1.19, 1.4, 1.2, 1.4, 1.98.
+                                s_e sets the bulk viscosity (Sec. 2.2.2)     */
+  double body_force[3];      /* rho*g per unit volume (Sec. 2.1)             */
+  int32_t bc;                /* LBM_BC_*                                      */
+  int32_t ibb_max_order;     /* 2: quadratic with fallback chain, 1: linear  */
+  double ibm_retraction;     /* r_d in lattice units: 0 (Uhlmann), 0.4
+                                (Breugem), Sec. 2.1 and Sec. 3.1             */
+  int32_t ibm_iters;         /* forcing passes after the first prediction;
+                                the paper uses 2 (Sec. 2.1)                  */
+  int32_t store;             /* LBM_STORE_*                                  */
+  int32_t wall;              /* LBM_WALL_*                                   */
+  double pipe_radius, pipe_cx, pipe_cy; /* pipe wall, lattice units         */
+  int32_t max_particles;     /* capacity reserved in the workspace           */
+  double max_radius;         /* largest sphere radius that will be set       */
+  double coll_restitution;   /* soft-sphere normal restitution (Sec. 3.1)    */
+  double coll_tc_steps;      /* soft-sphere contact duration, time steps     */
+} lbm_config;
+
+/* Fills *cfg with defaults: 32^3, tau 0.6, the usual d'Humieres rates, no
+ * force, no boundary, FP32 storage, ibm_iters 2, restitution 0.97, contact
+ * time 8 steps. */
+void lbm_config_default(lbm_config* cfg);
+
+/* Bytes of device workspace a context with this configuration needs.
+ * Errors: LBM_E_ARG for an invalid configuration. */
+int lbm_workspace_size(const lbm_config* cfg, size_t* bytes);
+
+/* Creates a context on the current HIP device. workspace: device pointer,
+ * 256-byte aligned, >= lbm_workspace_size() bytes, owned by the caller.
+ * stream: a hipStream_t (NULL = default stream). The lattice starts at rest
+ * with density 1. Errors: LBM_E_ARG, LBM_E_SIZE, LBM_E_HIP. */
+int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes,
+             void* stream, lbm_ctx** out);
+
+/* Sets every node to the equilibrium of (rho, u): u host [3][N] FP32,
+ * rho host [N] FP32 or NULL for 1. Resets the step counter. Sync. */
+int lbm_set_fields(lbm_ctx* ctx, const float* u, const float* rho);
+
+/* Same, from device pointers on the context's stream. Async. */
+int lbm_set_fields_device(lbm_ctx* ctx, const float* u_dev, const float* rho_dev);
+
+/* Advances nsteps time steps (Sec. 2.1, Sec. 3.1): pull streaming fused
+ * with MRT collision and body/boundary forcing, the no-slip treatment and
+ * the particle update. Async; instability latches and is reported by the
+ * next sync call. Errors: LBM_E_ARG if nsteps < 0. */
+int lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Density and half-force velocity u = (sum_i c_i f_i + F/2)/rho of the
+ * current step at every node, to host [N] and [3][N] FP32 (either may be
+ * NULL). At nodes inside an interpolated-bounce-back particle the values
+ * are undefined. Sync. */
+int lbm_get_fields(lbm_ctx* ctx, float* u, float* rho);
+
+/* Same, into device buffers on the context's stream. Async. */
+int lbm_get_fields_device(lbm_ctx* ctx, float* u_dev, float* rho_dev);
+
+/* Waits for the stream; returns the first latched error, if any. */
+int lbm_sync(lbm_ctx* ctx);
+
+/* Number of completed time steps since the last lbm_set_fields(). */
+int lbm_step_count(const lbm_ctx* ctx, int64_t* step);
+
+/* Kernel classes for lbm_profile_read(). */
+enum {
+  LBM_K_STREAM_COLLIDE = 0, /* fused pull-stream + MRT collision, all nodes  */
+  LBM_K_GEOMETRY = 1,       /* solid mask, boundary links, support sets      */
+  LBM_K_IBB_LINKS = 2,      /* interpolated bounce-back + link forces        */
+  LBM_K_REFILL = 3,         /* refilling of uncovered nodes                  */
+  LBM_K_IBM_PREPASS = 4,    /* density/velocity at immersed-boundary support */
+  LBM_K_IBM_FORCING = 5,    /* interpolate / spread passes                   */
+  LBM_K_PARTICLE = 6,       /* per-particle reductions, motion, contacts     */
+  LBM_K_STATS = 7,          /* statistics                                    */
+  LBM_K_CORRECTOR = 8,      /* learned gradient corrector                    */
+  LBM_NPROF = 9
+};
+
+/* Enables (on != 0) or disables per-kernel timing: every kernel that
+ * lbm_step() launches is bracketed by HIP events on the context's stream,
+ * grouped by the classes above. Timing adds event overhead; leave it off
+ * for throughput runs. */
+int lbm_profile_enable(lbm_ctx* ctx, int32_t on);
+
+/* Sync. Writes, per class, the summed kernel time in milliseconds and the
+ * number of timed launches since the last read (arrays of LBM_NPROF), then
+ * resets the counters. Either pointer may be NULL. */
+int lbm_profile_read(lbm_ctx* ctx, double* ms, int64_t* launches);
+
+/* Releases the context (not the caller's workspace). NULL is ignored. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Static text for a status code. */
+const char* lbm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

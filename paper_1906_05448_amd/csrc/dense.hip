@@ -1,0 +1,153 @@
+// dense.hip - the lattice-wide kernels: fused pull-stream + MRT collision,
+// equilibrium initialisation and macroscopic-field extraction.
+//
+// Memory layout: structure of arrays, population i of node n at
+// f[i * N + n], n = x + nx * (y + ny * z). The pull form
+//   f_i(x, t+1) = f~_i(x - c_i, t)
+// reads each of the 19 arrays once, shifted by c_i, and writes each once,
+// so one node update moves 19 * 2 * sizeof(store) bytes of HBM: 152 B in
+// FP32, 76 B with FP16 shifted storage. Reads of a row shifted by one in x
+// straddle cache lines shared with the neighbouring tile; the XCD-aware tile
+// order keeps that neighbour in the same L2.
+#include "internal.hpp"
+
+namespace lbm {
+
+namespace {
+
+struct Tile {
+  int x, y, z;
+  bool live;
+};
+
+__device__ __forceinline__ Tile tile_coords(const Dims& d) {
+  // Physical workgroup b runs on XCD b % 8; give each XCD a contiguous
+  // range of logical tiles.
+  const uint32_t b = blockIdx.x;
+  const uint32_t logical = (b & 7u) * d.per_xcd + (b >> 3);
+  Tile t;
+  t.live = logical < d.ntiles;
+  const uint32_t bx = logical % d.gx;
+  const uint32_t rest = logical / d.gx;
+  const uint32_t by = rest % d.gy;
+  const uint32_t bz = rest / d.gy;
+  t.x = (int)(bx * 64u + (threadIdx.x & 63u));
+  t.y = (int)(by * 4u + (threadIdx.x >> 6));
+  t.z = (int)bz;
+  t.live = t.live && t.x < d.nx && t.y < d.ny;
+  return t;
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(256)
+k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STORE>::T* __restrict__ B,
+                 Dims d, MrtRates r, float3 F, uint32_t* __restrict__ err) {
+  using P = Pop<STORE>;
+  const Tile t = tile_coords(d);
+  if (!t.live) return;
+  const int x = t.x, y = t.y, z = t.z;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const uint32_t N = d.N;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  auto row = [&](int yy, int zz) -> uint32_t { return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx; };
+  const uint32_t r00 = row(y, z), rm0 = row(ym, z), rp0 = row(yp, z);
+  const uint32_t r0m = row(y, zm), r0p = row(y, zp);
+  const uint32_t rmm = row(ym, zm), rmp = row(ym, zp), rpp = row(yp, zp), rpm = row(yp, zm);
+
+  // Source node of direction i is x - c_i.
+  const uint32_t src[kQ] = {
+      r00 + x,                                                      // 0
+      r00 + xm, rm0 + x, r0m + x,                                   // 1..3
+      rm0 + xm, rp0 + xm, r0m + xm, r0p + xm, rmm + x, rmp + x,    // 4..9
+      r00 + xp, rp0 + x, r0p + x,                                   // 10..12
+      rp0 + xp, rm0 + xp, r0p + xp, r0m + xp, rpp + x, rpm + x};   // 13..18
+
+  float g[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) g[i] = P::load(A + (size_t)i * N + src[i]);
+
+  float rho, ux, uy, uz;
+  mrt_collide(g, F.x, F.y, F.z, r, rho, ux, uy, uz);
+
+  const uint32_t n = r00 + (uint32_t)x;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) P::store(B + (size_t)i * N + n, g[i]);
+
+  const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
+  if (bad) atomicOr(err, kErrUnstable);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(256)
+k_init_equilibrium(const float* __restrict__ u, const float* __restrict__ rho, typename Pop<STORE>::T* __restrict__ f,
+                   uint32_t N) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= N) return;
+  const float r = rho ? rho[n] : 1.0f;
+  const float ux = u[n], uy = u[(size_t)N + n], uz = u[2 * (size_t)N + n];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) Pop<STORE>::store(f + (size_t)i * N + n, geq(i, r, ux, uy, uz));
+}
+
+// rho and u from post-collision populations: the Guo collision adds F to the
+// momentum, so sum_i c_i f~_i = rho u + F/2 and u = (sum_i c_i f~_i - F/2)/rho.
+template <int STORE>
+__global__ void __launch_bounds__(256)
+k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F, float* __restrict__ u,
+         float* __restrict__ rho) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= N) return;
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float g = Pop<STORE>::load(f + (size_t)i * N + n);
+    drho += g;
+    jx += cx_of(i) * g;
+    jy += cy_of(i) * g;
+    jz += cz_of(i) * g;
+  }
+  const float r = 1.0f + drho;
+  if (rho) rho[n] = r;
+  if (u) {
+    u[n] = (jx - 0.5f * F.x) / r;
+    u[(size_t)N + n] = (jy - 0.5f * F.y) / r;
+    u[2 * (size_t)N + n] = (jz - 0.5f * F.z) / r;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rho, void* f) {
+  const uint32_t N = c.dims.N;
+  const dim3 grid((N + 255) / 256), block(256);
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_init_equilibrium<0>, grid, block, 0, c.stream, u, rho, (float*)f, N);
+  else
+    hipLaunchKernelGGL(k_init_equilibrium<1>, grid, block, 0, c.stream, u, rho, (_Float16*)f, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
+  const dim3 grid(c.dims.per_xcd * 8), block(256);
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_stream_collide<0>, grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims, c.rates,
+                       c.body_force, c.err);
+  else
+    hipLaunchKernelGGL(k_stream_collide<1>, grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B, c.dims,
+                       c.rates, c.body_force, c.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(const Ctx& c, const void* f, float* u, float* rho) {
+  const uint32_t N = c.dims.N;
+  const dim3 grid((N + 255) / 256), block(256);
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_fields<0>, grid, block, 0, c.stream, (const float*)f, N, c.body_force, u, rho);
+  else
+    hipLaunchKernelGGL(k_fields<1>, grid, block, 0, c.stream, (const _Float16*)f, N, c.body_force, u, rho);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,231 @@
+"""ctypes binding of liblbm.so (declared in include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. PyTorch supplies the device workspace and the stream. The
+binding refuses to work without the compiled library; there is no other
+execution path.
+"""
+import ctypes
+import dataclasses
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "liblbm.so"
+_lib = None
+
+BC_NONE, BC_IBB, BC_IBM = 0, 1, 2
+STORE_F32, STORE_F16S = 0, 1
+WALL_NONE, WALL_PIPE_Z = 0, 1
+KERNEL_CLASSES = ("stream_collide", "geometry", "ibb_links", "refill", "ibm_prepass", "ibm_forcing",
+                  "particle", "stats", "corrector")
+NPROF = len(KERNEL_CLASSES)
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.lbm_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class _CConfig(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("s_pi", ctypes.c_double), ("s_m", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+        ("bc", ctypes.c_int32), ("ibb_max_order", ctypes.c_int32),
+        ("ibm_retraction", ctypes.c_double), ("ibm_iters", ctypes.c_int32),
+        ("store", ctypes.c_int32), ("wall", ctypes.c_int32),
+        ("pipe_radius", ctypes.c_double), ("pipe_cx", ctypes.c_double), ("pipe_cy", ctypes.c_double),
+        ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double),
+        ("coll_restitution", ctypes.c_double), ("coll_tc_steps", ctypes.c_double),
+    ]
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_1906_05448_amd/_build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(str(_LIB_PATH))
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    cfgp = ctypes.POINTER(_CConfig)
+    sig = {
+        "lbm_config_default": (None, [cfgp]),
+        "lbm_workspace_size": (ctypes.c_int, [cfgp, ctypes.POINTER(SZ)]),
+        "lbm_init": (ctypes.c_int, [cfgp, P, SZ, P, ctypes.POINTER(P)]),
+        "lbm_set_fields": (ctypes.c_int, [P, P, P]),
+        "lbm_set_fields_device": (ctypes.c_int, [P, P, P]),
+        "lbm_step": (ctypes.c_int, [P, I32]),
+        "lbm_get_fields": (ctypes.c_int, [P, P, P]),
+        "lbm_get_fields_device": (ctypes.c_int, [P, P, P]),
+        "lbm_sync": (ctypes.c_int, [P]),
+        "lbm_step_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        "lbm_profile_enable": (ctypes.c_int, [P, I32]),
+        "lbm_profile_read": (ctypes.c_int, [P, P, P]),
+        "lbm_destroy": (None, [P]),
+        "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+@dataclasses.dataclass
+class Config:
+    """Mirror of lbm_config; field meanings are documented in include/lbm.h."""
+    nx: int = 32
+    ny: int = 32
+    nz: int = 32
+    tau: float = 0.6
+    s_e: float = 1.19
+    s_eps: float = 1.4
+    s_q: float = 1.2
+    s_pi: float = 1.4
+    s_m: float = 1.98
+    body_force: tuple = (0.0, 0.0, 0.0)
+    bc: int = BC_NONE
+    ibb_max_order: int = 2
+    ibm_retraction: float = 0.0
+    ibm_iters: int = 2
+    store: int = STORE_F32
+    wall: int = WALL_NONE
+    pipe_radius: float = 0.0
+    pipe_cx: float = 0.0
+    pipe_cy: float = 0.0
+    max_particles: int = 0
+    max_radius: float = 0.0
+    coll_restitution: float = 0.97
+    coll_tc_steps: float = 8.0
+
+    def to_c(self) -> _CConfig:
+        c = _CConfig()
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            if f.name == "body_force":
+                c.body_force = (ctypes.c_double * 3)(*map(float, v))
+            else:
+                setattr(c, f.name, v)
+        return c
+
+    @property
+    def shape(self):
+        return (self.nx, self.ny, self.nz)
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise LbmError(status, where)
+
+
+def _host_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def workspace_size(cfg: Config) -> int:
+    L = lib()
+    n = ctypes.c_size_t()
+    _check(L.lbm_workspace_size(ctypes.byref(cfg.to_c()), ctypes.byref(n)), "lbm_workspace_size")
+    return n.value
+
+
+class Lattice:
+    """One simulation context on the current GPU.
+
+    The workspace is a torch uint8 tensor owned by this object; all work runs
+    on ``stream`` (default: torch's current stream)."""
+
+    def __init__(self, cfg: Config, device=None, stream=None):
+        import torch
+        self._torch = torch
+        self.cfg = cfg
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = workspace_size(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.lbm_init(ctypes.byref(cfg.to_c()), ctypes.c_void_p(self.workspace.data_ptr()),
+                              ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(h)), "lbm_init")
+        self._h = h
+
+    # -- fields ---------------------------------------------------------
+    def set_fields(self, u, rho=None) -> None:
+        """u: [3, nz, ny, nx] array-like (converted to FP32); rho optional."""
+        N = self.cfg.n_nodes
+        u32 = np.ascontiguousarray(np.asarray(u, dtype=np.float32).reshape(3, N))
+        r32 = None if rho is None else np.ascontiguousarray(np.asarray(rho, np.float32).reshape(N))
+        _check(lib().lbm_set_fields(self._h, _host_ptr(u32), None if r32 is None else _host_ptr(r32)),
+               "lbm_set_fields")
+
+    def set_fields_device(self, u, rho=None) -> None:
+        """u: torch float32 CUDA tensor [3, nz, ny, nx], rho optional."""
+        assert u.is_cuda and u.dtype == self._torch.float32 and u.is_contiguous()
+        _check(lib().lbm_set_fields_device(self._h, ctypes.c_void_p(u.data_ptr()),
+                                           None if rho is None else ctypes.c_void_p(rho.data_ptr())),
+               "lbm_set_fields_device")
+
+    def get_fields(self):
+        """Returns (u [3, nz, ny, nx], rho [nz, ny, nx]) as float32 numpy."""
+        nx, ny, nz = self.cfg.shape
+        u = np.empty((3, nz, ny, nx), np.float32)
+        rho = np.empty((nz, ny, nx), np.float32)
+        _check(lib().lbm_get_fields(self._h, _host_ptr(u), _host_ptr(rho)), "lbm_get_fields")
+        return u, rho
+
+    def get_fields_device(self, u, rho=None) -> None:
+        _check(lib().lbm_get_fields_device(self._h, ctypes.c_void_p(u.data_ptr()) if u is not None else None,
+                                           None if rho is None else ctypes.c_void_p(rho.data_ptr())),
+               "lbm_get_fields_device")
+
+    # -- time stepping -------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        _check(lib().lbm_step(self._h, int(n)), "lbm_step")
+
+    def sync(self) -> None:
+        _check(lib().lbm_sync(self._h), "lbm_sync")
+
+    @property
+    def step_count(self) -> int:
+        s = ctypes.c_int64()
+        _check(lib().lbm_step_count(self._h, ctypes.byref(s)), "lbm_step_count")
+        return s.value
+
+    # -- kernel timing ----------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        _check(lib().lbm_profile_enable(self._h, 1 if on else 0), "lbm_profile_enable")
+
+    def profile_read(self):
+        """Returns {class name: (total ms, launches)} since the last read."""
+        ms = np.zeros(NPROF, np.float64)
+        n = np.zeros(NPROF, np.int64)
+        _check(lib().lbm_profile_read(self._h, _host_ptr(ms), _host_ptr(n)), "lbm_profile_read")
+        return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(KERNEL_CLASSES)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

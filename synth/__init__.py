@@ -9,8 +9,8 @@ other.
 All randomness is numpy ``default_rng(seed)`` (PCG64).
 """
 from .fields import (HitSpectrum, hit_spectrum, hit_field, hit_field_at,
-                     pipe_initial_velocity, random_velocity)
+                     pipe_initial_velocity, random_density, random_velocity)
 from .particles import random_spheres
 
 __all__ = ["HitSpectrum", "hit_spectrum", "hit_field", "hit_field_at",
-           "pipe_initial_velocity", "random_velocity", "random_spheres"]
+           "pipe_initial_velocity", "random_density", "random_velocity", "random_spheres"]

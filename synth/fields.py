@@ -136,3 +136,10 @@ def random_velocity(shape, amp: float, seed: int) -> np.ndarray:
     nx, ny, nz = shape
     rng = np.random.default_rng(seed)
     return rng.uniform(-amp, amp, size=(3, nz, ny, nx))
+
+
+def random_density(shape, amp: float, seed: int) -> np.ndarray:
+    """1 + iid uniform in [-amp, amp]; shape (nx, ny, nz) -> [nz, ny, nx]."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    return 1.0 + rng.uniform(-amp, amp, size=(nz, ny, nx))
