@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the lattice Boltzmann hot path on one MI355X.
+"""Throughput of the lattice Boltzmann particle-resolved hot path on one MI355X.
+
+Workload (production case): 512^3 periodic decaying isotropic turbulence,
+D3Q19 MRT, tau 0.52, seeded random-phase field with E(k) ~ k^4 exp(-2 (k/4)^2)
+and u_rms 0.03, 6250 freely moving neutrally buoyant spheres of radius 8
+(volume fraction ~10%) released into the field (velocity = fluid average over
+the particle, zero spin), soft-sphere contacts. A step is one full lbm_step:
+boundary treatment, fused stream + collide, particle forces and motion,
+geometry rebuild and refilling.
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value        million lattice-node updates per second (MLUPS) over all N
-               nodes, whole step (every kernel of lbm_step), inputs resident
-               in HBM
+               nodes for the headline variant, inputs resident in HBM
   roofline     the dominant kernel (fused stream + collide): algorithmic
                bytes per launch / its average duration, timed with HIP events
                on the launch stream, against the 8 TB/s HBM peak
   cpu_baseline the FP64 oracle, single-threaded, on a bounded sample of the
-               same workload on this host
+               same recipe on this host
+  variants     every variant measured (boundary treatment x storage)
 """
 import argparse
 import json
@@ -27,6 +35,8 @@ METRIC = "MLUPS at 512^3 particle-laden D3Q19 (%HBM roofline), FP32/FP16 vs FP64
 HBM_PEAK_GBS = 8000.0
 U_RMS = 0.03
 TAU = 0.52
+RADIUS = 8.0
+MIN_GAP = 2.0          # centre distance >= 2r + 2 at placement
 
 
 def log(*a):
@@ -39,19 +49,21 @@ def parse():
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--n", type=int, default=512, help="lattice edge (production: 512)")
-    p.add_argument("--stores", default="f16s,f32", help="storage variants; the first is the headline")
+    p.add_argument("--particles", type=int, default=6250)
+    p.add_argument("--variants", default="ibb-f16s,ibb-f32,none-f16s,none-f32",
+                   help="comma list of <bc>-<store>, bc in ibb|none, store in f16s|f32; the first is the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     return p.parse_args()
 
 
-def bytes_per_node(store: int) -> int:
-    return 19 * 2 * (4 if store == 0 else 2)
-
-
-def run_variant(torch, lbm, n, store, u0_dev, steps, warmup):
-    cfg = lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store)
+def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup):
+    cfg = lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store, bc=bc,
+                     max_particles=len(X) if bc != lbm.BC_NONE else 0, max_radius=RADIUS)
     lat = lbm.Lattice(cfg)
     lat.set_fields_device(u0_dev)
+    if bc != lbm.BC_NONE and len(X):
+        lat.set_particles(X, RADIUS, mode=lbm.RELEASE, motion=lbm.MOTION_FREE)
+    solid, links = lat.geometry_counts() if bc == lbm.BC_IBB else (0, 0)
     lat.step(warmup)
     lat.sync()
     stream = lat.stream
@@ -74,40 +86,47 @@ def run_variant(torch, lbm, n, store, u0_dev, steps, warmup):
     del lat
     torch.cuda.empty_cache()
     N = n ** 3
+    s = 4 if store == lbm.STORE_F32 else 2
     k_ms, k_n = prof["stream_collide"]
     k_avg = k_ms / max(k_n, 1)
-    alg_bytes = bytes_per_node(store) * N
+    # Algorithmic bytes of the fused kernel: 19 populations read and written
+    # per updated node (fluid nodes only with bounce-back) plus the solid
+    # bitmask when it is consulted.
+    alg_bytes = 38 * s * (N - solid) + (N // 8 if bc == lbm.BC_IBB else 0)
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
     return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
-                kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes,
-                achieved_gbs=achieved,
-                kernels={k: dict(ms=v[0], launches=v[1]) for k, v in prof.items() if v[1]})
+                kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes, achieved_gbs=achieved,
+                solid_nodes=solid, links=links,
+                kernels_ms_per_step={k: v[0] / max(v[1], 1) * v[1] / steps for k, v in prof.items() if v[1]})
 
 
 def cpu_baseline():
-    """The FP64 oracle, one thread, on a 64^3 box of the same turbulence
-    field (about 10-20 s of CPU work)."""
+    """The FP64 oracle, one thread, on a 64^3 box of the same recipe (12
+    released spheres of radius 8, ~10% volume fraction, bounce-back), a few
+    steps: about 10-20 s of CPU work."""
     from threadpoolctl import threadpool_limits
 
     import synth
-    from oracle.sim import Config as OConfig, Sim as OSim
+    from oracle.sim import RELEASE, Config as OConfig, Sim as OSim
     n = 64
     spec = synth.hit_spectrum(seed=0, u_rms=U_RMS)
     u0 = synth.hit_field(spec, (n, n, n))
+    X = synth.random_spheres(12, (n, n, n), 2 * RADIUS + MIN_GAP, seed=0)
     with threadpool_limits(limits=1):
-        sim = OSim(OConfig(shape=(n, n, n), tau=TAU))
+        sim = OSim(OConfig(shape=(n, n, n), tau=TAU, bc="ibb"))
         sim.set_fields(u0)
+        sim.set_particles(X, r=np.full(len(X), RADIUS), mode=RELEASE)
         sim.step(1)
         t = time.perf_counter()
         sim.step(1)
         one = time.perf_counter() - t
-        steps = max(2, min(400, int(12.0 / max(one, 1e-3))))
+        steps = max(2, min(200, int(12.0 / max(one, 1e-3))))
         t = time.perf_counter()
         sim.step(steps)
         dt = time.perf_counter() - t
     return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{n}^3 periodic box, same spectrum and tau, no particles, {steps} steps, "
-                       f"{dt:.1f} s, numpy FP64 single thread")
+                sample=f"{n}^3 box of the same recipe with 12 spheres r=8 (bounce-back, FP64), {steps} steps, "
+                       f"{dt:.1f} s, numpy single thread")
 
 
 def main():
@@ -123,21 +142,25 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.n
-    stores = [{"f32": lbm.STORE_F32, "f16s": lbm.STORE_F16S}[s] for s in args.stores.split(",")]
-    log(f"bench: generating {n}^3 seeded turbulence field")
+    bcs = {"ibb": lbm.BC_IBB, "none": lbm.BC_NONE}
+    stores = {"f32": lbm.STORE_F32, "f16s": lbm.STORE_F16S}
+    variants = [v.split("-") for v in args.variants.split(",")]
+    log(f"bench: {n}^3 seeded turbulence field and {args.particles} sphere centres")
     spec = synth.hit_spectrum(seed=0, u_rms=U_RMS)
     u0 = torch.from_numpy(synth.hit_field(spec, (n, n, n), dtype=np.float32)).cuda()
+    X = synth.random_spheres(args.particles, (n, n, n), 2 * RADIUS + MIN_GAP, seed=0)
     results = {}
-    for st in stores:
-        name = "f32" if st == lbm.STORE_F32 else "f16s"
+    for bc, st in variants:
+        name = f"{bc}-{st}"
         log(f"bench: variant {name}: warmup {args.warmup}, timed {args.steps} steps")
-        results[name] = run_variant(torch, lbm, n, st, u0, args.steps, args.warmup)
+        results[name] = run_variant(torch, lbm, n, bcs[bc], stores[st], u0, X, args.steps, args.warmup)
         r = results[name]
-        log(f"bench: {name}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, "
-            f"kernel {r['kernel_avg_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s")
+        log(f"bench: {name}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, stream_collide "
+            f"{r['kernel_avg_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s; per step {r['kernels_ms_per_step']}")
     del u0
-    head_name = "f32" if stores[0] == lbm.STORE_F32 else "f16s"
+    head_name = "-".join(variants[0])
     head = results[head_name]
+    hb, hs = variants[0]
     out = {
         "metric": METRIC,
         "value": round(head["mlups"], 1),
@@ -151,9 +174,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{n}^3 periodic decaying turbulence, D3Q19 MRT, tau {TAU}, "
-                               f"u_rms {U_RMS}, no particles",
-                   "lattice": [n, n, n], "storage": head_name, "particles": 0},
+        "config": {"workload": f"{n}^3 periodic decaying turbulence with {args.particles} released spheres "
+                               f"r={RADIUS:g} (phi~10%), D3Q19 MRT tau {TAU}, u_rms {U_RMS}",
+                   "lattice": [n, n, n], "particles": args.particles if hb != "none" else 0, "radius": RADIUS,
+                   "boundary": {"ibb": "interpolated bounce-back (quadratic, fallback chain, refill)",
+                                "none": "no particles"}[hb],
+                   "storage": {"f16s": "FP16 shifted populations, FP32 collision",
+                               "f32": "FP32 shifted populations"}[hs]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_stream_collide", "alg_bytes_per_launch": head["alg_bytes"],

@@ -123,6 +123,52 @@ int lbm_sync(lbm_ctx* ctx);
 /* Number of completed time steps since the last lbm_set_fields(). */
 int lbm_step_count(const lbm_ctx* ctx, int64_t* step);
 
+/* lbm_set_particles() modes. LBM_RELEASE follows Sec. 3.1: each particle
+ * starts with the fluid velocity averaged over its volume (weighted by the
+ * cell solid fraction) and zero angular velocity, and the populations at its
+ * nodes are reset once to the equilibrium of the local density and that
+ * velocity. LBM_SET_STATE takes u and omega as given. */
+enum { LBM_SET_STATE = 0, LBM_RELEASE = 1 };
+/* Particle motion: free (equations of motion with hydrodynamic and contact
+ * forces), fixed in place, or prescribed (centres advance with the given
+ * constant velocities). Forces are evaluated in every mode. */
+enum { LBM_MOTION_FREE = 0, LBM_MOTION_FIXED = 1, LBM_MOTION_PRESCRIBED = 2 };
+
+/* Places np rigid spheres (Sec. 3.1). Host arrays: x, u, omega [np][3]
+ * (u, omega may be NULL for zero), radius [np], rho_p [np] (NULL for 1).
+ * Centres are wrapped into the box. Requires bc = LBM_BC_IBB or LBM_BC_IBM,
+ * np <= max_particles, 0 < radius <= max_radius, 2*radius + 8 <= min(nx,
+ * ny, nz), no pipe wall; the immersed boundary needs one common radius.
+ * Rebuilds the boundary geometry. Sync. Errors: LBM_E_ARG, LBM_E_SIZE. */
+int lbm_set_particles(lbm_ctx* ctx, int32_t np, const double* x, const double* u, const double* omega,
+                      const double* radius, const double* rho_p, int32_t mode, int32_t motion);
+
+/* Current particle state to host [np][3] arrays (any may be NULL). Sync. */
+int lbm_get_particles(lbm_ctx* ctx, double* x, double* u, double* omega);
+
+/* Hydrodynamic force and torque that entered the last particle update, and
+ * the contact force, to host [np][3] (any may be NULL). Interpolated
+ * bounce-back: sum of the link forces (Wen et al. momentum exchange) plus
+ * the momentum of nodes covered/uncovered in the previous step. Immersed
+ * boundary: minus the sum of the marker forces plus the change of the inner
+ * fluid momentum (Kempe et al.). Sync. */
+int lbm_forces(lbm_ctx* ctx, double* F, double* T, double* F_contact);
+
+/* Number of boundary links of the current geometry (spheres and wall). Sync. */
+int lbm_link_count(lbm_ctx* ctx, int64_t* n);
+
+/* Copies up to cap links to host arrays: fluid node (x, y, z) [cap][3],
+ * lattice direction c (towards the solid) [cap][3], owning particle [cap]
+ * (-1 for the wall), wall fraction q [cap], scheme [cap] (2 quadratic,
+ * 1 linear, 0 single-node). *n gets the number copied. Sync. */
+int lbm_get_links(lbm_ctx* ctx, int64_t cap, int32_t* node, int32_t* dir, int32_t* particle, float* q,
+                  int32_t* scheme, int64_t* n);
+
+/* Sizes of the current geometry: nodes inside solids (spheres and wall,
+ * interpolated bounce-back) and boundary links; either pointer may be NULL.
+ * Sync. */
+int lbm_geometry_counts(lbm_ctx* ctx, int64_t* solid_nodes, int64_t* links);
+
 /* Kernel classes for lbm_profile_read(). */
 enum {
   LBM_K_STREAM_COLLIDE = 0, /* fused pull-stream + MRT collision, all nodes  */

@@ -62,7 +62,7 @@ def bounce_values(ft, links, uw, shape):
     fb0 = _at(ft, ab, xf, shape)
     fb1 = _at(ft, ab, xf - c, shape)
     delta = -6.0 * W[a] * (CF[a] * uw).sum(1)
-    with np.errstate(invalid="ignore"):
+    with np.errstate(invalid="ignore", divide="ignore"):   # unselected branches may divide by q = 0
         quad_lo = q * (1 + 2 * q) * fa0 + (1 - 4 * q * q) * fa1 - q * (1 - 2 * q) * fa2 + delta
         quad_hi = (fa0 / (q * (2 * q + 1)) + (2 * q - 1) / q * fb0 - (2 * q - 1) / (2 * q + 1) * fb1
                    + delta / (q * (2 * q + 1)))

@@ -20,6 +20,10 @@ LIB = PKG / "liblbm.so"
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Geometry and particle arithmetic must round exactly like the FP64 recipe
+# they implement (no fused multiply-add), so classification is reproducible.
+PER_FILE_FLAGS = {"dense.hip": []}
+DEFAULT_EXTRA = ["-ffp-contract=off"]
 
 
 def hipcc() -> str:
@@ -31,7 +35,7 @@ def hipcc() -> str:
 
 def _compile(src: Path, obj: Path) -> None:
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-c",
-           *DEVICE_FLAGS, "-Wall", "-Wno-unused-function",
+           *DEVICE_FLAGS, *PER_FILE_FLAGS.get(src.name, DEFAULT_EXTRA), "-Wall", "-Wno-unused-function",
            f"-I{INCLUDE}", f"-I{CSRC}", str(src), "-o", str(obj)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

@@ -2,8 +2,11 @@
 // carving, and the host-side sequencing of the kernels on the caller's
 // stream. No kernel arithmetic lives here.
 #include <math.h>
-#include <new>
 #include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -15,26 +18,112 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
+size_t n_nodes(const lbm_config& c) { return (size_t)c.nx * (size_t)c.ny * (size_t)c.nz; }
+
 size_t pop_bytes(const lbm_config& c) {
-  const size_t N = (size_t)c.nx * (size_t)c.ny * (size_t)c.nz;
   const size_t elem = c.store == LBM_STORE_F32 ? 4 : 2;
-  return align_up((size_t)kQ * N * elem);
+  return align_up((size_t)kQ * n_nodes(c) * elem);
+}
+
+bool has_particles(const lbm_config& c) { return c.bc != LBM_BC_NONE && c.max_particles > 0; }
+
+// Links of an isolated sphere of radius r centred at offset o from a node:
+// an upper bound for the links any one particle can own (neighbours only
+// remove links). Evaluated on a few sub-grid offsets.
+uint32_t link_capacity(double r) {
+  uint32_t best = 0;
+  const int R = (int)ceil(r) + 2;
+  const int cxv[18] = {1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+  const int cyv[18] = {0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+  const int czv[18] = {0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+  for (int t = 0; t < 27; ++t) {
+    const double o[3] = {0.5 * (t % 3) * 0.5 + 0.03, 0.5 * ((t / 3) % 3) * 0.5 + 0.07, 0.5 * (t / 9) * 0.5 + 0.11};
+    auto inside = [&](int x, int y, int z) {
+      const double dx = x - o[0], dy = y - o[1], dz = z - o[2];
+      return (dx * dx + dy * dy) + dz * dz < r * r;
+    };
+    uint32_t n = 0;
+    for (int z = -R; z <= R; ++z)
+      for (int y = -R; y <= R; ++y)
+        for (int x = -R; x <= R; ++x) {
+          if (inside(x, y, z)) continue;
+          for (int a = 0; a < 18; ++a)
+            if (inside(x + cxv[a], y + cyv[a], z + czv[a])) ++n;
+        }
+    best = std::max(best, n);
+  }
+  return (uint32_t)(best * 1.25) + 64;
+}
+
+bool pipe_solid(const lbm_config& c, int x, int y) {
+  const double dx = (double)x - c.pipe_cx, dy = (double)y - c.pipe_cy;
+  return dx * dx + dy * dy >= c.pipe_radius * c.pipe_radius;
+}
+
+// Links into the static pipe wall (exact count; the pipe is z-invariant).
+uint32_t wall_link_count(const lbm_config& c) {
+  if (c.wall != LBM_WALL_PIPE_Z) return 0;
+  const int cxv[18] = {1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+  const int cyv[18] = {0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+  uint64_t n = 0;
+  for (int y = 0; y < c.ny; ++y)
+    for (int x = 0; x < c.nx; ++x) {
+      if (pipe_solid(c, x, y)) continue;
+      for (int a = 0; a < 18; ++a) {
+        const int xs = ((x + cxv[a]) % c.nx + c.nx) % c.nx, ys = ((y + cyv[a]) % c.ny + c.ny) % c.ny;
+        if (pipe_solid(c, xs, ys)) ++n;
+      }
+    }
+  return (uint32_t)(n * (uint64_t)c.nz);
 }
 
 // Workspace plan: offsets of every slice for a configuration.
 struct Plan {
-  size_t f_a, f_b, err, total;
+  size_t f_a, f_b, err, scratch;
+  size_t pdoubles;       // particle FP64 block
+  size_t owner[2], solid_bits, wall_bits;
+  size_t link_node, link_q, link_meta, link_count;
+  size_t wl_node, wl_q, wl_meta;
+  uint32_t link_cap, wl_count;
+  size_t total;
 };
 
+constexpr int kParticleVecs = 21;  // [P][3] FP64 arrays in ParticleBufs (plus r, rho, U0)
+
 Plan plan(const lbm_config& c) {
-  Plan p;
+  Plan p{};
   size_t off = 0;
-  p.f_a = off;
-  off += pop_bytes(c);
-  p.f_b = off;
-  off += pop_bytes(c);
-  p.err = off;
-  off += kAlign;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t N = n_nodes(c);
+  const size_t words = mask_words((uint32_t)N);
+  p.f_a = take(pop_bytes(c));
+  p.f_b = take(pop_bytes(c));
+  p.err = take(kAlign);
+  p.scratch = take(64 * sizeof(double));
+  const size_t P = has_particles(c) ? (size_t)c.max_particles : 0;
+  p.pdoubles = take((size_t)(kParticleVecs * 3 + 2 + 3) * std::max<size_t>(P, 1) * sizeof(double));
+  p.wall_bits = take(words * 4);
+  p.solid_bits = take(words * 4);
+  if (c.bc != LBM_BC_NONE) {
+    p.owner[0] = take(N * 4);
+    p.owner[1] = take(N * 4);
+  }
+  if (c.bc == LBM_BC_IBB) {
+    p.link_cap = P ? link_capacity(c.max_radius) : 0;
+    const size_t L = P * p.link_cap;
+    p.link_node = take(L * 4 + 4);
+    p.link_q = take(L * 4 + 4);
+    p.link_meta = take(L + 4);
+    p.link_count = take(P * 4 + 4);
+    p.wl_count = wall_link_count(c);
+    p.wl_node = take((size_t)p.wl_count * 4 + 4);
+    p.wl_q = take((size_t)p.wl_count * 4 + 4);
+    p.wl_meta = take((size_t)p.wl_count + 4);
+  }
   p.total = off;
   return p;
 }
@@ -52,8 +141,21 @@ int check_config(const lbm_config* c) {
   for (int k = 0; k < 3; ++k)
     if (!isfinite(c->body_force[k])) return LBM_E_ARG;
   if (c->store != LBM_STORE_F32 && c->store != LBM_STORE_F16S) return LBM_E_ARG;
-  if (c->bc != LBM_BC_NONE) return LBM_E_ARG;  // particle treatments not in this build yet
-  if (c->wall != LBM_WALL_NONE) return LBM_E_ARG;
+  if (c->bc != LBM_BC_NONE && c->bc != LBM_BC_IBB) return LBM_E_ARG;
+  if (c->wall != LBM_WALL_NONE && c->wall != LBM_WALL_PIPE_Z) return LBM_E_ARG;
+  if (c->wall == LBM_WALL_PIPE_Z) {
+    if (c->bc == LBM_BC_NONE) return LBM_E_ARG;
+    if (!(c->pipe_radius > 1.0) || !isfinite(c->pipe_cx) || !isfinite(c->pipe_cy)) return LBM_E_ARG;
+  }
+  if (c->max_particles < 0 || c->max_particles > (1 << 24)) return LBM_E_ARG;
+  if (c->max_particles > 0) {
+    if (c->bc == LBM_BC_NONE) return LBM_E_ARG;
+    if (!(c->max_radius > 0.0) || 2.0 * c->max_radius + 8.0 > (double)std::min(c->nx, std::min(c->ny, c->nz)))
+      return LBM_E_ARG;
+  }
+  if (c->ibb_max_order != 1 && c->ibb_max_order != 2) return LBM_E_ARG;
+  if (c->ibm_iters < 0 || c->ibm_iters > 16) return LBM_E_ARG;
+  if (!(c->coll_restitution > 0.0 && c->coll_restitution <= 1.0) || !(c->coll_tc_steps > 0.0)) return LBM_E_ARG;
   return LBM_OK;
 }
 
@@ -71,6 +173,59 @@ int drain_errors(Ctx& c) {
     if (bits & kErrCapacity) return LBM_E_SIZE;
   }
   return LBM_OK;
+}
+
+// Force of the last collision for field extraction: none before the first
+// step, the body force afterwards.
+float3 extraction_force(const Ctx& c) { return c.step > 0 ? c.body_force : make_float3(0.0f, 0.0f, 0.0f); }
+
+size_t pvec_bytes(const Ctx& c) { return (size_t)std::max(c.np, 0) * 3 * sizeof(double); }
+
+hipError_t zero_particle_accumulators(Ctx& c) {
+  const size_t b = pvec_bytes(c);
+  if (!b) return hipSuccess;
+  double* v[] = {c.P.F_link, c.P.T_link, c.P.F_rc, c.P.T_rc, c.P.F_h, c.P.T_h, c.P.F_c,
+                 c.P.F_ib,   c.P.T_ib,   c.P.Iu,   c.P.IL,   c.P.Iu_new, c.P.IL_new};
+  for (double* p : v) {
+    hipError_t e = hipMemsetAsync(p, 0, b, c.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t step_ibb(Ctx& c) {
+  const int pc = c.pcur, pn = 1 - c.pcur;
+  hipError_t e = timed(c, LBM_K_IBB_LINKS, [&] { return launch_ibb_links(c, c.f_cur, c.P.X[pc], c.P.U[pc], c.P.Om[pc]); });
+  if (e != hipSuccess) return e;
+  e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
+  if (e != hipSuccess) return e;
+  if (c.np > 0) {
+    e = timed(c, LBM_K_PARTICLE, [&] { return launch_particle_update(c); });
+    if (e != hipSuccess) return e;
+    if (c.motion != LBM_MOTION_FIXED) {
+      const int on = 1 - c.ocur;
+      e = timed(c, LBM_K_GEOMETRY, [&] {
+        hipError_t r = launch_owner_clear(c, c.ibb.owner[on], c.P.Xown[on], c.np);
+        if (r == hipSuccess)
+          r = hipMemcpyAsync(c.ibb.solid_bits, c.ibb.wall_bits, mask_words(c.dims.N) * 4, hipMemcpyDeviceToDevice,
+                             c.stream);
+        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.ibb.solid_bits, c.P.X[pn]);
+        if (r == hipSuccess)
+          r = hipMemcpyAsync(c.P.Xown[on], c.P.X[pn], pvec_bytes(c), hipMemcpyDeviceToDevice, c.stream);
+        if (r == hipSuccess) r = launch_links_build(c, c.ibb.owner[on], c.P.X[pn]);
+        return r;
+      });
+      if (e != hipSuccess) return e;
+      e = timed(c, LBM_K_REFILL, [&] {
+        return launch_cover_refill(c, c.f_nxt, c.ibb.owner[c.ocur], c.ibb.owner[on], c.P.X[pc], c.P.X[pn],
+                                   c.P.U[pn], c.P.Om[pn]);
+      });
+      if (e != hipSuccess) return e;
+      c.ocur = on;
+    }
+    c.pcur = pn;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -135,11 +290,88 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
   c.f_cur = base + p.f_a;
   c.f_nxt = base + p.f_b;
   c.err = (uint32_t*)(base + p.err);
+  c.scratch_d = (double*)(base + p.scratch);
   c.step = 0;
+  c.np = 0;
+  c.motion = LBM_MOTION_FREE;
+  c.pcur = 0;
+  c.ocur = 0;
+  c.link_cap = p.link_cap;
+  {
+    const size_t P = std::max(has_particles(*cfg) ? (size_t)cfg->max_particles : (size_t)0, (size_t)1);
+    double* d = (double*)(base + p.pdoubles);
+    auto vec = [&]() {
+      double* r = d;
+      d += 3 * P;
+      return r;
+    };
+    ParticleBufs& B = c.P;
+    B.X[0] = vec(); B.X[1] = vec(); B.U[0] = vec(); B.U[1] = vec(); B.Om[0] = vec(); B.Om[1] = vec();
+    B.F_link = vec(); B.T_link = vec(); B.F_rc = vec(); B.T_rc = vec(); B.F_h = vec(); B.T_h = vec();
+    B.F_c = vec(); B.F_ib = vec(); B.T_ib = vec(); B.Iu = vec(); B.IL = vec(); B.Iu_new = vec();
+    B.IL_new = vec(); B.Xown[0] = vec(); B.Xown[1] = vec();
+    B.r = d;
+    d += P;
+    B.rho = d;
+  }
+  c.ibb = IbbBufs{};
+  c.ibb.wall_bits = (uint32_t*)(base + p.wall_bits);
+  c.ibb.solid_bits = (uint32_t*)(base + p.solid_bits);
+  if (cfg->bc != LBM_BC_NONE) {
+    c.ibb.owner[0] = (uint32_t*)(base + p.owner[0]);
+    c.ibb.owner[1] = (uint32_t*)(base + p.owner[1]);
+  }
+  if (cfg->bc == LBM_BC_IBB) {
+    c.ibb.link_node = (uint32_t*)(base + p.link_node);
+    c.ibb.link_q = (float*)(base + p.link_q);
+    c.ibb.link_meta = (uint8_t*)(base + p.link_meta);
+    c.ibb.link_count = (uint32_t*)(base + p.link_count);
+    c.ibb.wl_node = (uint32_t*)(base + p.wl_node);
+    c.ibb.wl_q = (float*)(base + p.wl_q);
+    c.ibb.wl_meta = (uint8_t*)(base + p.wl_meta);
+    c.ibb.wl_count = p.wl_count;
+  }
 
   // Start at rest, density 1: shifted populations are all zero.
   hipError_t e = hipMemsetAsync(c.f_cur, 0, pop_bytes(*cfg), c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(c.err, 0, sizeof(uint32_t), c.stream);
+  // Static wall mask.
+  const size_t words = mask_words(c.dims.N);
+  if (e == hipSuccess) {
+    std::vector<uint32_t> wall(words, 0u);
+    if (cfg->wall == LBM_WALL_PIPE_Z) {
+      for (int z = 0; z < cfg->nz; ++z)
+        for (int y = 0; y < cfg->ny; ++y)
+          for (int x = 0; x < cfg->nx; ++x)
+            if (pipe_solid(*cfg, x, y)) {
+              const size_t n = ((size_t)z * cfg->ny + y) * cfg->nx + x;
+              wall[n >> 5] |= 1u << (n & 31);
+            }
+    }
+    e = hipMemcpyAsync(c.ibb.wall_bits, wall.data(), words * 4, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c.ibb.solid_bits, wall.data(), words * 4, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  }
+  if (e == hipSuccess && cfg->bc != LBM_BC_NONE) {
+    e = launch_owner_fill(c, c.ibb.owner[0]);
+    if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[1]);
+  }
+  if (e == hipSuccess && cfg->bc == LBM_BC_IBB && c.ibb.wl_count) {
+    // Static wall links, filled once.
+    uint32_t* counter = (uint32_t*)c.scratch_d;
+    e = hipMemsetAsync(counter, 0, sizeof(uint32_t), c.stream);
+    if (e == hipSuccess) e = launch_wall_links(c, c.ibb.owner[0], counter, false);
+    uint32_t got = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&got, counter, sizeof(got), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e == hipSuccess && got != c.ibb.wl_count) e = hipErrorUnknown;
+  }
+  if (e == hipSuccess && has_particles(*cfg)) {
+    c.np = 0;
+    e = zero_particle_accumulators(c);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
   if (e != hipSuccess) {
     delete h;
     return LBM_E_HIP;
@@ -152,7 +384,9 @@ int lbm_set_fields_device(lbm_ctx* h, const float* u_dev, const float* rho_dev) 
   if (!h || !u_dev) return LBM_E_ARG;
   Ctx& c = h->c;
   c.step = 0;
-  return hip_status(launch_init_equilibrium(c, u_dev, rho_dev, c.f_cur));
+  hipError_t e = launch_init_equilibrium(c, u_dev, rho_dev, c.f_cur);
+  if (e == hipSuccess) e = zero_particle_accumulators(c);
+  return hip_status(e);
 }
 
 int lbm_set_fields(lbm_ctx* h, const float* u, const float* rho) {
@@ -172,11 +406,210 @@ int lbm_set_fields(lbm_ctx* h, const float* u, const float* rho) {
   return LBM_OK;
 }
 
+int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, const double* omega,
+                      const double* radius, const double* rho_p, int32_t mode, int32_t motion) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const lbm_config& cfg = c.cfg;
+  if (cfg.bc == LBM_BC_NONE || cfg.wall != LBM_WALL_NONE) return LBM_E_ARG;
+  if (np < 0 || np > cfg.max_particles) return LBM_E_SIZE;
+  if (np > 0 && (!x || !radius)) return LBM_E_ARG;
+  if (mode != LBM_SET_STATE && mode != LBM_RELEASE) return LBM_E_ARG;
+  if (motion != LBM_MOTION_FREE && motion != LBM_MOTION_FIXED && motion != LBM_MOTION_PRESCRIBED) return LBM_E_ARG;
+  const double L[3] = {(double)cfg.nx, (double)cfg.ny, (double)cfg.nz};
+  std::vector<double> X(3 * (size_t)np), U(3 * (size_t)np, 0.0), W(3 * (size_t)np, 0.0), R(np), RHO(np, 1.0);
+  for (int32_t i = 0; i < np; ++i) {
+    const double r = radius[i];
+    if (!(r > 0.0) || r > cfg.max_radius) return LBM_E_ARG;
+    R[i] = r;
+    if (rho_p) {
+      if (!(rho_p[i] > 0.0) || !isfinite(rho_p[i])) return LBM_E_ARG;
+      RHO[i] = rho_p[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+      double v = x[3 * i + k];
+      if (!isfinite(v)) return LBM_E_ARG;
+      v = fmod(v, L[k]);
+      if (v < 0.0) v += L[k];
+      if (v >= L[k]) v -= L[k];
+      X[3 * i + k] = v;
+      if (u) {
+        if (!isfinite(u[3 * i + k])) return LBM_E_ARG;
+        U[3 * i + k] = u[3 * i + k];
+      }
+      if (omega) {
+        if (!isfinite(omega[3 * i + k])) return LBM_E_ARG;
+        W[3 * i + k] = omega[3 * i + k];
+      }
+    }
+  }
+  c.np = np;
+  c.motion = motion;
+  c.pcur = 0;
+  const size_t vb = pvec_bytes(c);
+  hipError_t e = hipSuccess;
+  if (np > 0) {
+    e = hipMemcpyAsync(c.P.X[0], X.data(), vb, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.P.U[0], U.data(), vb, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.P.Om[0], W.data(), vb, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.P.r, R.data(), np * sizeof(double), hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.P.rho, RHO.data(), np * sizeof(double), hipMemcpyHostToDevice, c.stream);
+  }
+  if (e == hipSuccess) e = zero_particle_accumulators(c);
+  // Owner map of the new positions (lowest index wins), needed by release
+  // and by the bounce-back geometry.
+  c.ocur = 0;
+  if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[0]);
+  if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[1]);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c.ibb.solid_bits, c.ibb.wall_bits, mask_words(c.dims.N) * 4, hipMemcpyDeviceToDevice,
+                       c.stream);
+  if (e == hipSuccess) e = launch_owner_set(c, c.ibb.owner[0], c.ibb.solid_bits, c.P.X[0]);
+  if (e == hipSuccess && mode == LBM_RELEASE && np > 0) {
+    float* ufield = (float*)c.f_nxt;  // idle between steps
+    double* U0 = c.P.F_h;             // scratch until the first step
+    e = launch_fields(c, c.f_cur, extraction_force(c), ufield, nullptr);
+    if (e == hipSuccess) e = launch_release_average(c, ufield, U0);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.P.U[0], U0, vb, hipMemcpyDeviceToDevice, c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c.P.Om[0], 0, vb, c.stream);
+    if (e == hipSuccess) e = launch_release_overwrite(c, c.f_cur, c.ibb.owner[0], c.P.U[0]);
+    if (e == hipSuccess) e = hipMemsetAsync(c.P.F_h, 0, vb, c.stream);
+  }
+  // Both owner maps now hold (at most) the current spheres, so the box
+  // positions recorded for each must be valid centres before the first
+  // clear: clearing around the current centres in the other map is a no-op.
+  if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[0], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
+  if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[1], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
+  if (e == hipSuccess && cfg.bc == LBM_BC_IBB) e = launch_links_build(c, c.ibb.owner[0], c.P.X[0]);
+  if (e != hipSuccess) return LBM_E_HIP;
+  return drain_errors(c);
+}
+
+int lbm_get_particles(lbm_ctx* h, double* x, double* u, double* omega) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const size_t vb = pvec_bytes(c);
+  if (vb) {
+    if (x && hipMemcpyAsync(x, c.P.X[c.pcur], vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+    if (u && hipMemcpyAsync(u, c.P.U[c.pcur], vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+    if (omega && hipMemcpyAsync(omega, c.P.Om[c.pcur], vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+  }
+  return drain_errors(c);
+}
+
+int lbm_forces(lbm_ctx* h, double* F, double* T, double* F_contact) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const size_t vb = pvec_bytes(c);
+  if (vb) {
+    if (F && hipMemcpyAsync(F, c.P.F_h, vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+    if (T && hipMemcpyAsync(T, c.P.T_h, vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+    if (F_contact && hipMemcpyAsync(F_contact, c.P.F_c, vb, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+  }
+  return drain_errors(c);
+}
+
+int lbm_link_count(lbm_ctx* h, int64_t* n) {
+  if (!h || !n) return LBM_E_ARG;
+  Ctx& c = h->c;
+  *n = 0;
+  if (c.cfg.bc != LBM_BC_IBB) return drain_errors(c);
+  std::vector<uint32_t> cnt(std::max(c.np, 0));
+  if (c.np > 0 && hipMemcpyAsync(cnt.data(), c.ibb.link_count, c.np * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                 c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  const int st = drain_errors(c);
+  int64_t t = c.ibb.wl_count;
+  for (uint32_t v : cnt) t += v;
+  *n = t;
+  return st;
+}
+
+int lbm_get_links(lbm_ctx* h, int64_t cap, int32_t* node, int32_t* dir, int32_t* particle, float* q, int32_t* scheme,
+                  int64_t* n) {
+  if (!h || !n || cap < 0) return LBM_E_ARG;
+  Ctx& c = h->c;
+  *n = 0;
+  if (c.cfg.bc != LBM_BC_IBB) return drain_errors(c);
+  const size_t tot = (size_t)std::max(c.np, 0) * c.link_cap;
+  std::vector<uint32_t> cnt(std::max(c.np, 0)), nd(tot), wn(c.ibb.wl_count);
+  std::vector<float> qq(tot), wq(c.ibb.wl_count);
+  std::vector<uint8_t> mm(tot), wm(c.ibb.wl_count);
+  hipError_t e = hipSuccess;
+  if (c.np > 0) {
+    e = hipMemcpyAsync(cnt.data(), c.ibb.link_count, c.np * 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(nd.data(), c.ibb.link_node, tot * 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(qq.data(), c.ibb.link_q, tot * 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(mm.data(), c.ibb.link_meta, tot, hipMemcpyDeviceToHost, c.stream);
+  }
+  if (e == hipSuccess && c.ibb.wl_count) {
+    e = hipMemcpyAsync(wn.data(), c.ibb.wl_node, wn.size() * 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(wq.data(), c.ibb.wl_q, wq.size() * 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(wm.data(), c.ibb.wl_meta, wm.size(), hipMemcpyDeviceToHost, c.stream);
+  }
+  if (e != hipSuccess) return LBM_E_HIP;
+  const int st = drain_errors(c);
+  if (st != LBM_OK) return st;
+  int64_t k = 0;
+  auto emit = [&](uint32_t nn, float qv, uint8_t meta, int32_t p) {
+    if (k >= cap) return;
+    const int a = meta & 31;
+    const int x = (int)(nn % (uint32_t)c.cfg.nx), y = (int)((nn / (uint32_t)c.cfg.nx) % (uint32_t)c.cfg.ny),
+              z = (int)(nn / ((uint32_t)c.cfg.nx * (uint32_t)c.cfg.ny));
+    if (node) {
+      node[3 * k] = x;
+      node[3 * k + 1] = y;
+      node[3 * k + 2] = z;
+    }
+    if (dir) {
+      dir[3 * k] = cx_of(a);
+      dir[3 * k + 1] = cy_of(a);
+      dir[3 * k + 2] = cz_of(a);
+    }
+    if (particle) particle[k] = p;
+    if (q) q[k] = qv;
+    if (scheme) scheme[k] = meta >> 5;
+    ++k;
+  };
+  for (int32_t p = 0; p < c.np; ++p)
+    for (uint32_t j = 0; j < std::min(cnt[p], c.link_cap); ++j) {
+      const size_t o = (size_t)p * c.link_cap + j;
+      emit(nd[o], qq[o], mm[o], p);
+    }
+  for (uint32_t j = 0; j < c.ibb.wl_count; ++j) emit(wn[j], wq[j], wm[j], -1);
+  *n = k;
+  return LBM_OK;
+}
+
+int lbm_geometry_counts(lbm_ctx* h, int64_t* solid_nodes, int64_t* links) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (solid_nodes) {
+    std::vector<uint32_t> bits(mask_words(c.dims.N));
+    if (hipMemcpyAsync(bits.data(), c.ibb.solid_bits, bits.size() * 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+    const int st = drain_errors(c);
+    if (st != LBM_OK) return st;
+    int64_t s = 0;
+    if (c.cfg.bc == LBM_BC_IBB)
+      for (uint32_t w : bits) s += __builtin_popcount(w);
+    *solid_nodes = s;
+  }
+  if (links) return lbm_link_count(h, links);
+  return drain_errors(c);
+}
+
 int lbm_step(lbm_ctx* h, int32_t nsteps) {
   if (!h || nsteps < 0) return LBM_E_ARG;
   Ctx& c = h->c;
   for (int32_t s = 0; s < nsteps; ++s) {
-    hipError_t e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
+    hipError_t e;
+    if (c.cfg.bc == LBM_BC_IBB)
+      e = step_ibb(c);
+    else
+      e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
     if (e != hipSuccess) return LBM_E_HIP;
     void* t = c.f_cur;
     c.f_cur = c.f_nxt;
@@ -189,7 +622,7 @@ int lbm_step(lbm_ctx* h, int32_t nsteps) {
 int lbm_get_fields_device(lbm_ctx* h, float* u_dev, float* rho_dev) {
   if (!h) return LBM_E_ARG;
   Ctx& c = h->c;
-  return hip_status(launch_fields(c, c.f_cur, u_dev, rho_dev));
+  return hip_status(launch_fields(c, c.f_cur, extraction_force(c), u_dev, rho_dev));
 }
 
 int lbm_get_fields(lbm_ctx* h, float* u, float* rho) {

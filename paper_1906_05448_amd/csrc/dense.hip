@@ -38,14 +38,21 @@ __device__ __forceinline__ Tile tile_coords(const Dims& d) {
   return t;
 }
 
-template <int STORE>
+// MODE 0: every node. MODE 1: nodes flagged in the solid bitmask are
+// skipped (interpolated bounce-back: only fluid nodes are updated, and the
+// body force acts on fluid only).
+template <int STORE, int MODE>
 __global__ void __launch_bounds__(256)
 k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STORE>::T* __restrict__ B,
-                 Dims d, MrtRates r, float3 F, uint32_t* __restrict__ err) {
+                 Dims d, MrtRates r, float3 F, const uint32_t* __restrict__ solid, uint32_t* __restrict__ err) {
   using P = Pop<STORE>;
   const Tile t = tile_coords(d);
   if (!t.live) return;
   const int x = t.x, y = t.y, z = t.z;
+  if (MODE == 1) {
+    const uint32_t n0 = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
+    if ((solid[n0 >> 5] >> (n0 & 31u)) & 1u) return;
+  }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -131,22 +138,33 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
-  if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_stream_collide<0>, grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims, c.rates,
-                       c.body_force, c.err);
-  else
-    hipLaunchKernelGGL(k_stream_collide<1>, grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B, c.dims,
-                       c.rates, c.body_force, c.err);
+  const bool skip = c.cfg.bc == LBM_BC_IBB;
+  const uint32_t* solid = c.ibb.solid_bits;
+  if (c.cfg.store == LBM_STORE_F32) {
+    if (skip)
+      hipLaunchKernelGGL((k_stream_collide<0, 1>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
+                         c.rates, c.body_force, solid, c.err);
+    else
+      hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
+                         c.rates, c.body_force, solid, c.err);
+  } else {
+    if (skip)
+      hipLaunchKernelGGL((k_stream_collide<1, 1>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
+                         c.dims, c.rates, c.body_force, solid, c.err);
+    else
+      hipLaunchKernelGGL((k_stream_collide<1, 0>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
+                         c.dims, c.rates, c.body_force, solid, c.err);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_fields(const Ctx& c, const void* f, float* u, float* rho) {
+hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho) {
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_fields<0>, grid, block, 0, c.stream, (const float*)f, N, c.body_force, u, rho);
+    hipLaunchKernelGGL(k_fields<0>, grid, block, 0, c.stream, (const float*)f, N, F, u, rho);
   else
-    hipLaunchKernelGGL(k_fields<1>, grid, block, 0, c.stream, (const _Float16*)f, N, c.body_force, u, rho);
+    hipLaunchKernelGGL(k_fields<1>, grid, block, 0, c.stream, (const _Float16*)f, N, F, u, rho);
   return hipGetLastError();
 }
 

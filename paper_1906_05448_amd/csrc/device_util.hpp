@@ -1,0 +1,110 @@
+// device_util.hpp - small device helpers: periodic wrap, per-sphere boxes,
+// block-wide scans and FP64 reductions in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace lbm {
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Minimum image of an offset in (-L, L): one explicit branch per side, so
+// any implementation following the same recipe rounds identically.
+__device__ __forceinline__ double min_image(double d, double L) {
+  if (d > 0.5 * L) d -= L;
+  if (d < -0.5 * L) d += L;
+  return d;
+}
+
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Axis-aligned periodic box floor(X - reach) .. ceil(X + reach) around a point.
+struct Box {
+  int lo[3];
+  int side[3];
+  __device__ uint32_t count() const { return (uint32_t)side[0] * (uint32_t)side[1] * (uint32_t)side[2]; }
+};
+
+__device__ __forceinline__ Box make_box(const double* X, double reach) {
+  Box b;
+  for (int k = 0; k < 3; ++k) {
+    const int lo = (int)floor(X[k] - reach);
+    const int hi = (int)ceil(X[k] + reach);
+    b.lo[k] = lo;
+    b.side[k] = hi - lo + 1;
+  }
+  return b;
+}
+
+// i-th node of a box in raster order (x fastest), wrapped into the lattice.
+__device__ __forceinline__ void box_node(const Box& b, uint32_t i, int nx, int ny, int nz, int& x, int& y, int& z) {
+  const uint32_t sx = (uint32_t)b.side[0], sy = (uint32_t)b.side[1];
+  const int ix = (int)(i % sx);
+  const int iy = (int)((i / sx) % sy);
+  const int iz = (int)(i / (sx * sy));
+  x = wrapi(b.lo[0] + ix, nx);
+  y = wrapi(b.lo[1] + iy, ny);
+  z = wrapi(b.lo[2] + iz, nz);
+}
+
+__device__ __forceinline__ uint32_t node_index(int x, int y, int z, int nx, int ny) {
+  return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+}
+
+__device__ __forceinline__ void node_coords(uint32_t n, int nx, int ny, int& x, int& y, int& z) {
+  x = (int)(n % (uint32_t)nx);
+  const uint32_t r = n / (uint32_t)nx;
+  y = (int)(r % (uint32_t)ny);
+  z = (int)(r / (uint32_t)ny);
+}
+
+// Exclusive prefix sum over a block of BLOCK threads (multiple of 64).
+// Every thread must call it. Returns the thread's offset; *total gets the sum.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t base = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    const uint32_t s = wsum[w];
+    if (w < wid) base += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return base + incl - v;
+}
+
+// Sum of a double over the block in a fixed tree order (deterministic for a
+// given block size). Every thread must call it; all get the result.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double buf[BLOCK];
+  buf[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) buf[threadIdx.x] += buf[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = buf[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace lbm

@@ -1,0 +1,215 @@
+// geometry.hip - solid/fluid classification and boundary links for
+// interpolated bounce-back (Sec. 3.1, Sec. 2.1).
+//
+// Classification is exact FP64 with no contraction (this file is built with
+// -ffp-contract=off): node x is inside sphere p iff the minimum-image
+// squared distance ((dx*dx + dy*dy) + dz*dz) is below r_p^2. Overlaps go to
+// the lowest particle index (atomicMin on the owner map). The pipe wall is
+// solid where (x - cx)^2 + (y - cy)^2 >= R^2.
+//
+// Links are built per sphere by one workgroup that walks the sphere's box in
+// raster order; a block-wide prefix sum gives every link a deterministic
+// slot, so the link order (and every FP64 sum over links) is reproducible.
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ bool inside_sphere(int x, int y, int z, const double* X, double r, double Lx, double Ly,
+                                              double Lz) {
+  const double dx = min_image((double)x - X[0], Lx);
+  const double dy = min_image((double)y - X[1], Ly);
+  const double dz = min_image((double)z - X[2], Lz);
+  return dist2(dx, dy, dz) < r * r;
+}
+
+__global__ void __launch_bounds__(256) k_owner_fill(uint32_t* __restrict__ owner, const uint32_t* __restrict__ wall,
+                                                    uint32_t N) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= N) return;
+  owner[n] = ((wall[n >> 5] >> (n & 31u)) & 1u) ? kWall : kFluid;
+}
+
+// Resets the box of every particle at its old position to fluid.
+__global__ void __launch_bounds__(kBlock) k_owner_clear(uint32_t* __restrict__ owner, const double* __restrict__ Xold,
+                                                        const double* __restrict__ rad, Dims d) {
+  const int p = blockIdx.x;
+  const Box b = make_box(Xold + 3 * p, rad[p] + 1.0);
+  const uint32_t cnt = b.count();
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    int x, y, z;
+    box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    if (owner[n] != kWall) owner[n] = kFluid;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ owner, uint32_t* __restrict__ bits,
+                                                      const double* __restrict__ X, const double* __restrict__ rad,
+                                                      Dims d) {
+  const int p = blockIdx.x;
+  const double r = rad[p];
+  const Box b = make_box(X + 3 * p, r + 1.0);
+  const uint32_t cnt = b.count();
+  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    int x, y, z;
+    box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+    if (!inside_sphere(x, y, z, X + 3 * p, r, d.nx, d.ny, d.nz)) continue;
+    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    atomicMin(owner + n, (uint32_t)p);
+    if (bits) atomicOr(bits + (n >> 5), 1u << (n & 31u));
+  }
+}
+
+// q: smaller root t of |d + t c|^2 = r^2 for a fluid point heading into the
+// sphere, in the cancellation-free form.
+__device__ __forceinline__ double sphere_q(double dx, double dy, double dz, int cx, int cy, int cz, double r) {
+  const double a = (double)((cx * cx + cy * cy) + cz * cz);
+  const double b = (dx * cx + dy * cy) + dz * cz;
+  const double cc = dist2(dx, dy, dz) - r * r;
+  return cc / (-b + sqrt(b * b - a * cc));
+}
+
+// Fallback chain: quadratic needs x_f - c (and x_f - 2c when q < 1/2) fluid;
+// linear needs x_f - c fluid when q < 1/2; otherwise the single-node scheme.
+__device__ __forceinline__ uint32_t pick_scheme(double q, bool f1, bool f2, int max_order) {
+  const bool lo = q < 0.5;
+  const bool quad_ok = lo ? (f1 && f2) : f1;
+  const bool lin_ok = lo ? f1 : true;
+  if (max_order >= 2 && quad_ok) return kSchemeQuadratic;
+  return lin_ok ? kSchemeLinear : kSchemeHalfway;
+}
+
+__device__ __forceinline__ uint32_t neighbour(int x, int y, int z, int k, int i, const Dims& d) {
+  return node_index(wrapi(x + k * cx_of(i), d.nx), wrapi(y + k * cy_of(i), d.ny), wrapi(z + k * cz_of(i), d.nz),
+                    d.nx, d.ny);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, const double* __restrict__ rad, Dims d,
+              int max_order, uint32_t cap, uint32_t* __restrict__ link_node, float* __restrict__ link_q,
+              uint8_t* __restrict__ link_meta, uint32_t* __restrict__ link_count, uint32_t* __restrict__ err) {
+  const uint32_t p = blockIdx.x;
+  const double r = rad[p];
+  const double* Xp = X + 3 * p;
+  const Box b = make_box(Xp, r + 2.0);
+  const uint32_t cnt = b.count();
+  const size_t base = (size_t)p * cap;
+  uint32_t written = 0;
+  for (uint32_t i0 = 0; i0 < cnt; i0 += kBlock) {
+    const uint32_t i = i0 + threadIdx.x;
+    int x = 0, y = 0, z = 0;
+    uint32_t n = 0, mine = 0, hits = 0;
+    if (i < cnt) {
+      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+      n = node_index(x, y, z, d.nx, d.ny);
+      if (owner[n] == kFluid) {
+        for (int a = 1; a < kQ; ++a)
+          if (owner[neighbour(x, y, z, 1, a, d)] == p) hits |= 1u << a;
+        mine = __popc(hits);
+      }
+    }
+    uint32_t total;
+    uint32_t off = written + block_exclusive_scan<kBlock>(mine, &total);
+    if (mine) {
+      const double dx = min_image((double)x - Xp[0], d.nx);
+      const double dy = min_image((double)y - Xp[1], d.ny);
+      const double dz = min_image((double)z - Xp[2], d.nz);
+      for (int a = 1; a < kQ; ++a) {
+        if (!((hits >> a) & 1u)) continue;
+        const double q = sphere_q(dx, dy, dz, cx_of(a), cy_of(a), cz_of(a), r);
+        const bool f1 = owner[neighbour(x, y, z, -1, a, d)] == kFluid;
+        const bool f2 = owner[neighbour(x, y, z, -2, a, d)] == kFluid;
+        const uint32_t s = pick_scheme(q, f1, f2, max_order);
+        if (off < cap) {
+          link_node[base + off] = n;
+          link_q[base + off] = (float)q;
+          link_meta[base + off] = (uint8_t)(a | (s << 5));
+        }
+        ++off;
+      }
+    }
+    written += total;
+  }
+  if (threadIdx.x == 0) {
+    if (written > cap) {
+      atomicOr(err, kErrCapacity);
+      written = cap;
+    }
+    link_count[p] = written;
+  }
+}
+
+// Pipe wall: root t in [0, 1) of |dxy + t cxy|^2 = R^2 for a point inside
+// heading out.
+__device__ __forceinline__ double pipe_q(double dx, double dy, int cx, int cy, double R) {
+  const double a = (double)(cx * cx + cy * cy);
+  const double b = dx * cx + dy * cy;
+  const double cc = (dx * dx + dy * dy) - R * R;
+  const double disc = sqrt(b * b - a * cc);
+  return b >= 0.0 ? -cc / (b + disc) : (disc - b) / a;
+}
+
+__global__ void __launch_bounds__(256)
+k_wall_links(const uint32_t* __restrict__ owner, Dims d, double R, double pcx, double pcy, uint32_t* __restrict__ counter,
+             uint32_t cap, uint32_t* __restrict__ node_out, float* __restrict__ q_out, uint8_t* __restrict__ meta_out,
+             int count_only) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= d.N) return;
+  if (owner[n] != kFluid) return;
+  int x, y, z;
+  node_coords(n, d.nx, d.ny, x, y, z);
+  for (int a = 1; a < kQ; ++a) {
+    if (owner[neighbour(x, y, z, 1, a, d)] != kWall) continue;
+    const uint32_t slot = atomicAdd(counter, 1u);
+    if (count_only || slot >= cap) continue;
+    const double q = pipe_q((double)x - pcx, (double)y - pcy, cx_of(a), cy_of(a), R);
+    const bool f1 = owner[neighbour(x, y, z, -1, a, d)] == kFluid;
+    const uint32_t s = pick_scheme(q, f1, false, 1);
+    node_out[slot] = n;
+    q_out[slot] = (float)q;
+    meta_out[slot] = (uint8_t)(a | (s << 5));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_owner_fill(const Ctx& c, uint32_t* owner) {
+  const uint32_t N = c.dims.N;
+  hipLaunchKernelGGL(k_owner_fill, dim3((N + 255) / 256), dim3(256), 0, c.stream, owner, c.ibb.wall_bits, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold, int32_t np_old) {
+  if (np_old <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_owner_clear, dim3(np_old), dim3(kBlock), 0, c.stream, owner, Xold, c.P.r, c.dims);
+  return hipGetLastError();
+}
+
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, uint32_t* solid_bits, const double* X) {
+  if (c.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_owner_set, dim3(c.np), dim3(kBlock), 0, c.stream, owner, solid_bits, X, c.P.r, c.dims);
+  return hipGetLastError();
+}
+
+hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double* X) {
+  if (c.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_links_build, dim3(c.np), dim3(kBlock), 0, c.stream, owner, X, c.P.r, c.dims,
+                     c.cfg.ibb_max_order, c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta,
+                     c.ibb.link_count, c.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only) {
+  const uint32_t N = c.dims.N;
+  hipLaunchKernelGGL(k_wall_links, dim3((N + 255) / 256), dim3(256), 0, c.stream, owner, c.dims, c.cfg.pipe_radius,
+                     c.cfg.pipe_cx, c.cfg.pipe_cy, counter, c.ibb.wl_count, c.ibb.wl_node, c.ibb.wl_q,
+                     c.ibb.wl_meta, count_only ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

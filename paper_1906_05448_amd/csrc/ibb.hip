@@ -1,0 +1,341 @@
+// ibb.hip - interpolated bounce-back at boundary links, the link forces, and
+// the refilling of uncovered nodes (Sec. 3.1, Sec. 2.1).
+//
+// Ghost-slot design: for a link (x_f, a) the unknown population f_abar(x_f)
+// is pulled from slot (abar, x_s) of the source buffer, where x_s = x_f + c_a
+// is the solid node. That slot is read by no other node, so this kernel
+// writes the interpolated bounce-back value there before the dense kernel
+// runs, and the dense kernel stays a branch-free pull over fluid nodes.
+//
+// Interpolation (Bouzidi, Firdaouss & Lallemand 2001) with the moving-wall
+// term delta = -6 w_a (c_a . u_w); coefficients of every branch sum to one
+// and w_a = w_abar, so the shifted populations g = f - w enter directly:
+//   quadratic q < 1/2 : q(1+2q) g_a(x_f) + (1-4q^2) g_a(x_f-c) - q(1-2q) g_a(x_f-2c) + delta
+//   quadratic q >= 1/2: [g_a(x_f) + delta]/(q(2q+1)) + (2q-1)/q g_abar(x_f)
+//                       - (2q-1)/(2q+1) g_abar(x_f-c)
+//   linear q < 1/2    : 2q g_a(x_f) + (1-2q) g_a(x_f-c) + delta
+//   linear q >= 1/2   : [g_a(x_f) + delta]/(2q) + (2q-1)/(2q) g_abar(x_f)
+//   single node       : g_a(x_f) + delta   (halfway bounce-back)
+// Link force (Wen et al. 2014, Galilean invariant momentum exchange):
+//   F = (c_a - u_w) f~_a(x_f) - (c_abar - u_w) f_abar(x_f, t+1), torque (x_w - X) x F.
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int STORE>
+__device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint32_t N, uint32_t n) {
+  return Pop<STORE>::load(f + (size_t)i * N + n);
+}
+
+// Interpolated value of the entering population for one link.
+template <int STORE>
+__device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, uint32_t N, uint32_t nf, uint32_t nm1,
+                                              uint32_t nm2, int a, uint32_t scheme, float q, float delta) {
+  const int ab = opp_of(a);
+  const float ga0 = ld<STORE>(A, a, N, nf);
+  if (scheme == kSchemeQuadratic) {
+    if (q < 0.5f) {
+      const float ga1 = ld<STORE>(A, a, N, nm1), ga2 = ld<STORE>(A, a, N, nm2);
+      return q * (1.0f + 2.0f * q) * ga0 + (1.0f - 4.0f * q * q) * ga1 - q * (1.0f - 2.0f * q) * ga2 + delta;
+    }
+    const float gb0 = ld<STORE>(A, ab, N, nf), gb1 = ld<STORE>(A, ab, N, nm1);
+    const float t = 2.0f * q - 1.0f;
+    return (ga0 + delta) / (q * (2.0f * q + 1.0f)) + t / q * gb0 - t / (2.0f * q + 1.0f) * gb1;
+  }
+  if (scheme == kSchemeLinear) {
+    if (q < 0.5f) {
+      const float ga1 = ld<STORE>(A, a, N, nm1);
+      return 2.0f * q * ga0 + (1.0f - 2.0f * q) * ga1 + delta;
+    }
+    const float gb0 = ld<STORE>(A, ab, N, nf);
+    return (ga0 + delta) / (2.0f * q) + (2.0f * q - 1.0f) / (2.0f * q) * gb0;
+  }
+  return ga0 + delta;
+}
+
+// One workgroup per sphere: fill the ghost slots of its links and reduce the
+// link forces and torques in FP64 in a fixed order.
+template <int STORE>
+__global__ void __launch_bounds__(kBlock)
+k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, const double* __restrict__ U,
+            const double* __restrict__ Om, uint32_t cap, const uint32_t* __restrict__ link_node,
+            const float* __restrict__ link_q, const uint8_t* __restrict__ link_meta,
+            const uint32_t* __restrict__ link_count, double* __restrict__ F_out, double* __restrict__ T_out) {
+  const int p = blockIdx.x;
+  const uint32_t cnt = link_count[p];
+  const size_t base = (size_t)p * cap;
+  const double Xp[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
+  const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
+  const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
+    const uint32_t nf = link_node[base + k];
+    const float q = link_q[base + k];
+    const uint32_t meta = link_meta[base + k];
+    const int a = (int)(meta & 31u);
+    const uint32_t scheme = meta >> 5;
+    int x, y, z;
+    node_coords(nf, d.nx, d.ny, x, y, z);
+    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
+    // lever arm x_w - X and wall velocity U + Omega x arm
+    const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q * cx,
+                           min_image((double)y - Xp[1], d.ny) + (double)q * cy,
+                           min_image((double)z - Xp[2], d.nz) + (double)q * cz};
+    const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
+                          Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
+    const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
+    const uint32_t nm1 = node_index(wrapi(x - cx, d.nx), wrapi(y - cy, d.ny), wrapi(z - cz, d.nz), d.nx, d.ny);
+    const uint32_t nm2 =
+        node_index(wrapi(x - 2 * cx, d.nx), wrapi(y - 2 * cy, d.ny), wrapi(z - 2 * cz, d.nz), d.nx, d.ny);
+    const uint32_t ns = node_index(wrapi(x + cx, d.nx), wrapi(y + cy, d.ny), wrapi(z + cz, d.nz), d.nx, d.ny);
+    const float gnew = bounce_value<STORE>(A, d.N, nf, nm1, nm2, a, scheme, q, delta);
+    Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
+    const double fa = (double)ld<STORE>(A, a, d.N, nf) + (double)w_of(a);
+    const double fb = (double)gnew + (double)w_of(a);
+    const double c[3] = {(double)cx, (double)cy, (double)cz};
+    double Fl[3];
+    for (int k3 = 0; k3 < 3; ++k3) Fl[k3] = (c[k3] - uw[k3]) * fa + (c[k3] + uw[k3]) * fb;
+    F[0] += Fl[0];
+    F[1] += Fl[1];
+    F[2] += Fl[2];
+    T[0] += arm[1] * Fl[2] - arm[2] * Fl[1];
+    T[1] += arm[2] * Fl[0] - arm[0] * Fl[2];
+    T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
+  }
+  for (int k3 = 0; k3 < 3; ++k3) {
+    const double fs = block_sum<kBlock>(F[k3]);
+    const double ts = block_sum<kBlock>(T[k3]);
+    if (threadIdx.x == 0) {
+      F_out[3 * p + k3] = fs;
+      T_out[3 * p + k3] = ts;
+    }
+  }
+}
+
+// Static wall links (pipe): zero wall velocity, no force needed.
+template <int STORE>
+__global__ void __launch_bounds__(256)
+k_wall_bounce(typename Pop<STORE>::T* A, Dims d, uint32_t count, const uint32_t* __restrict__ node,
+              const float* __restrict__ qv, const uint8_t* __restrict__ meta_v) {
+  const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t nf = node[k];
+  const float q = qv[k];
+  const uint32_t meta = meta_v[k];
+  const int a = (int)(meta & 31u);
+  int x, y, z;
+  node_coords(nf, d.nx, d.ny, x, y, z);
+  const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
+  const uint32_t nm1 = node_index(wrapi(x - cx, d.nx), wrapi(y - cy, d.ny), wrapi(z - cz, d.nz), d.nx, d.ny);
+  const uint32_t ns = node_index(wrapi(x + cx, d.nx), wrapi(y + cy, d.ny), wrapi(z + cz, d.nz), d.nx, d.ny);
+  const float gnew = bounce_value<STORE>(A, d.N, nf, nm1, nm1, a, meta >> 5, q, 0.0f);
+  Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
+}
+
+__device__ __forceinline__ bool valid_node(const uint32_t* o_old, const uint32_t* o_new, uint32_t n) {
+  return o_old[n] == kFluid && o_new[n] == kFluid;
+}
+
+// Refill of one uncovered node: extrapolation along the lattice direction
+// closest to the outward normal, then the equilibrium part swapped for the
+// wall velocity. Writes g into B and returns the node's momentum.
+template <int STORE>
+__device__ void refill_node(typename Pop<STORE>::T* B, const Dims& d, const uint32_t* o_old, const uint32_t* o_new,
+                            int x, int y, int z, const double dd[3], const double uwd[3], double mom[3]) {
+  // direction maximising c . d; ties to the lexicographically largest c
+  int best = 1;
+  double bv = -1e300;
+  for (int k = 1; k < kQ; ++k) {
+    const double v = (cx_of(k) * dd[0] + cy_of(k) * dd[1]) + cz_of(k) * dd[2];
+    bool take = v > bv;
+    if (v == bv) {
+      const int b0 = cx_of(best), b1 = cy_of(best), b2 = cz_of(best);
+      const int k0 = cx_of(k), k1 = cy_of(k), k2 = cz_of(k);
+      take = (k0 > b0) || (k0 == b0 && (k1 > b1 || (k1 == b1 && k2 > b2)));
+    }
+    if (take) {
+      bv = v;
+      best = k;
+    }
+  }
+  const int cx = cx_of(best), cy = cy_of(best), cz = cz_of(best);
+  uint32_t nb[3];
+  bool ok[3];
+  for (int s = 0; s < 3; ++s) {
+    nb[s] = node_index(wrapi(x + (s + 1) * cx, d.nx), wrapi(y + (s + 1) * cy, d.ny), wrapi(z + (s + 1) * cz, d.nz),
+                       d.nx, d.ny);
+    ok[s] = valid_node(o_old, o_new, nb[s]);
+  }
+  float ge[kQ];
+  if (ok[0] && ok[1] && ok[2]) {
+    for (int i = 0; i < kQ; ++i)
+      ge[i] = 3.0f * ld<STORE>(B, i, d.N, nb[0]) - 3.0f * ld<STORE>(B, i, d.N, nb[1]) + ld<STORE>(B, i, d.N, nb[2]);
+  } else if (ok[0] && ok[1]) {
+    for (int i = 0; i < kQ; ++i) ge[i] = 2.0f * ld<STORE>(B, i, d.N, nb[0]) - ld<STORE>(B, i, d.N, nb[1]);
+  } else {
+    // equilibrium of the mean density and mean raw velocity of the valid
+    // nearest neighbours, or of (1, u_w) if there are none
+    float rs = 0.0f, us[3] = {0.0f, 0.0f, 0.0f};
+    int cnt = 0;
+    for (int k = 1; k < kQ; ++k) {
+      const uint32_t m = node_index(wrapi(x + cx_of(k), d.nx), wrapi(y + cy_of(k), d.ny), wrapi(z + cz_of(k), d.nz),
+                                    d.nx, d.ny);
+      if (!valid_node(o_old, o_new, m)) continue;
+      float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+      for (int i = 0; i < kQ; ++i) {
+        const float g = ld<STORE>(B, i, d.N, m);
+        dr += g;
+        jx += cx_of(i) * g;
+        jy += cy_of(i) * g;
+        jz += cz_of(i) * g;
+      }
+      const float rho = 1.0f + dr;
+      rs += rho;
+      us[0] += jx / rho;
+      us[1] += jy / rho;
+      us[2] += jz / rho;
+      ++cnt;
+    }
+    float rho = 1.0f, ux = (float)uwd[0], uy = (float)uwd[1], uz = (float)uwd[2];
+    if (cnt) {
+      rho = rs / cnt;
+      ux = us[0] / cnt;
+      uy = us[1] / cnt;
+      uz = us[2] / cnt;
+    }
+    for (int i = 0; i < kQ; ++i) ge[i] = geq(i, rho, ux, uy, uz);
+  }
+  float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+  for (int i = 0; i < kQ; ++i) {
+    dr += ge[i];
+    jx += cx_of(i) * ge[i];
+    jy += cy_of(i) * ge[i];
+    jz += cz_of(i) * ge[i];
+  }
+  const float rho_e = 1.0f + dr;
+  const float ux = jx / rho_e, uy = jy / rho_e, uz = jz / rho_e;
+  const float wx = (float)uwd[0], wy = (float)uwd[1], wz = (float)uwd[2];
+  mom[0] = mom[1] = mom[2] = 0.0;
+  for (int i = 0; i < kQ; ++i) {
+    const float g = ge[i] - geq(i, rho_e, ux, uy, uz) + geq(i, rho_e, wx, wy, wz);
+    Pop<STORE>::store(B + (size_t)i * d.N + node_index(x, y, z, d.nx, d.ny), g);
+    const double gd = (double)g;
+    mom[0] += cx_of(i) * gd;
+    mom[1] += cy_of(i) * gd;
+    mom[2] += cz_of(i) * gd;
+  }
+}
+
+// One workgroup per sphere: refill the nodes it uncovered and collect the
+// momentum of the nodes it covered, both into F_rc/T_rc for the next step.
+template <int STORE>
+__global__ void __launch_bounds__(kBlock)
+k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o_old,
+               const uint32_t* __restrict__ o_new, const double* __restrict__ Xold, const double* __restrict__ Xnew,
+               const double* __restrict__ Unew, const double* __restrict__ Omnew, const double* __restrict__ rad,
+               double* __restrict__ F_rc, double* __restrict__ T_rc) {
+  const uint32_t p = blockIdx.x;
+  const double r = rad[p];
+  const double* Xn = Xnew + 3 * p;
+  const double Up[3] = {Unew[3 * p], Unew[3 * p + 1], Unew[3 * p + 2]};
+  const double Wp[3] = {Omnew[3 * p], Omnew[3 * p + 1], Omnew[3 * p + 2]};
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  // uncovered: solid for p before, fluid now
+  {
+    const Box b = make_box(Xold + 3 * p, r + 1.0);
+    const uint32_t cnt = b.count();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+      int x, y, z;
+      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+      const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+      if (o_old[n] != p || o_new[n] != kFluid) continue;
+      const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
+                            min_image((double)z - Xn[2], d.nz)};
+      const double uw[3] = {Up[0] + (Wp[1] * dd[2] - Wp[2] * dd[1]), Up[1] + (Wp[2] * dd[0] - Wp[0] * dd[2]),
+                            Up[2] + (Wp[0] * dd[1] - Wp[1] * dd[0])};
+      double mom[3];
+      refill_node<STORE>(B, d, o_old, o_new, x, y, z, dd, uw, mom);
+      for (int k = 0; k < 3; ++k) F[k] -= mom[k];
+      T[0] -= dd[1] * mom[2] - dd[2] * mom[1];
+      T[1] -= dd[2] * mom[0] - dd[0] * mom[2];
+      T[2] -= dd[0] * mom[1] - dd[1] * mom[0];
+    }
+  }
+  // covered: fluid before, solid for p now
+  {
+    const Box b = make_box(Xn, r + 1.0);
+    const uint32_t cnt = b.count();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+      int x, y, z;
+      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+      const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+      if (o_new[n] != p || o_old[n] != kFluid) continue;
+      double mom[3] = {0, 0, 0};
+      for (int k = 0; k < kQ; ++k) {
+        const double g = (double)ld<STORE>(B, k, d.N, n);
+        mom[0] += cx_of(k) * g;
+        mom[1] += cy_of(k) * g;
+        mom[2] += cz_of(k) * g;
+      }
+      const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
+                            min_image((double)z - Xn[2], d.nz)};
+      for (int k = 0; k < 3; ++k) F[k] += mom[k];
+      T[0] += dd[1] * mom[2] - dd[2] * mom[1];
+      T[1] += dd[2] * mom[0] - dd[0] * mom[2];
+      T[2] += dd[0] * mom[1] - dd[1] * mom[0];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double fs = block_sum<kBlock>(F[k]);
+    const double ts = block_sum<kBlock>(T[k]);
+    if (threadIdx.x == 0) {
+      F_rc[3 * p + k] = fs;
+      T_rc[3 * p + k] = ts;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double* U, const double* Om) {
+  if (c.ibb.wl_count) {
+    const dim3 g((c.ibb.wl_count + 255) / 256);
+    if (c.cfg.store == LBM_STORE_F32)
+      hipLaunchKernelGGL(k_wall_bounce<0>, g, dim3(256), 0, c.stream, (float*)A, c.dims, c.ibb.wl_count,
+                         c.ibb.wl_node, c.ibb.wl_q, c.ibb.wl_meta);
+    else
+      hipLaunchKernelGGL(k_wall_bounce<1>, g, dim3(256), 0, c.stream, (_Float16*)A, c.dims, c.ibb.wl_count,
+                         c.ibb.wl_node, c.ibb.wl_q, c.ibb.wl_meta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (c.np <= 0) return hipSuccess;
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_ibb_links<0>, dim3(c.np), dim3(kBlock), 0, c.stream, (float*)A, c.dims, X, U, Om,
+                       c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
+                       c.P.T_link);
+  else
+    hipLaunchKernelGGL(k_ibb_links<1>, dim3(c.np), dim3(kBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
+                       c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
+                       c.P.T_link);
+  return hipGetLastError();
+}
+
+hipError_t launch_cover_refill(const Ctx& c, void* B, const uint32_t* owner_old, const uint32_t* owner_new,
+                               const double* Xold, const double* Xnew, const double* Unew, const double* Omnew) {
+  if (c.np <= 0) return hipSuccess;
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_cover_refill<0>, dim3(c.np), dim3(kBlock), 0, c.stream, (float*)B, c.dims, owner_old,
+                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc);
+  else
+    hipLaunchKernelGGL(k_cover_refill<1>, dim3(c.np), dim3(kBlock), 0, c.stream, (_Float16*)B, c.dims, owner_old,
+                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

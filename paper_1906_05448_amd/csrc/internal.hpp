@@ -15,6 +15,13 @@ namespace lbm {
 // Error bits latched on the device and reported by the next sync call.
 enum : uint32_t { kErrUnstable = 1u, kErrOverlap = 2u, kErrCapacity = 4u };
 
+// Owner map codes: a particle index, or one of these.
+constexpr uint32_t kFluid = 0xFFFFFFFFu;
+constexpr uint32_t kWall = 0xFFFFFFFEu;
+
+// Link metadata byte: direction (bits 0..4), scheme (bits 5..6).
+enum : uint32_t { kSchemeHalfway = 0, kSchemeLinear = 1, kSchemeQuadratic = 2 };
+
 // Lattice extent plus the launch geometry of the dense kernels. Blocks are
 // 64 x 4 threads (one wavefront per 64-node x-run); the flat block id is
 // remapped so that consecutive tiles land on the same XCD (the hardware deals
@@ -39,6 +46,9 @@ inline Dims make_dims(int nx, int ny, int nz) {
   d.per_xcd = (d.ntiles + 7) / 8;
   return d;
 }
+
+// Bitmask words covering N nodes.
+inline uint32_t mask_words(uint32_t N) { return (N + 31u) / 32u; }
 
 // Optional per-kernel timing with HIP events on the context's stream.
 struct Profiler {
@@ -84,6 +94,45 @@ struct Profiler {
   }
 };
 
+// FP64 particle state and per-particle accumulators, each [P][3] unless
+// noted. X/U/Om are double-buffered: [cur] holds step n, [1-cur] receives n+1.
+struct ParticleBufs {
+  double* X[2];
+  double* U[2];
+  double* Om[2];
+  double* r;       // [P]
+  double* rho;     // [P]
+  double* F_link;  // interpolated bounce-back: link forces of this step
+  double* T_link;
+  double* F_rc;    // momentum of covered/uncovered nodes, for the next step
+  double* T_rc;
+  double* F_h;     // hydrodynamic force/torque that entered the last update
+  double* T_h;
+  double* F_c;     // contact force of the last update
+  double* F_ib;    // immersed boundary: -sum F_l dV of this step
+  double* T_ib;
+  double* Iu;      // Kempe inner momentum sum alpha u, previous and new
+  double* IL;
+  double* Iu_new;
+  double* IL_new;
+  double* Xown[2]; // positions owner map [b] was last built for
+};
+
+// Interpolated bounce-back geometry.
+struct IbbBufs {
+  uint32_t* owner[2];    // [N] owner codes, [cur] at step n
+  uint32_t* solid_bits;  // [mask_words] solid nodes of step n (dense kernel)
+  uint32_t* wall_bits;   // [mask_words] static wall
+  uint32_t* link_node;   // [P * link_cap] fluid node of each link
+  float* link_q;         // wall fraction q
+  uint8_t* link_meta;    // direction | scheme << 5
+  uint32_t* link_count;  // [P]
+  uint32_t* wl_node;     // static wall links
+  float* wl_q;
+  uint8_t* wl_meta;
+  uint32_t wl_count;
+};
+
 struct Ctx {
   lbm_config cfg;
   hipStream_t stream;
@@ -95,8 +144,18 @@ struct Ctx {
   void* f_cur;      // post-collision shifted populations, [19][N]
   void* f_nxt;
   uint32_t* err;    // latched error bits (one word)
+  double* scratch_d;  // small FP64 scratch for reductions
   int64_t step;
   Profiler prof;
+  // Particles.
+  int32_t np;            // particles set
+  int32_t motion;        // LBM_MOTION_*
+  int pcur;              // which X/U/Om buffer is current
+  int ocur;              // which owner map is current
+  uint32_t link_cap;     // links reserved per particle
+  ParticleBufs P;
+  IbbBufs ibb;
+  double max_radius_set; // largest radius of the particles set
 };
 
 // Runs a launcher, bracketed by timing events when profiling is on.
@@ -117,7 +176,26 @@ hipError_t timed(Ctx& c, int cls, F&& launch) {
 // Dense kernels (dense.hip).
 hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rho, void* f);
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B);
-hipError_t launch_fields(const Ctx& c, const void* f, float* u, float* rho);
+// u, rho from post-collision populations; F is the force of the collision
+// that produced them (zero before the first step).
+hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho);
+
+// Geometry (geometry.hip).
+hipError_t launch_owner_fill(const Ctx& c, uint32_t* owner);
+hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold, int32_t np_old);
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, uint32_t* solid_bits, const double* X);
+hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double* X);
+hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only);
+
+// Interpolated bounce-back (ibb.hip).
+hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double* U, const double* Om);
+hipError_t launch_cover_refill(const Ctx& c, void* B, const uint32_t* owner_old, const uint32_t* owner_new,
+                               const double* Xold, const double* Xnew, const double* Unew, const double* Omnew);
+
+// Particles (particles.hip).
+hipError_t launch_particle_update(const Ctx& c);
+hipError_t launch_release_average(const Ctx& c, const float* u, double* Uout);
+hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U);
 
 }  // namespace lbm
 

@@ -17,6 +17,8 @@ _lib = None
 BC_NONE, BC_IBB, BC_IBM = 0, 1, 2
 STORE_F32, STORE_F16S = 0, 1
 WALL_NONE, WALL_PIPE_Z = 0, 1
+SET_STATE, RELEASE = 0, 1
+MOTION_FREE, MOTION_FIXED, MOTION_PRESCRIBED = 0, 1, 2
 KERNEL_CLASSES = ("stream_collide", "geometry", "ibb_links", "refill", "ibm_prepass", "ibm_forcing",
                   "particle", "stats", "corrector")
 NPROF = len(KERNEL_CLASSES)
@@ -67,6 +69,12 @@ def lib() -> ctypes.CDLL:
         "lbm_get_fields_device": (ctypes.c_int, [P, P, P]),
         "lbm_sync": (ctypes.c_int, [P]),
         "lbm_step_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        "lbm_set_particles": (ctypes.c_int, [P, I32, P, P, P, P, P, I32, I32]),
+        "lbm_get_particles": (ctypes.c_int, [P, P, P, P]),
+        "lbm_forces": (ctypes.c_int, [P, P, P, P]),
+        "lbm_link_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
+        "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_profile_enable": (ctypes.c_int, [P, I32]),
         "lbm_profile_read": (ctypes.c_int, [P, P, P]),
         "lbm_destroy": (None, [P]),
@@ -194,6 +202,60 @@ class Lattice:
         _check(lib().lbm_get_fields_device(self._h, ctypes.c_void_p(u.data_ptr()) if u is not None else None,
                                            None if rho is None else ctypes.c_void_p(rho.data_ptr())),
                "lbm_get_fields_device")
+
+    # -- particles --------------------------------------------------------
+    def set_particles(self, x, radius, u=None, omega=None, rho_p=None, mode=SET_STATE,
+                      motion=MOTION_FREE) -> None:
+        x = np.ascontiguousarray(np.atleast_2d(np.asarray(x, np.float64)))
+        n = x.shape[0]
+        rad = np.ascontiguousarray(np.broadcast_to(np.asarray(radius, np.float64), (n,)))
+
+        def opt(a, shape):
+            return None if a is None else np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shape))
+
+        uu, ww, rr = opt(u, (n, 3)), opt(omega, (n, 3)), opt(rho_p, (n,))
+        self._particles_keep = (x, rad, uu, ww, rr)
+        _check(lib().lbm_set_particles(self._h, n, _host_ptr(x), None if uu is None else _host_ptr(uu),
+                                       None if ww is None else _host_ptr(ww), _host_ptr(rad),
+                                       None if rr is None else _host_ptr(rr), int(mode), int(motion)),
+               "lbm_set_particles")
+        self.n_particles = n
+
+    def get_particles(self):
+        n = getattr(self, "n_particles", 0)
+        X, U, W = (np.zeros((n, 3)) for _ in range(3))
+        _check(lib().lbm_get_particles(self._h, _host_ptr(X), _host_ptr(U), _host_ptr(W)), "lbm_get_particles")
+        return X, U, W
+
+    def forces(self):
+        """(hydrodynamic force, torque, contact force), each (np, 3)."""
+        n = getattr(self, "n_particles", 0)
+        F, T, Fc = (np.zeros((n, 3)) for _ in range(3))
+        _check(lib().lbm_forces(self._h, _host_ptr(F), _host_ptr(T), _host_ptr(Fc)), "lbm_forces")
+        return F, T, Fc
+
+    def links(self):
+        """Boundary links: dict of node (L, 3) xyz, dir (L, 3), particle (L,),
+        q (L,) float32, scheme (L,)."""
+        n = ctypes.c_int64()
+        _check(lib().lbm_link_count(self._h, ctypes.byref(n)), "lbm_link_count")
+        cap = n.value
+        node = np.zeros((cap, 3), np.int32)
+        d = np.zeros((cap, 3), np.int32)
+        p = np.zeros(cap, np.int32)
+        q = np.zeros(cap, np.float32)
+        s = np.zeros(cap, np.int32)
+        got = ctypes.c_int64()
+        _check(lib().lbm_get_links(self._h, cap, _host_ptr(node), _host_ptr(d), _host_ptr(p), _host_ptr(q),
+                                   _host_ptr(s), ctypes.byref(got)), "lbm_get_links")
+        k = got.value
+        return {"node": node[:k], "dir": d[:k], "particle": p[:k], "q": q[:k], "scheme": s[:k]}
+
+    def geometry_counts(self):
+        """(solid nodes, boundary links) of the current geometry."""
+        s, l = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lbm_geometry_counts(self._h, ctypes.byref(s), ctypes.byref(l)), "lbm_geometry_counts")
+        return s.value, l.value
 
     # -- time stepping -------------------------------------------------
     def step(self, n: int = 1) -> None:

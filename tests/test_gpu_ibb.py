@@ -1,0 +1,158 @@
+"""Parity of the HIP interpolated-bounce-back path with the FP64 oracle,
+through the C ABI: link geometry bit-exact, fields and particle state
+within the FP32 / FP16 tolerances."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import C as OC
+from oracle.sim import RELEASE, SET_STATE, Config as OConfig, Sim as OSim
+from tests.helpers import gpu_config, gpu_lattice, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+MOTION = {"free": 0, "fixed": 1, "prescribed": 2}
+
+
+def _pair(shape, tau=0.6, F=(0, 0, 0), store=0, max_order=2, max_np=8, max_r=6.0, **kw):
+    o = OSim(OConfig(shape=shape, tau=tau, body_force=tuple(F), bc="ibb", ibb_max_order=max_order, **kw))
+    g = gpu_lattice(gpu_config(nx=shape[0], ny=shape[1], nz=shape[2], tau=tau, body_force=tuple(F), bc=1,
+                               ibb_max_order=max_order, store=store, max_particles=max_np, max_radius=max_r,
+                               **{k: v for k, v in kw.items() if k in ("coll_restitution", "coll_tc_steps")}))
+    return o, g
+
+
+def _oracle_links_sorted(o):
+    L = o.state.links
+    rows = []
+    for (x, y, z), a, p, q, s in zip(L["xf"], L["a"], L["p"], L["q"], L["scheme"]):
+        rows.append((int(p), int(x), int(y), int(z), tuple(int(v) for v in OC[a]), np.float32(q), int(s)))
+    return sorted(rows, key=lambda r: r[:5])
+
+
+def _gpu_links_sorted(g):
+    L = g.links()
+    rows = [(int(p), int(n[0]), int(n[1]), int(n[2]), tuple(int(v) for v in d), np.float32(q), int(s))
+            for n, d, p, q, s in zip(L["node"], L["dir"], L["particle"], L["q"], L["scheme"])]
+    return sorted(rows, key=lambda r: r[:5])
+
+
+def test_links_bit_exact_overlapping_and_wrapping_spheres():
+    shape = (40, 36, 38)
+    X = np.array([[0.37, 17.61, 37.52], [20.2, 18.1, 19.3], [27.9, 18.6, 20.1], [10.5, 33.9, 3.3],
+                  [30.01, 5.02, 12.77]])
+    r = np.array([5.7, 4.6, 5.2, 3.9, 4.75])
+    o, g = _pair(shape, max_r=6.0)
+    o.set_particles(X, r=r)
+    g.set_particles(X, r)
+    lo, lg = _oracle_links_sorted(o), _gpu_links_sorted(g)
+    assert len(lo) == len(lg) > 1000
+    assert [t[:5] for t in lo] == [t[:5] for t in lg]
+    assert [t[6] for t in lo] == [t[6] for t in lg]          # fallback scheme
+    assert all(a[5] == b[5] for a, b in zip(lo, lg))         # q, FP64 then rounded to FP32
+    assert len({t[6] for t in lo}) >= 2                       # overlaps exercise the fallback chain
+    g.close()
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_fixed_sphere_body_force_500_steps(store):
+    """Fixed sphere r = 4.5 at the centre of a 32^3 box driven by g = 1e-6,
+    quadratic IBB, 500 steps from rest (the plain-method drag case)."""
+    shape = (32, 32, 32)
+    F = (1e-6, 0.0, 0.0)
+    o, g = _pair(shape, tau=0.6, F=F, store=store, max_np=1, max_r=4.5)
+    o.set_particles([[16.0, 16.0, 16.0]], r=[4.5], motion="fixed")
+    g.set_particles([[16.0, 16.0, 16.0]], [4.5], motion=MOTION["fixed"])
+    for chunk in (1, 9, 90, 400):
+        o.step(chunk)
+        g.step(chunk)
+        fluid = o.fluid_mask()
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        tol = 1e-5 if store == 0 else 2e-3
+        assert rel_l2(ug, uo, fluid) < tol, o.state.step
+        Fg, Tg, _ = g.forces()
+        Fo, To, _ = o.forces()
+        # from rest the first step's link forces cancel to round-off
+        assert abs(Fg[0, 0] - Fo[0, 0]) <= (1e-5 if store == 0 else 3e-3) * abs(Fo[0, 0]) + 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_moving_spheres_release_contact_refill(store):
+    """Freely moving neutrally buoyant spheres released into a seeded
+    turbulence field: refill, cover/uncover momentum, contact forces."""
+    shape = (48, 44, 40)
+    spec = synth.hit_spectrum(seed=3, u_rms=0.04, kcut=10)
+    u0 = synth.hit_field(spec, shape)
+    # spheres 0 and 1 start in contact (gap -0.4); sphere 5 straddles three
+    # periodic faces; all other gaps exceed 6 lattice units
+    X = np.array([[10.0, 10.0, 10.0], [19.6, 10.3, 10.0], [30.0, 28.0, 25.0], [12.0, 30.0, 28.0],
+                  [36.0, 12.0, 30.0], [46.5, 2.0, 38.7]])
+    r = np.full(6, 5.0)
+    o, g = _pair(shape, tau=0.55, store=store, max_np=6, max_r=5.0, coll_restitution=0.9, coll_tc_steps=8.0)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, r=r, mode=RELEASE)
+    g.set_particles(X, r, mode=1)
+    Xg, Ug, _ = g.get_particles()
+    Xo, Uo = o.state.P.X, o.state.P.U
+    assert np.abs(Xg - Xo).max() < 1e-12
+    assert np.abs(Ug - Uo).max() < (1e-6 if store == 0 else 2e-3) * np.abs(Uo).max()
+    moved = 0
+    for _ in range(6):
+        o.step(5)
+        g.step(5)
+        moved += o.state.extra["uncovered"]
+        fluid = o.fluid_mask()
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        tol = 1e-5 if store == 0 else 2e-3
+        assert rel_l2(ug, uo, fluid) < tol, o.state.step
+        Xg, Ug, Wg = g.get_particles()
+        P = o.state.P
+        assert np.abs(Xg - P.X).max() < (1e-6 if store == 0 else 2e-4)
+        assert rel_l2(Ug, P.U) < (1e-4 if store == 0 else 1e-2)
+        Fg, Tg, Fcg = g.forces()
+        Fo, To, Fco = o.forces()
+        assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
+        assert np.abs(Fco).max() == 0 or rel_l2(Fcg, Fco) < (1e-6 if store == 0 else 1e-3)
+    assert np.abs(o.state.F_c).max() > 0 or moved > 0
+    g.close()
+
+
+def test_comoving_sphere_stays_uniform_on_gpu():
+    shape = (24, 20, 22)
+    U = np.array([0.021, -0.013, 0.008])
+    o, g = _pair(shape, tau=0.7, max_np=1, max_r=4.0)
+    u0 = np.broadcast_to(U[:, None, None, None], (3, 22, 20, 24))
+    g.set_particles([[11.3, 9.9, 10.6]], [3.4], u=[U], motion=MOTION["prescribed"])
+    g.set_fields(u0)
+    g.step(80)
+    ug, rg = g.get_fields()
+    X, _, _ = g.get_particles()
+    owner = __import__("oracle.geometry", fromlist=["owner_map"]).owner_map(shape, X, np.array([3.4]))
+    fluid = owner == -1
+    assert np.abs(ug[:, fluid] - U[:, None]).max() < 2e-6
+    assert np.abs(rg[fluid] - 1).max() < 2e-6
+    g.close()
+
+
+def test_pipe_wall_linear_ibb():
+    """Static pipe wall along z (linear IBB, ray-cylinder q), body-force
+    driven, FP32 vs FP64."""
+    shape = (24, 24, 8)
+    F = (0.0, 0.0, 2e-5)
+    kw = dict(wall="pipe_z", pipe_radius=9.3, pipe_cx=11.5, pipe_cy=11.7)
+    o = OSim(OConfig(shape=shape, tau=0.8, body_force=F, bc="ibb", ibb_max_order=1, **kw))
+    g = gpu_lattice(gpu_config(nx=24, ny=24, nz=8, tau=0.8, body_force=F, bc=1, ibb_max_order=1, wall=1,
+                               pipe_radius=9.3, pipe_cx=11.5, pipe_cy=11.7))
+    lo, lg = _oracle_links_sorted(o), _gpu_links_sorted(g)
+    assert [t[1:5] for t in lo] == [t[1:5] for t in lg]
+    assert all(a[5] == b[5] and a[6] == b[6] for a, b in zip(lo, lg))
+    o.step(200)
+    g.step(200)
+    ug, _ = g.get_fields()
+    uo, _ = o.fields()
+    assert rel_l2(ug, uo, o.fluid_mask()) < 1e-5
+    g.close()
