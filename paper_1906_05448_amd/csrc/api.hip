@@ -148,6 +148,10 @@ int check_config(const lbm_config* c) {
     if (!(c->pipe_radius > 1.0) || !isfinite(c->pipe_cx) || !isfinite(c->pipe_cy)) return LBM_E_ARG;
   }
   if (c->max_particles < 0 || c->max_particles > (1 << 24)) return LBM_E_ARG;
+  // Boundary nodes are stored as packed 11/11/10-bit coordinates.
+  if ((c->max_particles > 0 || c->wall != LBM_WALL_NONE) && (c->nx > 2048 || c->ny > 2048 || c->nz > 1024))
+    return LBM_E_SIZE;
+  if (c->max_radius > 28.0) return LBM_E_ARG;
   if (c->max_particles > 0) {
     if (c->bc == LBM_BC_NONE) return LBM_E_ARG;
     if (!(c->max_radius > 0.0) || 2.0 * c->max_radius + 8.0 > (double)std::min(c->nx, std::min(c->ny, c->nz)))
@@ -206,10 +210,7 @@ hipError_t step_ibb(Ctx& c) {
       const int on = 1 - c.ocur;
       e = timed(c, LBM_K_GEOMETRY, [&] {
         hipError_t r = launch_owner_clear(c, c.ibb.owner[on], c.P.Xown[on], c.np);
-        if (r == hipSuccess)
-          r = hipMemcpyAsync(c.ibb.solid_bits, c.ibb.wall_bits, mask_words(c.dims.N) * 4, hipMemcpyDeviceToDevice,
-                             c.stream);
-        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.ibb.solid_bits, c.P.X[pn]);
+        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.P.X[pn]);
         if (r == hipSuccess)
           r = hipMemcpyAsync(c.P.Xown[on], c.P.X[pn], pvec_bytes(c), hipMemcpyDeviceToDevice, c.stream);
         if (r == hipSuccess) r = launch_links_build(c, c.ibb.owner[on], c.P.X[pn]);
@@ -461,10 +462,7 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
   c.ocur = 0;
   if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[0]);
   if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[1]);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(c.ibb.solid_bits, c.ibb.wall_bits, mask_words(c.dims.N) * 4, hipMemcpyDeviceToDevice,
-                       c.stream);
-  if (e == hipSuccess) e = launch_owner_set(c, c.ibb.owner[0], c.ibb.solid_bits, c.P.X[0]);
+  if (e == hipSuccess) e = launch_owner_set(c, c.ibb.owner[0], c.P.X[0]);
   if (e == hipSuccess && mode == LBM_RELEASE && np > 0) {
     float* ufield = (float*)c.f_nxt;  // idle between steps
     double* U0 = c.P.F_h;             // scratch until the first step
@@ -556,8 +554,8 @@ int lbm_get_links(lbm_ctx* h, int64_t cap, int32_t* node, int32_t* dir, int32_t*
   auto emit = [&](uint32_t nn, float qv, uint8_t meta, int32_t p) {
     if (k >= cap) return;
     const int a = meta & 31;
-    const int x = (int)(nn % (uint32_t)c.cfg.nx), y = (int)((nn / (uint32_t)c.cfg.nx) % (uint32_t)c.cfg.ny),
-              z = (int)(nn / ((uint32_t)c.cfg.nx * (uint32_t)c.cfg.ny));
+    // packed coordinates x | y << 11 | z << 22
+    const int x = (int)(nn & 2047u), y = (int)((nn >> 11) & 2047u), z = (int)(nn >> 22);
     if (node) {
       node[3 * k] = x;
       node[3 * k + 1] = y;
@@ -587,15 +585,18 @@ int lbm_geometry_counts(lbm_ctx* h, int64_t* solid_nodes, int64_t* links) {
   if (!h) return LBM_E_ARG;
   Ctx& c = h->c;
   if (solid_nodes) {
-    std::vector<uint32_t> bits(mask_words(c.dims.N));
-    if (hipMemcpyAsync(bits.data(), c.ibb.solid_bits, bits.size() * 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
-      return LBM_E_HIP;
-    const int st = drain_errors(c);
-    if (st != LBM_OK) return st;
-    int64_t s = 0;
-    if (c.cfg.bc == LBM_BC_IBB)
-      for (uint32_t w : bits) s += __builtin_popcount(w);
-    *solid_nodes = s;
+    *solid_nodes = 0;
+    if (c.cfg.bc == LBM_BC_IBB) {
+      unsigned long long* cnt = (unsigned long long*)c.scratch_d;
+      unsigned long long s = 0;
+      hipError_t e = hipMemsetAsync(cnt, 0, sizeof(s), c.stream);
+      if (e == hipSuccess) e = launch_count_solid(c, c.ibb.owner[c.ocur], cnt);
+      if (e == hipSuccess) e = hipMemcpyAsync(&s, cnt, sizeof(s), hipMemcpyDeviceToHost, c.stream);
+      if (e != hipSuccess) return LBM_E_HIP;
+      const int st = drain_errors(c);
+      if (st != LBM_OK) return st;
+      *solid_nodes = (int64_t)s;
+    }
   }
   if (links) return lbm_link_count(h, links);
   return drain_errors(c);

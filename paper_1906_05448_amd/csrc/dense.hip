@@ -136,25 +136,19 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
   return hipGetLastError();
 }
 
+// Interpolated bounce-back runs this kernel over solid nodes too: a sphere
+// of diameter 16 is narrower than one 64-node wavefront row, so skipping
+// them saves no cache lines and only costs divergence. Their values are never
+// read by a fluid node (those pull the ghost slots) and are refilled before
+// the node turns fluid.
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
-  const bool skip = c.cfg.bc == LBM_BC_IBB;
-  const uint32_t* solid = c.ibb.solid_bits;
-  if (c.cfg.store == LBM_STORE_F32) {
-    if (skip)
-      hipLaunchKernelGGL((k_stream_collide<0, 1>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
-                         c.rates, c.body_force, solid, c.err);
-    else
-      hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
-                         c.rates, c.body_force, solid, c.err);
-  } else {
-    if (skip)
-      hipLaunchKernelGGL((k_stream_collide<1, 1>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
-                         c.dims, c.rates, c.body_force, solid, c.err);
-    else
-      hipLaunchKernelGGL((k_stream_collide<1, 0>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
-                         c.dims, c.rates, c.body_force, solid, c.err);
-  }
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
+                       c.rates, c.body_force, nullptr, c.err);
+  else
+    hipLaunchKernelGGL((k_stream_collide<1, 0>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
+                       c.dims, c.rates, c.body_force, nullptr, c.err);
   return hipGetLastError();
 }
 

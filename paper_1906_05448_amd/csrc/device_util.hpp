@@ -53,6 +53,50 @@ __device__ __forceinline__ void box_node(const Box& b, uint32_t i, int nx, int n
   z = wrapi(b.lo[2] + iz, nz);
 }
 
+// Wrap for v in [-n, 2n): one conditional add or subtract, no division.
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Box traversal by x-rows: a 256-thread block covers 256/W rows of W lanes
+// per iteration (W = 32 or 64 >= side_x), so a node's coordinates cost one
+// division per row instead of two per node and wrapping needs no modulo.
+struct BoxRows {
+  int W, shift, rows_per_iter, nrows;
+};
+
+__device__ __forceinline__ BoxRows box_rows(const Box& b) {
+  BoxRows r;
+  r.W = b.side[0] <= 32 ? 32 : 64;
+  r.shift = b.side[0] <= 32 ? 5 : 6;
+  r.rows_per_iter = 256 >> r.shift;
+  r.nrows = b.side[1] * b.side[2];
+  return r;
+}
+
+// Node of lane t in iteration `base` (rows base .. base + rows_per_iter - 1).
+// Returns false for lanes beyond the box.
+__device__ __forceinline__ bool box_row_node(const Box& b, const BoxRows& br, int base, int t, int nx, int ny, int nz,
+                                             int& x, int& y, int& z) {
+  const int row = base + (t >> br.shift);
+  const int ix = t & (br.W - 1);
+  if (row >= br.nrows || ix >= b.side[0]) return false;
+  const int iy = row % b.side[1];
+  const int iz = row / b.side[1];
+  x = wrap1(b.lo[0] + ix, nx);
+  y = wrap1(b.lo[1] + iy, ny);
+  z = wrap1(b.lo[2] + iz, nz);
+  return true;
+}
+
+// Link nodes are stored as packed coordinates x | y << 11 | z << 22.
+__device__ __forceinline__ uint32_t pack_xyz(int x, int y, int z) {
+  return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);
+}
+__device__ __forceinline__ void unpack_xyz(uint32_t v, int& x, int& y, int& z) {
+  x = (int)(v & 2047u);
+  y = (int)((v >> 11) & 2047u);
+  z = (int)(v >> 22);
+}
+
 __device__ __forceinline__ uint32_t node_index(int x, int y, int z, int nx, int ny) {
   return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
 }

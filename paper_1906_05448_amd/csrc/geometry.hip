@@ -7,8 +7,10 @@
 // the lowest particle index (atomicMin on the owner map). The pipe wall is
 // solid where (x - cx)^2 + (y - cy)^2 >= R^2.
 //
-// Links are built per sphere by one workgroup that walks the sphere's box in
-// raster order; a block-wide prefix sum gives every link a deterministic
+// Links are built per sphere by one workgroup. It first compacts the nodes
+// of the shell r <= |x - X| < r + sqrt(2) (the only possible fluid ends of
+// its links) into an LDS list in raster order, then examines the list with
+// every lane busy; a block-wide prefix sum gives every link a deterministic
 // slot, so the link order (and every FP64 sum over links) is reproducible.
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -18,6 +20,7 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kCand = 2048;  // shell candidates buffered in LDS per flush
 
 __device__ __forceinline__ bool inside_sphere(int x, int y, int z, const double* X, double r, double Lx, double Ly,
                                               double Lz) {
@@ -34,34 +37,51 @@ __global__ void __launch_bounds__(256) k_owner_fill(uint32_t* __restrict__ owner
   owner[n] = ((wall[n >> 5] >> (n & 31u)) & 1u) ? kWall : kFluid;
 }
 
-// Resets the box of every particle at its old position to fluid.
+// Resets the nodes inside every particle at its old position to fluid (every
+// entry a set pass wrote lies inside some sphere at the positions it used).
 __global__ void __launch_bounds__(kBlock) k_owner_clear(uint32_t* __restrict__ owner, const double* __restrict__ Xold,
                                                         const double* __restrict__ rad, Dims d) {
   const int p = blockIdx.x;
-  const Box b = make_box(Xold + 3 * p, rad[p] + 1.0);
-  const uint32_t cnt = b.count();
-  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+  const double r = rad[p];
+  const double* Xp = Xold + 3 * p;
+  const Box b = make_box(Xp, r + 1.0);
+  const BoxRows br = box_rows(b);
+  for (int base = 0; base < br.nrows; base += br.rows_per_iter) {
     int x, y, z;
-    box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+    if (!box_row_node(b, br, base, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     if (owner[n] != kWall) owner[n] = kFluid;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ owner, uint32_t* __restrict__ bits,
-                                                      const double* __restrict__ X, const double* __restrict__ rad,
-                                                      Dims d) {
+__global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ owner, const double* __restrict__ X,
+                                                      const double* __restrict__ rad, Dims d) {
   const int p = blockIdx.x;
   const double r = rad[p];
-  const Box b = make_box(X + 3 * p, r + 1.0);
-  const uint32_t cnt = b.count();
-  for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+  const double* Xp = X + 3 * p;
+  const Box b = make_box(Xp, r + 1.0);
+  const BoxRows br = box_rows(b);
+  for (int base = 0; base < br.nrows; base += br.rows_per_iter) {
     int x, y, z;
-    box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
-    if (!inside_sphere(x, y, z, X + 3 * p, r, d.nx, d.ny, d.nz)) continue;
-    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
-    atomicMin(owner + n, (uint32_t)p);
-    if (bits) atomicOr(bits + (n >> 5), 1u << (n & 31u));
+    if (!box_row_node(b, br, base, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
+    atomicMin(owner + node_index(x, y, z, d.nx, d.ny), (uint32_t)p);
+  }
+}
+
+// Nodes not owned by the fluid (spheres and wall), for reporting.
+__global__ void __launch_bounds__(256) k_count_solid(const uint32_t* __restrict__ owner, uint32_t N,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ unsigned int part[4];
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  const bool solid = n < N && owner[n] != kFluid;
+  const unsigned long long b = __ballot(solid);
+  if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = (unsigned int)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int s = part[0] + part[1] + part[2] + part[3];
+    if (s) atomicAdd(out, (unsigned long long)s);
   }
 }
 
@@ -85,37 +105,29 @@ __device__ __forceinline__ uint32_t pick_scheme(double q, bool f1, bool f2, int 
 }
 
 __device__ __forceinline__ uint32_t neighbour(int x, int y, int z, int k, int i, const Dims& d) {
-  return node_index(wrapi(x + k * cx_of(i), d.nx), wrapi(y + k * cy_of(i), d.ny), wrapi(z + k * cz_of(i), d.nz),
+  return node_index(wrap1(x + k * cx_of(i), d.nx), wrap1(y + k * cy_of(i), d.ny), wrap1(z + k * cz_of(i), d.nz),
                     d.nx, d.ny);
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, const double* __restrict__ rad, Dims d,
-              int max_order, uint32_t cap, uint32_t* __restrict__ link_node, float* __restrict__ link_q,
-              uint8_t* __restrict__ link_meta, uint32_t* __restrict__ link_count, uint32_t* __restrict__ err) {
-  const uint32_t p = blockIdx.x;
-  const double r = rad[p];
-  const double* Xp = X + 3 * p;
-  const Box b = make_box(Xp, r + 2.0);
-  const uint32_t cnt = b.count();
-  const size_t base = (size_t)p * cap;
-  uint32_t written = 0;
-  for (uint32_t i0 = 0; i0 < cnt; i0 += kBlock) {
-    const uint32_t i = i0 + threadIdx.x;
+// Examines the buffered shell candidates and writes their links from slot
+// `written` on. Every thread must call it.
+__device__ void flush_candidates(const uint32_t* __restrict__ owner, const double* Xp, double r, const Dims& d,
+                                 int max_order, uint32_t p, uint32_t cap, size_t base, const uint32_t* cand,
+                                 int ncand, uint32_t& written, uint32_t* __restrict__ link_node,
+                                 float* __restrict__ link_q, uint8_t* __restrict__ link_meta) {
+  for (int c0 = 0; c0 < ncand; c0 += kBlock) {
+    const int k = c0 + (int)threadIdx.x;
     int x = 0, y = 0, z = 0;
-    uint32_t n = 0, mine = 0, hits = 0;
-    if (i < cnt) {
-      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
-      n = node_index(x, y, z, d.nx, d.ny);
-      if (owner[n] == kFluid) {
+    uint32_t hits = 0;
+    if (k < ncand) {
+      unpack_xyz(cand[k], x, y, z);
+      if (owner[node_index(x, y, z, d.nx, d.ny)] == kFluid)
         for (int a = 1; a < kQ; ++a)
           if (owner[neighbour(x, y, z, 1, a, d)] == p) hits |= 1u << a;
-        mine = __popc(hits);
-      }
     }
     uint32_t total;
-    uint32_t off = written + block_exclusive_scan<kBlock>(mine, &total);
-    if (mine) {
+    uint32_t off = written + block_exclusive_scan<kBlock>(__popc(hits), &total);
+    if (hits) {
       const double dx = min_image((double)x - Xp[0], d.nx);
       const double dy = min_image((double)y - Xp[1], d.ny);
       const double dz = min_image((double)z - Xp[2], d.nz);
@@ -126,7 +138,7 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
         const bool f2 = owner[neighbour(x, y, z, -2, a, d)] == kFluid;
         const uint32_t s = pick_scheme(q, f1, f2, max_order);
         if (off < cap) {
-          link_node[base + off] = n;
+          link_node[base + off] = pack_xyz(x, y, z);
           link_q[base + off] = (float)q;
           link_meta[base + off] = (uint8_t)(a | (s << 5));
         }
@@ -135,6 +147,44 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
     }
     written += total;
   }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, const double* __restrict__ rad, Dims d,
+              int max_order, uint32_t cap, uint32_t* __restrict__ link_node, float* __restrict__ link_q,
+              uint8_t* __restrict__ link_meta, uint32_t* __restrict__ link_count, uint32_t* __restrict__ err) {
+  __shared__ uint32_t cand[kCand];
+  const uint32_t p = blockIdx.x;
+  const double r = rad[p];
+  const double* Xp = X + 3 * p;
+  const Box b = make_box(Xp, r + 2.0);
+  const BoxRows br = box_rows(b);
+  const size_t base = (size_t)p * cap;
+  // The outer bound only prunes, so it carries a margin.
+  const double r_out = r + 1.4142135623730951 + 1e-6;
+  const double r2 = r * r, ro2 = r_out * r_out;
+  uint32_t written = 0;
+  int ncand = 0;
+  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
+    int x = 0, y = 0, z = 0;
+    bool shell = false;
+    if (box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) {
+      const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
+                              min_image((double)z - Xp[2], d.nz));
+      shell = d2 >= r2 && d2 < ro2;
+    }
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan<kBlock>(shell ? 1u : 0u, &total);
+    if (ncand + (int)total > kCand) {  // uniform: total is block-wide
+      flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, written, link_node, link_q, link_meta);
+      __syncthreads();
+      ncand = 0;
+    }
+    if (shell) cand[ncand + off] = pack_xyz(x, y, z);
+    ncand += (int)total;
+    __syncthreads();
+  }
+  flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, written, link_node, link_q, link_meta);
   if (threadIdx.x == 0) {
     if (written > cap) {
       atomicOr(err, kErrCapacity);
@@ -170,7 +220,7 @@ k_wall_links(const uint32_t* __restrict__ owner, Dims d, double R, double pcx, d
     const double q = pipe_q((double)x - pcx, (double)y - pcy, cx_of(a), cy_of(a), R);
     const bool f1 = owner[neighbour(x, y, z, -1, a, d)] == kFluid;
     const uint32_t s = pick_scheme(q, f1, false, 1);
-    node_out[slot] = n;
+    node_out[slot] = pack_xyz(x, y, z);
     q_out[slot] = (float)q;
     meta_out[slot] = (uint8_t)(a | (s << 5));
   }
@@ -190,9 +240,15 @@ hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold,
   return hipGetLastError();
 }
 
-hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, uint32_t* solid_bits, const double* X) {
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X) {
   if (c.np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_owner_set, dim3(c.np), dim3(kBlock), 0, c.stream, owner, solid_bits, X, c.P.r, c.dims);
+  hipLaunchKernelGGL(k_owner_set, dim3(c.np), dim3(kBlock), 0, c.stream, owner, X, c.P.r, c.dims);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_solid(const Ctx& c, const uint32_t* owner, unsigned long long* out) {
+  const uint32_t N = c.dims.N;
+  hipLaunchKernelGGL(k_count_solid, dim3((N + 255) / 256), dim3(256), 0, c.stream, owner, N, out);
   return hipGetLastError();
 }
 

@@ -80,7 +80,7 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
     const int a = (int)(meta & 31u);
     const uint32_t scheme = meta >> 5;
     int x, y, z;
-    node_coords(nf, d.nx, d.ny, x, y, z);
+    unpack_xyz(nf, x, y, z);
     const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
     // lever arm x_w - X and wall velocity U + Omega x arm
     const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q * cx,
@@ -89,13 +89,14 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
     const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
                           Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
     const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
-    const uint32_t nm1 = node_index(wrapi(x - cx, d.nx), wrapi(y - cy, d.ny), wrapi(z - cz, d.nz), d.nx, d.ny);
+    const uint32_t n0 = node_index(x, y, z, d.nx, d.ny);
+    const uint32_t nm1 = node_index(wrap1(x - cx, d.nx), wrap1(y - cy, d.ny), wrap1(z - cz, d.nz), d.nx, d.ny);
     const uint32_t nm2 =
-        node_index(wrapi(x - 2 * cx, d.nx), wrapi(y - 2 * cy, d.ny), wrapi(z - 2 * cz, d.nz), d.nx, d.ny);
-    const uint32_t ns = node_index(wrapi(x + cx, d.nx), wrapi(y + cy, d.ny), wrapi(z + cz, d.nz), d.nx, d.ny);
-    const float gnew = bounce_value<STORE>(A, d.N, nf, nm1, nm2, a, scheme, q, delta);
+        node_index(wrap1(x - 2 * cx, d.nx), wrap1(y - 2 * cy, d.ny), wrap1(z - 2 * cz, d.nz), d.nx, d.ny);
+    const uint32_t ns = node_index(wrap1(x + cx, d.nx), wrap1(y + cy, d.ny), wrap1(z + cz, d.nz), d.nx, d.ny);
+    const float gnew = bounce_value<STORE>(A, d.N, n0, nm1, nm2, a, scheme, q, delta);
     Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
-    const double fa = (double)ld<STORE>(A, a, d.N, nf) + (double)w_of(a);
+    const double fa = (double)ld<STORE>(A, a, d.N, n0) + (double)w_of(a);
     const double fb = (double)gnew + (double)w_of(a);
     const double c[3] = {(double)cx, (double)cy, (double)cz};
     double Fl[3];
@@ -129,11 +130,12 @@ k_wall_bounce(typename Pop<STORE>::T* A, Dims d, uint32_t count, const uint32_t*
   const uint32_t meta = meta_v[k];
   const int a = (int)(meta & 31u);
   int x, y, z;
-  node_coords(nf, d.nx, d.ny, x, y, z);
+  unpack_xyz(nf, x, y, z);
   const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
-  const uint32_t nm1 = node_index(wrapi(x - cx, d.nx), wrapi(y - cy, d.ny), wrapi(z - cz, d.nz), d.nx, d.ny);
-  const uint32_t ns = node_index(wrapi(x + cx, d.nx), wrapi(y + cy, d.ny), wrapi(z + cz, d.nz), d.nx, d.ny);
-  const float gnew = bounce_value<STORE>(A, d.N, nf, nm1, nm1, a, meta >> 5, q, 0.0f);
+  const uint32_t n0 = node_index(x, y, z, d.nx, d.ny);
+  const uint32_t nm1 = node_index(wrap1(x - cx, d.nx), wrap1(y - cy, d.ny), wrap1(z - cz, d.nz), d.nx, d.ny);
+  const uint32_t ns = node_index(wrap1(x + cx, d.nx), wrap1(y + cy, d.ny), wrap1(z + cz, d.nz), d.nx, d.ny);
+  const float gnew = bounce_value<STORE>(A, d.N, n0, nm1, nm1, a, meta >> 5, q, 0.0f);
   Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
 }
 
@@ -245,13 +247,24 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   const double Up[3] = {Unew[3 * p], Unew[3 * p + 1], Unew[3 * p + 2]};
   const double Wp[3] = {Omnew[3 * p], Omnew[3 * p + 1], Omnew[3 * p + 2]};
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  const double* Xo = Xold + 3 * p;
+  // A node p uncovers lies inside p's old sphere and outside its new one; a
+  // node p covers lies inside the new sphere and outside the old one. The
+  // exact FP64 tests (the same ones that built the owner maps) prune the box
+  // before the owner maps are read.
+  auto inside = [&](int x, int y, int z, const double* C) {
+    const double dx = min_image((double)x - C[0], d.nx), dy = min_image((double)y - C[1], d.ny),
+                 dz = min_image((double)z - C[2], d.nz);
+    return dist2(dx, dy, dz) < r * r;
+  };
   // uncovered: solid for p before, fluid now
   {
-    const Box b = make_box(Xold + 3 * p, r + 1.0);
-    const uint32_t cnt = b.count();
-    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    const Box b = make_box(Xo, r + 1.0);
+    const BoxRows br = box_rows(b);
+    for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
       int x, y, z;
-      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+      if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+      if (!inside(x, y, z, Xo) || inside(x, y, z, Xn)) continue;
       const uint32_t n = node_index(x, y, z, d.nx, d.ny);
       if (o_old[n] != p || o_new[n] != kFluid) continue;
       const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
@@ -269,10 +282,11 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   // covered: fluid before, solid for p now
   {
     const Box b = make_box(Xn, r + 1.0);
-    const uint32_t cnt = b.count();
-    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    const BoxRows br = box_rows(b);
+    for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
       int x, y, z;
-      box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
+      if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+      if (!inside(x, y, z, Xn) || inside(x, y, z, Xo)) continue;
       const uint32_t n = node_index(x, y, z, d.nx, d.ny);
       if (o_new[n] != p || o_old[n] != kFluid) continue;
       double mom[3] = {0, 0, 0};

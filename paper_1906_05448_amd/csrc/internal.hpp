@@ -183,7 +183,8 @@ hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float*
 // Geometry (geometry.hip).
 hipError_t launch_owner_fill(const Ctx& c, uint32_t* owner);
 hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold, int32_t np_old);
-hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, uint32_t* solid_bits, const double* X);
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X);
+hipError_t launch_count_solid(const Ctx& c, const uint32_t* owner, unsigned long long* out);
 hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double* X);
 hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only);
 

@@ -30,8 +30,10 @@ k_particle_update(int np, int motion, int bc, Dims d, const double* __restrict__
                   const double* __restrict__ Iu_new, const double* __restrict__ IL_new, double* __restrict__ F_h,
                   double* __restrict__ T_h, double* __restrict__ F_c, double lne, double tc,
                   uint32_t* __restrict__ err) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= np) return;
+  // One wavefront per particle: lanes stride over the partners, a butterfly
+  // reduction (fixed order) combines them, lane 0 applies the update.
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   const double L[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
   const double ri = rad[i];
   const double mi = rho_p[i] * (4.0 / 3.0) * kPi * ri * ri * ri;
@@ -52,7 +54,7 @@ k_particle_update(int np, int motion, int bc, Dims d, const double* __restrict__
   if (motion == LBM_MOTION_FREE) {
     const double Xi[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
     const double Ui[3] = {U[3 * i], U[3 * i + 1], U[3 * i + 2]};
-    for (int j = 0; j < np; ++j) {
+    for (int j = lane; j < np; j += 64) {
       if (j == i) continue;
       const double dx = min_image(Xi[0] - X[3 * j], L[0]);
       const double dy = min_image(Xi[1] - X[3 * j + 1], L[1]);
@@ -74,6 +76,9 @@ k_particle_update(int np, int motion, int bc, Dims d, const double* __restrict__
       Fc[2] += mag * n[2];
     }
   }
+  for (int k = 0; k < 3; ++k)
+    for (int o = 32; o > 0; o >>= 1) Fc[k] += __shfl_xor(Fc[k], o, 64);
+  if (lane != 0) return;
   for (int k = 0; k < 3; ++k) {
     double u1 = U[3 * i + k], w1 = Om[3 * i + k];
     if (motion == LBM_MOTION_FREE) {
@@ -171,7 +176,7 @@ hipError_t launch_particle_update(const Ctx& c) {
   const int pc = c.pcur, pn = 1 - c.pcur;
   const bool ibb = c.cfg.bc == LBM_BC_IBB;
   const double lne = log(c.cfg.coll_restitution);
-  hipLaunchKernelGGL(k_particle_update, dim3((c.np + 63) / 64), dim3(64), 0, c.stream, c.np, c.motion, c.cfg.bc,
+  hipLaunchKernelGGL(k_particle_update, dim3(c.np), dim3(64), 0, c.stream, c.np, c.motion, c.cfg.bc,
                      c.dims, c.P.X[pc], c.P.U[pc], c.P.Om[pc], c.P.X[pn], c.P.U[pn], c.P.Om[pn], c.P.r, c.P.rho,
                      ibb ? c.P.F_link : c.P.F_ib, ibb ? c.P.T_link : c.P.T_ib, c.P.F_rc, c.P.T_rc, c.P.Iu, c.P.IL,
                      c.P.Iu_new, c.P.IL_new, c.P.F_h, c.P.T_h, c.P.F_c, lne, c.cfg.coll_tc_steps, c.err);
