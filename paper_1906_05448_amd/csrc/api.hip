@@ -77,6 +77,70 @@ uint32_t wall_link_count(const lbm_config& c) {
   return (uint32_t)(n * (uint64_t)c.nz);
 }
 
+// Immersed boundary marker layout (Uhlmann/Breugem count and a Fibonacci
+// lattice of directions; the paper only asks for a marker volume close to
+// the cell volume, Sec. 2.1).
+int marker_count(double r_l) { return (int)lround(M_PI * (12.0 * r_l * r_l + 1.0) / 3.0); }
+double marker_volume(double r_l, int n) {
+  return (4.0 / 3.0) * M_PI * ((r_l + 0.5) * (r_l + 0.5) * (r_l + 0.5) - (r_l - 0.5) * (r_l - 0.5) * (r_l - 0.5)) / n;
+}
+void fibonacci_dirs(int n, std::vector<double>& out) {
+  out.resize(3 * (size_t)n);
+  const double ga = M_PI * (3.0 - sqrt(5.0));
+  for (int k = 0; k < n; ++k) {
+    const double z = 1.0 - (2.0 * k + 1.0) / n;
+    const double phi = k * ga;
+    const double s = sqrt(1.0 - z * z);
+    out[3 * k] = s * cos(phi);
+    out[3 * k + 1] = s * sin(phi);
+    out[3 * k + 2] = z;
+  }
+}
+int ibm_half_width(double r, double r_d) {
+  return std::max((int)ceil(r - r_d) + 3, (int)ceil(r) + 2);
+}
+int ibm_box_side(double r, double r_d) { return 2 * ibm_half_width(r, r_d) + 2; }
+
+// Forcing support (union of marker stencils) and full support (plus the
+// Kempe cells) of an isolated sphere, maximised over sub-grid offsets:
+// capacity bounds (neighbours only merge supports).
+void ibm_support_bounds(double r, double r_d, uint32_t& forcing, uint32_t& full) {
+  const double r_l = r - r_d;
+  const int n = marker_count(r_l);
+  std::vector<double> dirs;
+  fibonacci_dirs(n, dirs);
+  const int R = ibm_half_width(r, r_d), side = 2 * R + 2;
+  forcing = full = 0;
+  std::vector<uint8_t> box((size_t)side * side * side);
+  for (int t = 0; t < 27; ++t) {
+    const double o[3] = {0.5 * (t % 3) * 0.5 + 0.03, 0.5 * ((t / 3) % 3) * 0.5 + 0.07, 0.5 * (t / 9) * 0.5 + 0.11};
+    std::fill(box.begin(), box.end(), 0);
+    const int lo = -R;  // floor(o) = 0
+    for (int l = 0; l < n; ++l) {
+      int b[3];
+      for (int k = 0; k < 3; ++k) b[k] = (int)floor(o[k] + r_l * dirs[3 * l + k]) - 1 - lo;
+      for (int jz = 0; jz < 4; ++jz)
+        for (int jy = 0; jy < 4; ++jy)
+          for (int jx = 0; jx < 4; ++jx) box[((size_t)(b[2] + jz) * side + b[1] + jy) * side + b[0] + jx] = 1;
+    }
+    uint32_t f = 0, a = 0;
+    const double ra = r + 0.8661;
+    for (int z = 0; z < side; ++z)
+      for (int y = 0; y < side; ++y)
+        for (int x = 0; x < side; ++x) {
+          const size_t i = ((size_t)z * side + y) * side + x;
+          const double dx = x + lo - o[0], dy = y + lo - o[1], dz = z + lo - o[2];
+          const bool cell = (dx * dx + dy * dy) + dz * dz < ra * ra;
+          f += box[i];
+          a += (box[i] || cell) ? 1u : 0u;
+        }
+    forcing = std::max(forcing, f);
+    full = std::max(full, a);
+  }
+  forcing = (uint32_t)(forcing * 1.05) + 32;
+  full = (uint32_t)(full * 1.05) + 32;
+}
+
 // Workspace plan: offsets of every slice for a configuration.
 struct Plan {
   size_t f_a, f_b, err, scratch;
@@ -85,6 +149,11 @@ struct Plan {
   size_t link_node, link_q, link_meta, link_count;
   size_t wl_node, wl_q, wl_meta;
   uint32_t link_cap, wl_count;
+  // immersed boundary
+  size_t ib_bits[2], ib_rank[2], ib_count, ib_fib[2], ib_shared, ib_list, ib_us, ib_bsum, ib_dirs, ib_rowbits,
+      ib_fcount, ib_fslot;
+  uint32_t s_cap, fcap, n_markers;
+  int side;
   size_t total;
 };
 
@@ -124,6 +193,29 @@ Plan plan(const lbm_config& c) {
     p.wl_q = take((size_t)p.wl_count * 4 + 4);
     p.wl_meta = take((size_t)p.wl_count + 4);
   }
+  if (c.bc == LBM_BC_IBM) {
+    uint32_t forcing = 1, full = 1;
+    if (P) ibm_support_bounds(c.max_radius, c.ibm_retraction, forcing, full);
+    p.fcap = forcing;
+    p.s_cap = (uint32_t)std::min<uint64_t>((uint64_t)N, (uint64_t)P * full + 4096);
+    p.n_markers = P ? (uint32_t)marker_count(c.max_radius - c.ibm_retraction) : 0;
+    p.side = P ? ibm_box_side(c.max_radius, c.ibm_retraction) : 0;
+    const size_t rows = (size_t)p.side * p.side;
+    for (int b = 0; b < 2; ++b) {
+      p.ib_bits[b] = take(words * 4);
+      p.ib_rank[b] = take(words * 4);
+      p.ib_fib[b] = take((size_t)3 * p.s_cap * 4);
+    }
+    p.ib_count = take(2 * sizeof(uint32_t));
+    p.ib_shared = take(words * 4);
+    p.ib_list = take((size_t)p.s_cap * 4);
+    p.ib_us = take((size_t)p.s_cap * 16);
+    p.ib_bsum = take((words / 1024 + 2) * 4);
+    p.ib_dirs = take((size_t)std::max<uint32_t>(p.n_markers, 1) * 3 * sizeof(double));
+    p.ib_rowbits = take(P * rows * 4 + 4);
+    p.ib_fcount = take(P * 4 + 4);
+    p.ib_fslot = take(P * (size_t)p.fcap * 4 + 4);
+  }
   p.total = off;
   return p;
 }
@@ -141,7 +233,19 @@ int check_config(const lbm_config* c) {
   for (int k = 0; k < 3; ++k)
     if (!isfinite(c->body_force[k])) return LBM_E_ARG;
   if (c->store != LBM_STORE_F32 && c->store != LBM_STORE_F16S) return LBM_E_ARG;
-  if (c->bc != LBM_BC_NONE && c->bc != LBM_BC_IBB) return LBM_E_ARG;
+  if (c->bc != LBM_BC_NONE && c->bc != LBM_BC_IBB && c->bc != LBM_BC_IBM) return LBM_E_ARG;
+  if (c->bc == LBM_BC_IBM) {
+    // The immersed boundary runs on spheres here; its box (side 2 R_b + 2)
+    // must fit a 32-bit row mask.
+    if (c->wall != LBM_WALL_NONE) return LBM_E_ARG;
+    if (!(c->ibm_retraction >= 0.0) || c->ibm_retraction > 2.0) return LBM_E_ARG;
+    if (c->max_particles > 0) {
+      if (!(c->max_radius - c->ibm_retraction > 1.0)) return LBM_E_ARG;
+      const int side = ibm_box_side(c->max_radius, c->ibm_retraction);
+      // the box must not wrap onto itself
+      if (side > 32 || side > std::min(c->nx, std::min(c->ny, c->nz))) return LBM_E_ARG;
+    }
+  }
   if (c->wall != LBM_WALL_NONE && c->wall != LBM_WALL_PIPE_Z) return LBM_E_ARG;
   if (c->wall == LBM_WALL_PIPE_Z) {
     if (c->bc == LBM_BC_NONE) return LBM_E_ARG;
@@ -193,6 +297,45 @@ hipError_t zero_particle_accumulators(Ctx& c) {
   for (double* p : v) {
     hipError_t e = hipMemsetAsync(p, 0, b, c.stream);
     if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Kempe inner momentum of the current fields (step 0: the extraction force is
+// zero), the reference for the first step's inner-inertia term.
+hipError_t ibm_inner_momentum_init(Ctx& c) {
+  if (c.cfg.bc != LBM_BC_IBM || c.np <= 0) return hipSuccess;
+  float* ufield = (float*)c.f_nxt;  // idle between steps
+  hipError_t e = launch_fields(c, c.f_cur, extraction_force(c), ufield, nullptr);
+  if (e == hipSuccess) e = launch_kempe_dense(c, ufield, c.P.X[c.pcur], c.P.Iu, c.P.IL);
+  return e;
+}
+
+hipError_t step_ibm(Ctx& c) {
+  const int pc = c.pcur, pn = 1 - c.pcur;
+  hipError_t e = timed(c, LBM_K_IBM_PREPASS, [&] { return launch_ibm_prepass(c, c.f_cur); });
+  if (e != hipSuccess) return e;
+  if (c.np > 0) {
+    e = timed(c, LBM_K_IBM_FORCING, [&] { return launch_ibm_forcing_pass(c, c.P.X[pc], c.P.U[pc], c.P.Om[pc]); });
+    if (e != hipSuccess) return e;
+    e = timed(c, LBM_K_PARTICLE, [&] {
+      hipError_t r = launch_ibm_kempe(c, c.P.X[pc], c.P.Iu_new, c.P.IL_new);
+      if (r == hipSuccess) r = launch_particle_update(c);
+      return r;
+    });
+    if (e != hipSuccess) return e;
+  }
+  e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide_ibm(c, c.f_cur, c.f_nxt); });
+  if (e != hipSuccess) return e;
+  c.ibm.last = c.ibm.cur;
+  if (c.np > 0) {
+    if (c.motion != LBM_MOTION_FIXED) {
+      const int nb = 1 - c.ibm.cur;
+      e = timed(c, LBM_K_GEOMETRY, [&] { return launch_ibm_support_build(c, nb, c.P.X[pn]); });
+      if (e != hipSuccess) return e;
+      c.ibm.cur = nb;
+    }
+    c.pcur = pn;
   }
   return hipSuccess;
 }
@@ -332,6 +475,37 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.ibb.wl_meta = (uint8_t*)(base + p.wl_meta);
     c.ibb.wl_count = p.wl_count;
   }
+  c.ibm = IbmBufs{};
+  if (cfg->bc == LBM_BC_IBM) {
+    IbmBufs& m = c.ibm;
+    for (int b = 0; b < 2; ++b) {
+      m.bits[b] = (uint32_t*)(base + p.ib_bits[b]);
+      m.rank[b] = (uint32_t*)(base + p.ib_rank[b]);
+      m.fib[b] = (float*)(base + p.ib_fib[b]);
+      m.count[b] = (uint32_t*)(base + p.ib_count) + b;
+    }
+    m.shared = (uint32_t*)(base + p.ib_shared);
+    m.list = (uint32_t*)(base + p.ib_list);
+    m.us = (float4*)(base + p.ib_us);
+    m.block_sums = (uint32_t*)(base + p.ib_bsum);
+    m.dirs = (double*)(base + p.ib_dirs);
+    m.rowbits = (uint32_t*)(base + p.ib_rowbits);
+    m.fcount = (uint32_t*)(base + p.ib_fcount);
+    m.fslot = (uint32_t*)(base + p.ib_fslot);
+    m.s_cap = p.s_cap;
+    m.fcap = p.fcap;
+    m.side = p.side;
+    m.R_b = (p.side - 2) / 2;
+    m.cur = m.last = 0;
+    if (has_particles(*cfg)) {
+      int lds_max = 0;
+      if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) != hipSuccess ||
+          ibm_pass_lds_bytes(c) > (size_t)lds_max) {
+        delete h;
+        return LBM_E_SIZE;
+      }
+    }
+  }
 
   // Start at rest, density 1: shifted populations are all zero.
   hipError_t e = hipMemsetAsync(c.f_cur, 0, pop_bytes(*cfg), c.stream);
@@ -372,6 +546,14 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.np = 0;
     e = zero_particle_accumulators(c);
   }
+  if (e == hipSuccess && cfg->bc == LBM_BC_IBM) {
+    // empty support until particles are set
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+      e = hipMemsetAsync(c.ibm.bits[b], 0, words * 4, c.stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c.ibm.rank[b], 0, words * 4, c.stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c.ibm.count[b], 0, sizeof(uint32_t), c.stream);
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
   if (e != hipSuccess) {
     delete h;
@@ -387,6 +569,7 @@ int lbm_set_fields_device(lbm_ctx* h, const float* u_dev, const float* rho_dev) 
   c.step = 0;
   hipError_t e = launch_init_equilibrium(c, u_dev, rho_dev, c.f_cur);
   if (e == hipSuccess) e = zero_particle_accumulators(c);
+  if (e == hipSuccess) e = ibm_inner_momentum_init(c);
   return hip_status(e);
 }
 
@@ -479,6 +662,24 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
   if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[0], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
   if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[1], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
   if (e == hipSuccess && cfg.bc == LBM_BC_IBB) e = launch_links_build(c, c.ibb.owner[0], c.P.X[0]);
+  std::vector<double> dirs;
+  if (e == hipSuccess && cfg.bc == LBM_BC_IBM) {
+    IbmBufs& m = c.ibm;
+    m.cur = m.last = 0;
+    m.n_markers = 0;
+    if (np > 0) {
+      for (int32_t i = 1; i < np; ++i)
+        if (R[i] != R[0]) return LBM_E_ARG;  // one marker layout for all spheres
+      m.r_l = R[0] - cfg.ibm_retraction;
+      if (!(m.r_l > 1.0)) return LBM_E_ARG;
+      m.n_markers = marker_count(m.r_l);
+      m.dV = marker_volume(m.r_l, m.n_markers);
+      fibonacci_dirs(m.n_markers, dirs);
+      e = hipMemcpyAsync(m.dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, c.stream);
+    }
+    if (e == hipSuccess) e = launch_ibm_support_build(c, 0, c.P.X[0]);
+    if (e == hipSuccess) e = ibm_inner_momentum_init(c);
+  }
   if (e != hipSuccess) return LBM_E_HIP;
   return drain_errors(c);
 }
@@ -609,6 +810,8 @@ int lbm_step(lbm_ctx* h, int32_t nsteps) {
     hipError_t e;
     if (c.cfg.bc == LBM_BC_IBB)
       e = step_ibb(c);
+    else if (c.cfg.bc == LBM_BC_IBM)
+      e = step_ibm(c);
     else
       e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
     if (e != hipSuccess) return LBM_E_HIP;
@@ -623,6 +826,8 @@ int lbm_step(lbm_ctx* h, int32_t nsteps) {
 int lbm_get_fields_device(lbm_ctx* h, float* u_dev, float* rho_dev) {
   if (!h) return LBM_E_ARG;
   Ctx& c = h->c;
+  if (c.cfg.bc == LBM_BC_IBM && c.step > 0)
+    return hip_status(launch_fields_ibm(c, c.f_cur, c.ibm.last, u_dev, rho_dev));
   return hip_status(launch_fields(c, c.f_cur, extraction_force(c), u_dev, rho_dev));
 }
 

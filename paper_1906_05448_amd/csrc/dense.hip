@@ -38,21 +38,39 @@ __device__ __forceinline__ Tile tile_coords(const Dims& d) {
   return t;
 }
 
-// MODE 0: every node. MODE 1: nodes flagged in the solid bitmask are
-// skipped (interpolated bounce-back: only fluid nodes are updated, and the
-// body force acts on fluid only).
+// Immersed-boundary force lookup: node n is in the support iff its bit is
+// set; its slot is the word rank plus the set bits below it.
+struct IbView {
+  const uint32_t* bits;
+  const uint32_t* rank;
+  const float* fib;  // [3][s_cap]
+  uint32_t s_cap;
+};
+
+__device__ __forceinline__ void add_ib_force(const IbView& v, uint32_t n, float3& F) {
+  const uint32_t w = v.bits[n >> 5];
+  const uint32_t b = n & 31u;
+  if ((w >> b) & 1u) {
+    const uint32_t s = v.rank[n >> 5] + __popc(w & ((1u << b) - 1u));
+    if (s >= v.s_cap) return;  // capacity overflow is latched by the build
+    F.x += v.fib[s];
+    F.y += v.fib[(size_t)v.s_cap + s];
+    F.z += v.fib[2 * (size_t)v.s_cap + s];
+  }
+}
+
+// MODE 0: uniform force. MODE 2: plus the immersed-boundary force at the
+// support nodes.
 template <int STORE, int MODE>
 __global__ void __launch_bounds__(256)
 k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STORE>::T* __restrict__ B,
-                 Dims d, MrtRates r, float3 F, const uint32_t* __restrict__ solid, uint32_t* __restrict__ err) {
+                 Dims d, MrtRates r, float3 F0, IbView ib, uint32_t* __restrict__ err) {
   using P = Pop<STORE>;
   const Tile t = tile_coords(d);
   if (!t.live) return;
   const int x = t.x, y = t.y, z = t.z;
-  if (MODE == 1) {
-    const uint32_t n0 = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
-    if ((solid[n0 >> 5] >> (n0 & 31u)) & 1u) return;
-  }
+  float3 F = F0;
+  if (MODE == 2) add_ib_force(ib, ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x, F);
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -100,12 +118,14 @@ k_init_equilibrium(const float* __restrict__ u, const float* __restrict__ rho, t
 
 // rho and u from post-collision populations: the Guo collision adds F to the
 // momentum, so sum_i c_i f~_i = rho u + F/2 and u = (sum_i c_i f~_i - F/2)/rho.
-template <int STORE>
+template <int STORE, int MODE>
 __global__ void __launch_bounds__(256)
-k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F, float* __restrict__ u,
+k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F0, IbView ib, float* __restrict__ u,
          float* __restrict__ rho) {
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
+  float3 F = F0;
+  if (MODE == 2) add_ib_force(ib, n, F);
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -143,22 +163,50 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 // the node turns fluid.
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
+  const IbView none{nullptr, nullptr, nullptr, 0};
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
-                       c.rates, c.body_force, nullptr, c.err);
+                       c.rates, c.body_force, none, c.err);
   else
     hipLaunchKernelGGL((k_stream_collide<1, 0>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
-                       c.dims, c.rates, c.body_force, nullptr, c.err);
+                       c.dims, c.rates, c.body_force, none, c.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
+  const dim3 grid(c.dims.per_xcd * 8), block(256);
+  const int b = c.ibm.cur;
+  const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap};
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL((k_stream_collide<0, 2>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
+                       c.rates, c.body_force, ib, c.err);
+  else
+    hipLaunchKernelGGL((k_stream_collide<1, 2>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
+                       c.dims, c.rates, c.body_force, ib, c.err);
   return hipGetLastError();
 }
 
 hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho) {
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
+  const IbView none{nullptr, nullptr, nullptr, 0};
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_fields<0>, grid, block, 0, c.stream, (const float*)f, N, F, u, rho);
+    hipLaunchKernelGGL((k_fields<0, 0>), grid, block, 0, c.stream, (const float*)f, N, F, none, u, rho);
   else
-    hipLaunchKernelGGL(k_fields<1>, grid, block, 0, c.stream, (const _Float16*)f, N, F, u, rho);
+    hipLaunchKernelGGL((k_fields<1, 0>), grid, block, 0, c.stream, (const _Float16*)f, N, F, none, u, rho);
+  return hipGetLastError();
+}
+
+// Fields after an immersed-boundary step: the collision force was the body
+// force plus the spread force of support buffer `buf`.
+hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, float* rho) {
+  const uint32_t N = c.dims.N;
+  const dim3 grid((N + 255) / 256), block(256);
+  const IbView ib{c.ibm.bits[buf], c.ibm.rank[buf], c.ibm.fib[buf], c.ibm.s_cap};
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL((k_fields<0, 2>), grid, block, 0, c.stream, (const float*)f, N, c.body_force, ib, u, rho);
+  else
+    hipLaunchKernelGGL((k_fields<1, 2>), grid, block, 0, c.stream, (const _Float16*)f, N, c.body_force, ib, u, rho);
   return hipGetLastError();
 }
 

@@ -108,6 +108,20 @@ __device__ __forceinline__ void node_coords(uint32_t n, int nx, int ny, int& x, 
   z = (int)(r / (uint32_t)ny);
 }
 
+// Kempe et al. solid fraction of the unit cell around a node at offset d
+// from a sphere centre: sum over the 8 corners of (-phi) H(-phi) / sum |phi|,
+// phi = |corner - X| - r (corners in the order (-,-,-), (-,-,+), ...).
+__device__ __forceinline__ double kempe_alpha(double dx, double dy, double dz, double r) {
+  double num = 0.0, den = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    const double sx = (c & 4) ? 0.5 : -0.5, sy = (c & 2) ? 0.5 : -0.5, sz = (c & 1) ? 0.5 : -0.5;
+    const double phi = sqrt(dist2(dx + sx, dy + sy, dz + sz)) - r;
+    num += phi < 0.0 ? -phi : 0.0;
+    den += fabs(phi);
+  }
+  return den > 0.0 ? num / den : 0.0;
+}
+
 // Exclusive prefix sum over a block of BLOCK threads (multiple of 64).
 // Every thread must call it. Returns the thread's offset; *total gets the sum.
 template <int BLOCK>

@@ -1,0 +1,553 @@
+// ibm.hip - immersed boundary method on moving spheres (Sec. 2.1, Sec. 3.1):
+// Peskin 4-point delta (Peskin 2002), multi-direct forcing with the
+// prediction plus ibm_iters passes, and the Kempe et al. (2012) inner-fluid
+// inertia, FP64 per-particle sums.
+//
+// Step structure (support of step n built at the end of step n-1):
+//   prepass   pull the 19 populations at every support node: rho and
+//             u* = (sum c f + F_body/2) / rho into the slot arrays
+//   passes    one workgroup per sphere stages its forcing support (union
+//             of its marker stencils) in LDS: u = u* + f_IB/(2 rho);
+//             markers interpolate U_l, dF_l = 2 (U_d - U_l) (reference
+//             density 1, half-force velocity), then spread dF_l delta dV
+//             into LDS accumulators with LDS float atomics, one component
+//             at a time; the result goes back to the slot force array with
+//             plain adds, or global atomics at nodes another sphere's
+//             support shares. All markers of a pass read the same u
+//             (one launch per pass).
+//   kempe     sum alpha u and sum alpha (x - X) x u over the cells with
+//             solid fraction alpha > 0, per sphere, in FP64
+//   dense     the fused stream + collide adds f_IB at support nodes
+//   build     support of step n+1 from the new centres
+// Marker positions are X + r_L n_k in FP64 with the box-local stencil base
+// floor(X_l) - 1, so the stencil nodes match an FP64 reference.
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kAlphaReach = 0.8661;  // > sqrt(3)/2: cells with any corner inside
+
+__device__ __forceinline__ float peskin(float r) {
+  const float a = fabsf(r);
+  if (a <= 1.0f) return (3.0f - 2.0f * a + sqrtf(1.0f + 4.0f * a - 4.0f * a * a)) * 0.125f;
+  if (a < 2.0f) return (5.0f - 2.0f * a - sqrtf(fmaxf(-7.0f + 12.0f * a - 4.0f * a * a, 0.0f))) * 0.125f;
+  return 0.0f;
+}
+
+// Box of a sphere: floor(X) - R_b .. floor(X) + R_b + 1 per axis.
+__device__ __forceinline__ void ibm_box_lo(const double* X, int R_b, int lo[3]) {
+  for (int k = 0; k < 3; ++k) lo[k] = (int)floor(X[k]) - R_b;
+}
+
+// Marker l of a sphere: stencil base (box-local, 0 .. side-4) and the 4x3
+// Peskin weights.
+struct Stencil {
+  int bx, by, bz;
+  float wx[4], wy[4], wz[4];
+};
+
+__device__ __forceinline__ void marker_stencil(const double* X, const double* dir, double r_l, const int lo[3],
+                                               Stencil& s) {
+  double xl[3];
+  int b[3];
+  for (int k = 0; k < 3; ++k) {
+    xl[k] = X[k] + r_l * dir[k];
+    b[k] = (int)floor(xl[k]) - 1;
+  }
+  for (int j = 0; j < 4; ++j) {
+    s.wx[j] = peskin((float)(xl[0] - (double)(b[0] + j)));
+    s.wy[j] = peskin((float)(xl[1] - (double)(b[1] + j)));
+    s.wz[j] = peskin((float)(xl[2] - (double)(b[2] + j)));
+  }
+  s.bx = b[0] - lo[0];
+  s.by = b[1] - lo[1];
+  s.bz = b[2] - lo[2];
+}
+
+// ---------------------------------------------------------------- build --
+// Per sphere: forcing rows (marker stencils) and the full support (stencils
+// plus Kempe cells) in LDS, then the global support bits and the
+// shared-node bits.
+__global__ void __launch_bounds__(kBlock)
+k_ibm_mark(const double* __restrict__ X, const double* __restrict__ rad, const double* __restrict__ dirs, int nmk,
+           double r_l, int R_b, int side, Dims d, uint32_t* __restrict__ bits, uint32_t* __restrict__ shared,
+           uint32_t* __restrict__ rowbits_out, uint32_t* __restrict__ fcount, uint32_t fcap,
+           uint32_t* __restrict__ err) {
+  extern __shared__ uint32_t lds[];
+  const int rows = side * side;
+  uint32_t* fb = lds;          // forcing rows
+  uint32_t* ab = lds + rows;   // Kempe-cell rows
+  const int p = blockIdx.x;
+  const double* Xp = X + 3 * p;
+  const double r = rad[p];
+  int lo[3];
+  ibm_box_lo(Xp, R_b, lo);
+  for (int i = threadIdx.x; i < rows; i += kBlock) fb[i] = ab[i] = 0u;
+  __syncthreads();
+  for (int l = threadIdx.x; l < nmk; l += kBlock) {
+    Stencil s;
+    marker_stencil(Xp, dirs + 3 * l, r_l, lo, s);
+    const uint32_t m = 0xFu << s.bx;
+    for (int jz = 0; jz < 4; ++jz)
+      for (int jy = 0; jy < 4; ++jy) atomicOr(&fb[(s.by + jy) + side * (s.bz + jz)], m);
+  }
+  const double ra = r + kAlphaReach;
+  const double ra2 = ra * ra;
+  for (int rb = 0; rb < rows; rb += kBlock / 32) {
+    const int row = rb + (threadIdx.x >> 5), lx = threadIdx.x & 31;
+    if (row >= rows || lx >= side) continue;
+    const int ly = row % side, lz = row / side;
+    const int x = wrap1(lo[0] + lx, d.nx), y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+    const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
+                            min_image((double)z - Xp[2], d.nz));
+    if (d2 < ra2) atomicOr(&ab[row], 1u << lx);
+  }
+  __syncthreads();
+  uint32_t cnt = 0;
+  for (int row = threadIdx.x; row < rows; row += kBlock) {
+    const uint32_t f = fb[row];
+    rowbits_out[(size_t)p * rows + row] = f;
+    cnt += __popc(f);
+    uint32_t m = f | ab[row];
+    if (!m) continue;
+    const int ly = row % side, lz = row / side;
+    const int y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+    uint32_t word = 0xFFFFFFFFu, wm = 0u;
+    while (m) {
+      const int lx = __ffs(m) - 1;
+      m &= m - 1u;
+      const uint32_t n = node_index(wrap1(lo[0] + lx, d.nx), y, z, d.nx, d.ny);
+      if ((n >> 5) != word) {
+        if (wm) {
+          const uint32_t old = atomicOr(bits + word, wm);
+          if (old & wm) atomicOr(shared + word, old & wm);
+        }
+        word = n >> 5;
+        wm = 0u;
+      }
+      wm |= 1u << (n & 31u);
+    }
+    if (wm) {
+      const uint32_t old = atomicOr(bits + word, wm);
+      if (old & wm) atomicOr(shared + word, old & wm);
+    }
+  }
+  const double tot = block_sum<kBlock>((double)cnt);
+  if (threadIdx.x == 0) {
+    uint32_t t = (uint32_t)tot;
+    if (t > fcap) {
+      atomicOr(err, kErrCapacity);
+      t = fcap;
+    }
+    fcount[p] = t;
+  }
+}
+
+// Exclusive rank of the support words: per-block partial scans, a scan of
+// the block sums, then the offsets plus the slot -> node list.
+constexpr int kScanPer = 4;  // words per thread
+constexpr int kScanWords = kBlock * kScanPer;
+
+__global__ void __launch_bounds__(kBlock) k_scan_block(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                      uint32_t* __restrict__ rank, uint32_t* __restrict__ block_sums) {
+  const uint32_t w0 = blockIdx.x * kScanWords + threadIdx.x * kScanPer;
+  uint32_t c[kScanPer], s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    c[k] = (w0 + k < nwords) ? __popc(bits[w0 + k]) : 0u;
+    s += c[k];
+  }
+  uint32_t total;
+  uint32_t off = block_exclusive_scan<kBlock>(s, &total);
+  for (int k = 0; k < kScanPer; ++k) {
+    if (w0 + k < nwords) rank[w0 + k] = off;
+    off += c[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* __restrict__ block_sums, uint32_t nblocks,
+                                                   uint32_t* __restrict__ count) {
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nblocks; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t v = i < nblocks ? block_sums[i] : 0u;
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan<1024>(v, &total);
+    if (i < nblocks) block_sums[i] = carry + off;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_add(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                    uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ block_sums,
+                                                    uint32_t* __restrict__ list, uint32_t s_cap,
+                                                    uint32_t* __restrict__ err) {
+  const uint32_t w0 = blockIdx.x * kScanWords + threadIdx.x * kScanPer;
+  const uint32_t add = block_sums[blockIdx.x];
+  for (int k = 0; k < kScanPer; ++k) {
+    const uint32_t w = w0 + k;
+    if (w >= nwords) break;
+    const uint32_t rk = rank[w] + add;
+    rank[w] = rk;
+    uint32_t m = bits[w], j = 0;
+    while (m) {
+      const int b = __ffs(m) - 1;
+      m &= m - 1u;
+      const uint32_t slot = rk + j++;
+      if (slot < s_cap)
+        list[slot] = w * 32u + (uint32_t)b;
+      else
+        atomicOr(err, kErrCapacity);
+    }
+  }
+}
+
+__device__ __forceinline__ bool support_slot(const uint32_t* bits, const uint32_t* rank, uint32_t n, uint32_t& slot) {
+  const uint32_t w = bits[n >> 5];
+  const uint32_t b = n & 31u;
+  if (!((w >> b) & 1u)) return false;
+  slot = rank[n >> 5] + __popc(w & ((1u << b) - 1u));
+  return true;
+}
+
+// Per sphere: global slot of every forcing-support node, in box raster order.
+__global__ void __launch_bounds__(kBlock)
+k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint32_t* __restrict__ bits,
+            const uint32_t* __restrict__ rank, const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount,
+            uint32_t fcap, uint32_t* __restrict__ fslot) {
+  const int rows = side * side;
+  const int p = blockIdx.x;
+  int lo[3];
+  ibm_box_lo(X + 3 * p, R_b, lo);
+  const uint32_t cap = fcount[p];
+  uint32_t base = 0;
+  for (int r0 = 0; r0 < rows; r0 += kBlock) {
+    const int row = r0 + threadIdx.x;
+    uint32_t m = row < rows ? rowbits[(size_t)p * rows + row] : 0u;
+    uint32_t total;
+    uint32_t j = base + block_exclusive_scan<kBlock>(__popc(m), &total);
+    if (m) {
+      const int ly = row % side, lz = row / side;
+      const int y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+      while (m) {
+        const int lx = __ffs(m) - 1;
+        m &= m - 1u;
+        uint32_t slot = 0;
+        (void)support_slot(bits, rank, node_index(wrap1(lo[0] + lx, d.nx), y, z, d.nx, d.ny), slot);
+        if (j < cap) fslot[(size_t)p * fcap + j] = slot;
+        ++j;
+      }
+    }
+    base += total;
+  }
+}
+
+// -------------------------------------------------------------- prepass --
+template <int STORE>
+__global__ void __launch_bounds__(256)
+k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F, const uint32_t* __restrict__ list,
+              const uint32_t* __restrict__ count, uint32_t s_cap, float4* __restrict__ us, float* __restrict__ fib) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= *count || s >= s_cap) return;
+  const uint32_t n = list[s];
+  int x, y, z;
+  node_coords(n, d.nx, d.ny, x, y, z);
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const uint32_t src = node_index(wrap1(x - cx_of(i), d.nx), wrap1(y - cy_of(i), d.ny), wrap1(z - cz_of(i), d.nz),
+                                    d.nx, d.ny);
+    const float g = Pop<STORE>::load(A + (size_t)i * d.N + src);
+    drho += g;
+    jx += cx_of(i) * g;
+    jy += cy_of(i) * g;
+    jz += cz_of(i) * g;
+  }
+  const float rho = 1.0f + drho;
+  us[s] = make_float4((jx + 0.5f * F.x) / rho, (jy + 0.5f * F.y) / rho, (jz + 0.5f * F.z) / rho, rho);
+  fib[s] = 0.0f;
+  fib[(size_t)s_cap + s] = 0.0f;
+  fib[2 * (size_t)s_cap + s] = 0.0f;
+}
+
+// --------------------------------------------------------------- passes --
+// LDS: rows u32 (forcing row bits), rows u32 (row prefix), fcap float3
+// (velocity), fcap float (spread accumulator), fcap/32 u32 (shared flags).
+template <int MPT>
+__global__ void __launch_bounds__(kBlock)
+k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om,
+           const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
+           const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
+           const uint32_t* __restrict__ fslot, const uint32_t* __restrict__ list, const uint32_t* __restrict__ shared,
+           const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap, double* __restrict__ F_ib,
+           double* __restrict__ T_ib, int first) {
+  extern __shared__ uint32_t lds[];
+  const int rows = side * side;
+  uint32_t* rb = lds;
+  uint32_t* rp = rb + rows;
+  float* uj = (float*)(rp + rows);
+  float* dj = uj + 3 * fcap;
+  uint32_t* sh = (uint32_t*)(dj + fcap);
+  const int p = blockIdx.x;
+  const double* Xp = X + 3 * p;
+  int lo[3];
+  ibm_box_lo(Xp, R_b, lo);
+  const uint32_t cnt = fcount[p];
+  // row bits and their exclusive prefix (box raster order = slot list order)
+  uint32_t base = 0;
+  for (int r0 = 0; r0 < rows; r0 += kBlock) {
+    const int row = r0 + threadIdx.x;
+    const uint32_t m = row < rows ? rowbits[(size_t)p * rows + row] : 0u;
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan<kBlock>(__popc(m), &total);
+    if (row < rows) {
+      rb[row] = m;
+      rp[row] = base + off;
+    }
+    base += total;
+  }
+  // A forcing support beyond the LDS capacity was latched as an error when it
+  // was built; skip the sphere rather than index past the buffers.
+  if (base > fcap || base != cnt) return;
+  for (uint32_t j = threadIdx.x; j < (fcap + 31) / 32; j += kBlock) sh[j] = 0u;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+    const uint32_t s = fslot[(size_t)p * fcap + j];
+    if (s >= s_cap) {
+      uj[3 * j] = uj[3 * j + 1] = uj[3 * j + 2] = 0.0f;
+      continue;
+    }
+    const float4 v = us[s];
+    const float h = 0.5f / v.w;
+    uj[3 * j] = v.x + fib[s] * h;
+    uj[3 * j + 1] = v.y + fib[(size_t)s_cap + s] * h;
+    uj[3 * j + 2] = v.z + fib[2 * (size_t)s_cap + s] * h;
+    const uint32_t n = list[s];
+    if ((shared[n >> 5] >> (n & 31u)) & 1u) atomicOr(&sh[j >> 5], 1u << (j & 31u));
+  }
+  __syncthreads();
+  // interpolate, force
+  const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
+  const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
+  Stencil st[MPT];
+  float dF[MPT][3];
+  double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    const int l = threadIdx.x + m * kBlock;
+    dF[m][0] = dF[m][1] = dF[m][2] = 0.0f;
+    if (l >= nmk) continue;
+    marker_stencil(Xp, dirs + 3 * l, r_l, lo, st[m]);
+    float Ul[3] = {0.0f, 0.0f, 0.0f};
+    for (int jz = 0; jz < 4; ++jz)
+      for (int jy = 0; jy < 4; ++jy) {
+        const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+        const uint32_t bitsr = rb[row];
+        const uint32_t j0 = rp[row] + __popc(bitsr & ((1u << st[m].bx) - 1u));
+        const float wyz = st[m].wy[jy] * st[m].wz[jz];
+        for (int jx = 0; jx < 4; ++jx) {
+          const float w = st[m].wx[jx] * wyz;
+          const uint32_t j = j0 + jx;
+          Ul[0] += w * uj[3 * j];
+          Ul[1] += w * uj[3 * j + 1];
+          Ul[2] += w * uj[3 * j + 2];
+        }
+      }
+    const double arm[3] = {r_l * dirs[3 * l], r_l * dirs[3 * l + 1], r_l * dirs[3 * l + 2]};
+    const double Ud[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
+                          Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
+    for (int k = 0; k < 3; ++k) dF[m][k] = 2.0f * ((float)Ud[k] - Ul[k]);
+    const double f[3] = {(double)dF[m][0] * dV, (double)dF[m][1] * dV, (double)dF[m][2] * dV};
+    // force and torque on the particle: minus the force on the fluid
+    for (int k = 0; k < 3; ++k) Fs[k] -= f[k];
+    Ts[0] -= arm[1] * f[2] - arm[2] * f[1];
+    Ts[1] -= arm[2] * f[0] - arm[0] * f[2];
+    Ts[2] -= arm[0] * f[1] - arm[1] * f[0];
+  }
+  // spread, one component at a time
+  const float dVf = (float)dV;
+  for (int k = 0; k < 3; ++k) {
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) dj[j] = 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MPT; ++m) {
+      const int l = threadIdx.x + m * kBlock;
+      if (l >= nmk) continue;
+      const float a = dF[m][k] * dVf;
+      for (int jz = 0; jz < 4; ++jz)
+        for (int jy = 0; jy < 4; ++jy) {
+          const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+          const uint32_t j0 = rp[row] + __popc(rb[row] & ((1u << st[m].bx) - 1u));
+          const float ayz = a * st[m].wy[jy] * st[m].wz[jz];
+          for (int jx = 0; jx < 4; ++jx) atomicAdd(&dj[j0 + jx], ayz * st[m].wx[jx]);
+        }
+    }
+    __syncthreads();
+    float* fk = fib + (size_t)k * s_cap;
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+      const uint32_t s = fslot[(size_t)p * fcap + j];
+      if (s >= s_cap) continue;
+      const float v = dj[j];
+      if ((sh[j >> 5] >> (j & 31u)) & 1u)
+        atomicAdd(fk + s, v);
+      else
+        fk[s] += v;
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double fs = block_sum<kBlock>(Fs[k]);
+    const double ts = block_sum<kBlock>(Ts[k]);
+    if (threadIdx.x == 0) {
+      F_ib[3 * p + k] = (first ? 0.0 : F_ib[3 * p + k]) + fs;
+      T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + ts;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kempe --
+// Sum alpha u and sum alpha (x - X) x u per sphere; u from the support
+// slots (u* + f_IB / (2 rho)) or, before the first step, a dense field.
+template <bool DENSE>
+__global__ void __launch_bounds__(kBlock)
+k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, const uint32_t* __restrict__ bits,
+        const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float* __restrict__ fib,
+        uint32_t s_cap, const float* __restrict__ ufield, double* __restrict__ Iu, double* __restrict__ IL) {
+  const int p = blockIdx.x;
+  const double* Xp = X + 3 * p;
+  const double r = rad[p];
+  const Box b = make_box(Xp, r + 1.0);
+  const BoxRows br = box_rows(b);
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
+    int x, y, z;
+    if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    const double dx = min_image((double)x - Xp[0], d.nx), dy = min_image((double)y - Xp[1], d.ny),
+                 dz = min_image((double)z - Xp[2], d.nz);
+    const double a = kempe_alpha(dx, dy, dz, r);
+    if (a <= 0.0) continue;
+    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    double u[3];
+    if (DENSE) {
+      u[0] = ufield[n];
+      u[1] = ufield[(size_t)d.N + n];
+      u[2] = ufield[2 * (size_t)d.N + n];
+    } else {
+      uint32_t slot;
+      if (!support_slot(bits, rank, n, slot) || slot >= s_cap) continue;
+      const float4 v = us[slot];
+      const float h = 0.5f / v.w;
+      u[0] = (double)(v.x + fib[slot] * h);
+      u[1] = (double)(v.y + fib[(size_t)s_cap + slot] * h);
+      u[2] = (double)(v.z + fib[2 * (size_t)s_cap + slot] * h);
+    }
+    s[0] += a * u[0];
+    s[1] += a * u[1];
+    s[2] += a * u[2];
+    s[3] += a * (dy * u[2] - dz * u[1]);
+    s[4] += a * (dz * u[0] - dx * u[2]);
+    s[5] += a * (dx * u[1] - dy * u[0]);
+  }
+  for (int k = 0; k < 6; ++k) {
+    const double t = block_sum<kBlock>(s[k]);
+    if (threadIdx.x == 0) {
+      if (k < 3)
+        Iu[3 * p + k] = t;
+      else
+        IL[3 * p + k - 3] = t;
+    }
+  }
+}
+
+size_t pass_lds_bytes(const Ctx& c) {
+  const size_t rows = (size_t)c.ibm.side * c.ibm.side;
+  return rows * 8 + (size_t)c.ibm.fcap * 16 + ((c.ibm.fcap + 31) / 32) * 4;
+}
+
+}  // namespace
+
+size_t ibm_pass_lds_bytes(const Ctx& c) { return pass_lds_bytes(c); }
+
+hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
+  const uint32_t words = mask_words(c.dims.N);
+  IbmBufs& m = c.ibm;
+  hipError_t e = hipMemsetAsync(m.bits[buf], 0, (size_t)words * 4, c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m.shared, 0, (size_t)words * 4, c.stream);
+  if (e != hipSuccess) return e;
+  if (c.np > 0) {
+    const size_t lds = (size_t)m.side * m.side * 8;
+    hipLaunchKernelGGL(k_ibm_mark, dim3(c.np), dim3(kBlock), lds, c.stream, X, c.P.r, m.dirs, m.n_markers, m.r_l,
+                       m.R_b, m.side, c.dims, m.bits[buf], m.shared, m.rowbits, m.fcount, m.fcap, c.err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint32_t nblk = (words + kScanWords - 1) / kScanWords;
+  hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kBlock), 0, c.stream, m.bits[buf], words, m.rank[buf],
+                     m.block_sums);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c.stream, m.block_sums, nblk, m.count[buf]);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kBlock), 0, c.stream, m.bits[buf], words, m.rank[buf],
+                     m.block_sums, m.list, m.s_cap, c.err);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (c.np > 0) {
+    hipLaunchKernelGGL(k_ibm_slots, dim3(c.np), dim3(kBlock), 0, c.stream, X, m.R_b, m.side, c.dims, m.bits[buf],
+                       m.rank[buf], m.rowbits, m.fcount, m.fcap, m.fslot);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_ibm_prepass(const Ctx& c, const void* A) {
+  const IbmBufs& m = c.ibm;
+  const dim3 grid((m.s_cap + 255) / 256);
+  if (c.cfg.store == LBM_STORE_F32)
+    hipLaunchKernelGGL(k_ibm_prepass<0>, grid, dim3(256), 0, c.stream, (const float*)A, c.dims, c.body_force, m.list,
+                       m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
+  else
+    hipLaunchKernelGGL(k_ibm_prepass<1>, grid, dim3(256), 0, c.stream, (const _Float16*)A, c.dims, c.body_force,
+                       m.list, m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
+  return hipGetLastError();
+}
+
+hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* U, const double* Om) {
+  if (c.np <= 0) return hipSuccess;
+  const IbmBufs& m = c.ibm;
+  const size_t lds = pass_lds_bytes(c);
+  const int passes = 1 + c.cfg.ibm_iters;
+  for (int k = 0; k < passes; ++k) {
+    if (m.n_markers <= 4 * kBlock)
+      hipLaunchKernelGGL(k_ibm_pass<4>, dim3(c.np), dim3(kBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
+                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
+                         m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_ibm_pass<8>, dim3(c.np), dim3(kBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
+                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
+                         m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_ibm_kempe(const Ctx& c, const double* X, double* Iu, double* IL) {
+  if (c.np <= 0) return hipSuccess;
+  const IbmBufs& m = c.ibm;
+  hipLaunchKernelGGL(k_kempe<false>, dim3(c.np), dim3(kBlock), 0, c.stream, X, c.P.r, c.dims, m.bits[m.cur],
+                     m.rank[m.cur], m.us, m.fib[m.cur], m.s_cap, nullptr, Iu, IL);
+  return hipGetLastError();
+}
+
+hipError_t launch_kempe_dense(const Ctx& c, const float* u, const double* X, double* Iu, double* IL) {
+  if (c.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kempe<true>, dim3(c.np), dim3(kBlock), 0, c.stream, X, c.P.r, c.dims, nullptr, nullptr,
+                     nullptr, nullptr, c.ibm.s_cap, u, Iu, IL);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -133,6 +133,36 @@ struct IbbBufs {
   uint32_t wl_count;
 };
 
+// Immersed boundary support. The support set S (marker stencils plus the
+// cells of the Kempe integrals) is a bitmask with a per-word exclusive rank,
+// so node n in S has slot rank[n >> 5] + popcount(bits[n >> 5] below n).
+// Slot arrays hold the prepass density/velocity and the spread force. Bits,
+// rank, count and force are double-buffered: [cur] is the support of step n,
+// [1-cur] that of the last completed collision (field extraction).
+struct IbmBufs {
+  uint32_t* bits[2];     // [mask_words]
+  uint32_t* rank[2];     // [mask_words]
+  uint32_t* count[2];    // [1] support size
+  float* fib[2];         // [3][S_cap] spread force per slot
+  uint32_t* shared;      // [mask_words] nodes in more than one sphere's support
+  uint32_t* list;        // [S_cap] node of each slot (current support)
+  float4* us;            // [S_cap] (u*, rho) from the prepass
+  uint32_t* block_sums;  // scan scratch
+  double* dirs;          // [n_markers][3] unit marker directions (Fibonacci)
+  uint32_t* rowbits;     // [P][rows] per-sphere forcing-support rows (box-local)
+  uint32_t* fcount;      // [P] forcing-support size per sphere
+  uint32_t* fslot;       // [P][fcap] global slot of each forcing-support node
+  uint32_t s_cap;        // slots reserved
+  uint32_t fcap;         // forcing-support nodes reserved per sphere
+  int n_markers;         // markers per sphere
+  double r_l;            // marker radius r - r_d
+  double dV;             // marker volume
+  int R_b;               // box half-width: box is floor(X) - R_b .. + R_b + 1
+  int side;              // 2 R_b + 2 (<= 32)
+  int cur;               // support of the next collision
+  int last;              // support used by the last collision
+};
+
 struct Ctx {
   lbm_config cfg;
   hipStream_t stream;
@@ -155,6 +185,7 @@ struct Ctx {
   uint32_t link_cap;     // links reserved per particle
   ParticleBufs P;
   IbbBufs ibb;
+  IbmBufs ibm;
   double max_radius_set; // largest radius of the particles set
 };
 
@@ -192,6 +223,16 @@ hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, b
 hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double* U, const double* Om);
 hipError_t launch_cover_refill(const Ctx& c, void* B, const uint32_t* owner_old, const uint32_t* owner_new,
                                const double* Xold, const double* Xnew, const double* Unew, const double* Omnew);
+
+// Immersed boundary (ibm.hip).
+size_t ibm_pass_lds_bytes(const Ctx& c);
+hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X);
+hipError_t launch_ibm_prepass(const Ctx& c, const void* A);
+hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* U, const double* Om);
+hipError_t launch_ibm_kempe(const Ctx& c, const double* X, double* Iu, double* IL);
+hipError_t launch_kempe_dense(const Ctx& c, const float* u, const double* X, double* Iu, double* IL);
+hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B);
+hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, float* rho);
 
 // Particles (particles.hip).
 hipError_t launch_particle_update(const Ctx& c);

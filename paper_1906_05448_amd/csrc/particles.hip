@@ -106,20 +106,6 @@ k_particle_update(int np, int motion, int bc, Dims d, const double* __restrict__
 
 }  // namespace
 
-// Kempe solid fraction of the unit cell around a node at offset d from the
-// centre: sum over the 8 corners of (-phi) H(-phi) / sum |phi|,
-// phi = |corner - X| - r.
-__device__ double kempe_alpha(double dx, double dy, double dz, double r) {
-  double num = 0.0, den = 0.0;
-  for (int c = 0; c < 8; ++c) {
-    const double sx = (c & 4) ? 0.5 : -0.5, sy = (c & 2) ? 0.5 : -0.5, sz = (c & 1) ? 0.5 : -0.5;
-    const double phi = sqrt(dist2(dx + sx, dy + sy, dz + sz)) - r;
-    num += phi < 0.0 ? -phi : 0.0;
-    den += fabs(phi);
-  }
-  return den > 0.0 ? num / den : 0.0;
-}
-
 namespace {
 
 __global__ void __launch_bounds__(256)
