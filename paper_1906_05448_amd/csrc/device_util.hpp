@@ -112,6 +112,12 @@ __device__ __forceinline__ void node_coords(uint32_t n, int nx, int ny, int& x, 
 // from a sphere centre: sum over the 8 corners of (-phi) H(-phi) / sum |phi|,
 // phi = |corner - X| - r (corners in the order (-,-,-), (-,-,+), ...).
 __device__ __forceinline__ double kempe_alpha(double dx, double dy, double dz, double r) {
+  // Away from the surface every corner is on one side: the formula gives
+  // exactly 1 (num and den are the same sum) or exactly 0.
+  const double d2 = dist2(dx, dy, dz);
+  const double ri = r - 0.8661, ro = r + 0.8661;  // 0.8661 > sqrt(3)/2
+  if (ri > 0.0 && d2 < ri * ri) return 1.0;
+  if (d2 >= ro * ro) return 0.0;
   double num = 0.0, den = 0.0;
   for (int c = 0; c < 8; ++c) {
     const double sx = (c & 4) ? 0.5 : -0.5, sy = (c & 2) ? 0.5 : -0.5, sz = (c & 1) ? 0.5 : -0.5;
@@ -148,21 +154,71 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return base + incl - v;
 }
 
-// Sum of a double over the block in a fixed tree order (deterministic for a
-// given block size). Every thread must call it; all get the result.
+// Sum of a double over the block in a fixed order (butterfly within each
+// wavefront, then the wavefront partials in index order), so the result is
+// deterministic for a given block size. Every thread must call it; all get
+// the result.
 template <int BLOCK>
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double buf[BLOCK];
-  buf[threadIdx.x] = v;
-  __syncthreads();
+  __shared__ double part[BLOCK / 64];
 #pragma unroll
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) buf[threadIdx.x] += buf[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = buf[0];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / 64; ++w) r += part[w];
   __syncthreads();
   return r;
+}
+
+// N independent block sums at once (fewer barriers).
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N]) {
+  __shared__ double part[N][BLOCK / 64];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) part[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) r += part[k][w];
+    v[k] = r;
+  }
+  __syncthreads();
+}
+
+// N block sums whose results only thread 0 needs: lanes 0 .. N-1 of the first
+// wavefront add the wavefront partials in index order, so the result matches
+// block_sum_n bit for bit. Every thread must call it.
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_sum_first(double (&v)[N]) {
+  static_assert(N <= 64, "one lane per sum");
+  __shared__ double part[N][BLOCK / 64];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) part[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x < N ? (int)threadIdx.x : 0;
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) r += part[k][w];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = __shfl(r, i, 64);
+  }
 }
 
 }  // namespace lbm

@@ -10,11 +10,10 @@
 //             of its marker stencils) in LDS: u = u* + f_IB/(2 rho);
 //             markers interpolate U_l, dF_l = 2 (U_d - U_l) (reference
 //             density 1, half-force velocity), then spread dF_l delta dV
-//             into LDS accumulators with LDS float atomics, one component
-//             at a time; the result goes back to the slot force array with
-//             plain adds, or global atomics at nodes another sphere's
-//             support shares. All markers of a pass read the same u
-//             (one launch per pass).
+//             into separate LDS accumulators with LDS float atomics; the
+//             result goes back to the slot force array with plain adds, or
+//             global atomics at nodes another sphere's support shares. All
+//             markers of a pass read the same u (one launch per pass).
 //   kempe     sum alpha u and sum alpha (x - X) x u over the cells with
 //             solid fraction alpha > 0, per sphere, in FP64
 //   dense     the fused stream + collide adds f_IB at support nodes
@@ -277,10 +276,31 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F, co
 }
 
 // --------------------------------------------------------------- passes --
-// LDS: rows u32 (forcing row bits), rows u32 (row prefix), fcap float3
-// (velocity), fcap float (spread accumulator), fcap/32 u32 (shared flags).
+// One 1024-thread workgroup per sphere, MPT markers per thread.
+// LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 24
+// bytes holding first the staged velocities (float3 per node) and, once every
+// marker has interpolated, the spread sums (3 x int64 per node), then fcap/32
+// u32 (shared flags).
+//
+// The spread sums are 64-bit fixed point in units of 2^-50: LDS integer
+// atomics run at about the rate of plain LDS accesses, while LDS float
+// atomics measured about 25 times slower on gfx950, and integer sums are
+// exact, so a node's total does not depend on the order in which markers
+// land. |sum| < 2^13 per node and pass holds with a wide margin: the weights
+// a node receives sum to O(1) and |dF| < 1.4 below the Mach limit that the
+// collision kernel latches as unstable.
+constexpr int kPassBlock = 1024;
+constexpr int kStage = 5;  // support nodes per thread per staging round
+constexpr double kFixScale = 0x1p50;
+constexpr double kFixUnit = 0x1p-50;
+
+__device__ __forceinline__ unsigned long long to_fix(float v) {
+  return (unsigned long long)(long long)((double)v * kFixScale);
+}
+__device__ __forceinline__ float from_fix(unsigned long long a) { return (float)((double)(long long)a * kFixUnit); }
+
 template <int MPT>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kPassBlock)
 k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om,
            const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
@@ -292,20 +312,21 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   uint32_t* rb = lds;
   uint32_t* rp = rb + rows;
   float* uj = (float*)(rp + rows);
-  float* dj = uj + 3 * fcap;
-  uint32_t* sh = (uint32_t*)(dj + fcap);
+  unsigned long long* acc = (unsigned long long*)(rp + rows);  // rows * 8 bytes in: 8-byte aligned
+  uint32_t* sh = (uint32_t*)(acc + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
+  const uint32_t* slots = fslot + (size_t)p * fcap;
   int lo[3];
   ibm_box_lo(Xp, R_b, lo);
   const uint32_t cnt = fcount[p];
   // row bits and their exclusive prefix (box raster order = slot list order)
   uint32_t base = 0;
-  for (int r0 = 0; r0 < rows; r0 += kBlock) {
+  for (int r0 = 0; r0 < rows; r0 += kPassBlock) {
     const int row = r0 + threadIdx.x;
     const uint32_t m = row < rows ? rowbits[(size_t)p * rows + row] : 0u;
     uint32_t total;
-    const uint32_t off = block_exclusive_scan<kBlock>(__popc(m), &total);
+    const uint32_t off = block_exclusive_scan<kPassBlock>(__popc(m), &total);
     if (row < rows) {
       rb[row] = m;
       rp[row] = base + off;
@@ -315,98 +336,146 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   // A forcing support beyond the LDS capacity was latched as an error when it
   // was built; skip the sphere rather than index past the buffers.
   if (base > fcap || base != cnt) return;
-  for (uint32_t j = threadIdx.x; j < (fcap + 31) / 32; j += kBlock) sh[j] = 0u;
+  for (uint32_t j = threadIdx.x; j < (fcap + 31) / 32; j += kPassBlock) sh[j] = 0u;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
-    const uint32_t s = fslot[(size_t)p * fcap + j];
-    if (s >= s_cap) {
-      uj[3 * j] = uj[3 * j + 1] = uj[3 * j + 2] = 0.0f;
-      continue;
+  // Stage u = u* + f_IB / (2 rho): all loads of a round are issued before
+  // any is used, so a round costs three dependent trips to memory.
+  for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
+    uint32_t s[kStage], n[kStage];
+    float4 v[kStage];
+    float f[kStage][3];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
     }
-    const float4 v = us[s];
-    const float h = 0.5f / v.w;
-    uj[3 * j] = v.x + fib[s] * h;
-    uj[3 * j + 1] = v.y + fib[(size_t)s_cap + s] * h;
-    uj[3 * j + 2] = v.z + fib[2 * (size_t)s_cap + s] * h;
-    const uint32_t n = list[s];
-    if ((shared[n >> 5] >> (n & 31u)) & 1u) atomicOr(&sh[j >> 5], 1u << (j & 31u));
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      if (s[i] < s_cap) {
+        v[i] = us[s[i]];
+        n[i] = list[s[i]];
+        for (int k = 0; k < 3; ++k) f[i][k] = fib[(size_t)k * s_cap + s[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      if (j >= cnt) continue;
+      if (s[i] >= s_cap) {
+        uj[3 * j] = uj[3 * j + 1] = uj[3 * j + 2] = 0.0f;
+        continue;
+      }
+      const float h = 0.5f / v[i].w;
+      uj[3 * j] = v[i].x + f[i][0] * h;
+      uj[3 * j + 1] = v[i].y + f[i][1] * h;
+      uj[3 * j + 2] = v[i].z + f[i][2] * h;
+      if ((shared[n[i] >> 5] >> (n[i] & 31u)) & 1u) atomicOr(&sh[j >> 5], 1u << (j & 31u));
+    }
   }
   __syncthreads();
-  // interpolate, force
+  // interpolate and form the marker forces; every marker reads u before the
+  // accumulators replace it
   const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
   const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
-  Stencil st[MPT];
+  const float dVf = (float)dV;
+  double fsum[6] = {0, 0, 0, 0, 0, 0};  // force and torque on the particle
   float dF[MPT][3];
-  double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
+  Stencil st[MPT];
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
-    const int l = threadIdx.x + m * kBlock;
+    const int l = threadIdx.x + m * kPassBlock;
     dF[m][0] = dF[m][1] = dF[m][2] = 0.0f;
     if (l >= nmk) continue;
     marker_stencil(Xp, dirs + 3 * l, r_l, lo, st[m]);
+    const uint32_t below = (1u << st[m].bx) - 1u;
     float Ul[3] = {0.0f, 0.0f, 0.0f};
-    for (int jz = 0; jz < 4; ++jz)
-      for (int jy = 0; jy < 4; ++jy) {
-        const int row = (st[m].by + jy) + side * (st[m].bz + jz);
-        const uint32_t bitsr = rb[row];
-        const uint32_t j0 = rp[row] + __popc(bitsr & ((1u << st[m].bx) - 1u));
-        const float wyz = st[m].wy[jy] * st[m].wz[jz];
-        for (int jx = 0; jx < 4; ++jx) {
-          const float w = st[m].wx[jx] * wyz;
-          const uint32_t j = j0 + jx;
-          Ul[0] += w * uj[3 * j];
-          Ul[1] += w * uj[3 * j + 1];
-          Ul[2] += w * uj[3 * j + 2];
-        }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int jy = q & 3, jz = q >> 2;
+      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+      const float wyz = st[m].wy[jy] * st[m].wz[jz];
+#pragma unroll
+      for (int jx = 0; jx < 4; ++jx) {
+        const float w = st[m].wx[jx] * wyz;
+        const uint32_t j = j0 + jx;
+        Ul[0] += w * uj[3 * j];
+        Ul[1] += w * uj[3 * j + 1];
+        Ul[2] += w * uj[3 * j + 2];
       }
+    }
     const double arm[3] = {r_l * dirs[3 * l], r_l * dirs[3 * l + 1], r_l * dirs[3 * l + 2]};
     const double Ud[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
                           Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
     for (int k = 0; k < 3; ++k) dF[m][k] = 2.0f * ((float)Ud[k] - Ul[k]);
     const double f[3] = {(double)dF[m][0] * dV, (double)dF[m][1] * dV, (double)dF[m][2] * dV};
-    // force and torque on the particle: minus the force on the fluid
-    for (int k = 0; k < 3; ++k) Fs[k] -= f[k];
-    Ts[0] -= arm[1] * f[2] - arm[2] * f[1];
-    Ts[1] -= arm[2] * f[0] - arm[0] * f[2];
-    Ts[2] -= arm[0] * f[1] - arm[1] * f[0];
+    // the particle feels minus the force on the fluid
+    for (int k = 0; k < 3; ++k) fsum[k] -= f[k];
+    fsum[3] -= arm[1] * f[2] - arm[2] * f[1];
+    fsum[4] -= arm[2] * f[0] - arm[0] * f[2];
+    fsum[5] -= arm[0] * f[1] - arm[1] * f[0];
   }
-  // spread, one component at a time
-  const float dVf = (float)dV;
-  for (int k = 0; k < 3; ++k) {
-    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) dj[j] = 0.0f;
-    __syncthreads();
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < 3 * cnt; j += kPassBlock) acc[j] = 0ull;
+  __syncthreads();
+  // spread dF delta dV into the fixed-point sums
 #pragma unroll
-    for (int m = 0; m < MPT; ++m) {
-      const int l = threadIdx.x + m * kBlock;
-      if (l >= nmk) continue;
-      const float a = dF[m][k] * dVf;
-      for (int jz = 0; jz < 4; ++jz)
-        for (int jy = 0; jy < 4; ++jy) {
-          const int row = (st[m].by + jy) + side * (st[m].bz + jz);
-          const uint32_t j0 = rp[row] + __popc(rb[row] & ((1u << st[m].bx) - 1u));
-          const float ayz = a * st[m].wy[jy] * st[m].wz[jz];
-          for (int jx = 0; jx < 4; ++jx) atomicAdd(&dj[j0 + jx], ayz * st[m].wx[jx]);
-        }
+  for (int m = 0; m < MPT; ++m) {
+    const int l = threadIdx.x + m * kPassBlock;
+    if (l >= nmk) continue;
+    const uint32_t below = (1u << st[m].bx) - 1u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int jy = q & 3, jz = q >> 2;
+      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+      const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
+#pragma unroll
+      for (int jx = 0; jx < 4; ++jx) {
+        const float w = st[m].wx[jx] * wyz;
+        const uint32_t j = j0 + jx;
+        atomicAdd(&acc[3 * j], to_fix(dF[m][0] * w));
+        atomicAdd(&acc[3 * j + 1], to_fix(dF[m][1] * w));
+        atomicAdd(&acc[3 * j + 2], to_fix(dF[m][2] * w));
+      }
     }
-    __syncthreads();
-    float* fk = fib + (size_t)k * s_cap;
-    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
-      const uint32_t s = fslot[(size_t)p * fcap + j];
-      if (s >= s_cap) continue;
-      const float v = dj[j];
-      if ((sh[j >> 5] >> (j & 31u)) & 1u)
-        atomicAdd(fk + s, v);
-      else
-        fk[s] += v;
-    }
-    __syncthreads();
   }
-  for (int k = 0; k < 3; ++k) {
-    const double fs = block_sum<kBlock>(Fs[k]);
-    const double ts = block_sum<kBlock>(Ts[k]);
-    if (threadIdx.x == 0) {
-      F_ib[3 * p + k] = (first ? 0.0 : F_ib[3 * p + k]) + fs;
-      T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + ts;
+  __syncthreads();
+  // add the pass's spread to the slot forces: plain read-modify-write where
+  // this sphere owns the node alone, global atomics where supports meet
+  for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
+    uint32_t s[kStage];
+    float old[kStage][3];
+    bool shr[kStage];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
+      shr[i] = j < cnt && ((sh[j >> 5] >> (j & 31u)) & 1u);
+    }
+#pragma unroll
+    for (int i = 0; i < kStage; ++i)
+      if (s[i] < s_cap && !shr[i])
+        for (int k = 0; k < 3; ++k) old[i][k] = fib[(size_t)k * s_cap + s[i]];
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      if (s[i] >= s_cap) continue;
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      for (int k = 0; k < 3; ++k) {
+        float* fk = fib + (size_t)k * s_cap + s[i];
+        const float v = from_fix(acc[3 * j + k]);
+        if (shr[i])
+          atomicAdd(fk, v);
+        else
+          *fk = old[i][k] + v;
+      }
+    }
+  }
+  block_sum_first<kPassBlock, 6>(fsum);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      F_ib[3 * p + k] = (first ? 0.0 : F_ib[3 * p + k]) + fsum[k];
+      T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + fsum[3 + k];
     }
   }
 }
@@ -454,20 +523,17 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
     s[4] += a * (dz * u[0] - dx * u[2]);
     s[5] += a * (dx * u[1] - dy * u[0]);
   }
-  for (int k = 0; k < 6; ++k) {
-    const double t = block_sum<kBlock>(s[k]);
-    if (threadIdx.x == 0) {
-      if (k < 3)
-        Iu[3 * p + k] = t;
-      else
-        IL[3 * p + k - 3] = t;
+  block_sum_n<kBlock, 6>(s);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) {
+      Iu[3 * p + k] = s[k];
+      IL[3 * p + k] = s[3 + k];
     }
-  }
 }
 
 size_t pass_lds_bytes(const Ctx& c) {
   const size_t rows = (size_t)c.ibm.side * c.ibm.side;
-  return rows * 8 + (size_t)c.ibm.fcap * 16 + ((c.ibm.fcap + 31) / 32) * 4;
+  return rows * 8 + (size_t)c.ibm.fcap * 24 + ((c.ibm.fcap + 31) / 32) * 4;
 }
 
 }  // namespace
@@ -521,12 +587,12 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
   const size_t lds = pass_lds_bytes(c);
   const int passes = 1 + c.cfg.ibm_iters;
   for (int k = 0; k < passes; ++k) {
-    if (m.n_markers <= 4 * kBlock)
-      hipLaunchKernelGGL(k_ibm_pass<4>, dim3(c.np), dim3(kBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
+    if (m.n_markers <= kPassBlock)
+      hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
                          m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_ibm_pass<8>, dim3(c.np), dim3(kBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
+      hipLaunchKernelGGL(k_ibm_pass<2>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
                          m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
