@@ -143,7 +143,7 @@ void ibm_support_bounds(double r, double r_d, uint32_t& forcing, uint32_t& full)
 
 // Workspace plan: offsets of every slice for a configuration.
 struct Plan {
-  size_t f_a, f_b, err, scratch;
+  size_t f_a, f_b, err, scratch, stats_part;
   size_t pdoubles;       // particle FP64 block
   size_t owner[2], solid_bits, wall_bits;
   size_t link_node, link_q, link_meta, link_count;
@@ -173,6 +173,7 @@ Plan plan(const lbm_config& c) {
   p.f_b = take(pop_bytes(c));
   p.err = take(kAlign);
   p.scratch = take(64 * sizeof(double));
+  p.stats_part = take(stats_part_bytes());
   const size_t P = has_particles(c) ? (size_t)c.max_particles : 0;
   p.pdoubles = take((size_t)(kParticleVecs * 3 + 2 + 3) * std::max<size_t>(P, 1) * sizeof(double));
   p.wall_bits = take(words * 4);
@@ -435,6 +436,7 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
   c.f_nxt = base + p.f_b;
   c.err = (uint32_t*)(base + p.err);
   c.scratch_d = (double*)(base + p.scratch);
+  c.stats_part = (double*)(base + p.stats_part);
   c.step = 0;
   c.np = 0;
   c.motion = LBM_MOTION_FREE;
@@ -844,6 +846,71 @@ int lbm_get_fields(lbm_ctx* h, float* u, float* rho) {
   if (rho && hipMemcpyAsync(rho, sr, N * sizeof(float), hipMemcpyDeviceToHost, c.stream) != hipSuccess)
     return LBM_E_HIP;
   return drain_errors(c);
+}
+
+int lbm_stats(lbm_ctx* h, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist) {
+  if (!h || !out || nbins < 0 || nbins > LBM_STATS_MAX_BINS || !(bin_width > 0.0)) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const size_t N = c.dims.N;
+  // u [3][N], rho [N] and the node keys [N] fit in the idle population
+  // buffer (at least 38 bytes per node).
+  float* su = (float*)c.f_nxt;
+  float* sr = su + 3 * N;
+  uint32_t* key = (uint32_t*)(sr + N);
+  int st = lbm_get_fields_device(h, su, sr);
+  if (st != LBM_OK) return st;
+  const int pc = c.pcur;
+  double* part = c.stats_part;
+  double* dout = part + (size_t)kStatGrid * kStatStride;
+  hipError_t e = timed(c, LBM_K_STATS, [&] {
+    return launch_stats(c, su, sr, key, nbins, bin_width, c.P.X[pc], c.P.U[pc], c.P.Om[pc], part, dout);
+  });
+  if (e != hipSuccess) return LBM_E_HIP;
+  std::vector<double> v((size_t)kStatScalars + 5 * (size_t)nbins);
+  if (hipMemcpyAsync(v.data(), dout, v.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  const size_t np = (size_t)std::max(c.np, 0);
+  std::vector<double> U(3 * np), Om(3 * np), r(np), rp(np);
+  if (np) {
+    if (hipMemcpyAsync(U.data(), c.P.U[pc], 3 * np * 8, hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipMemcpyAsync(Om.data(), c.P.Om[pc], 3 * np * 8, hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipMemcpyAsync(r.data(), c.P.r, np * 8, hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipMemcpyAsync(rp.data(), c.P.rho, np * 8, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+  }
+  st = drain_errors(c);
+  if (st != LBM_OK) return st;
+  const double Nd = (double)N, nf = v[kStatNf], nfd = nf > 0.0 ? nf : 1.0;
+  lbm_stats_t o{};
+  o.step = c.step;
+  o.n_nodes = (int64_t)N;
+  o.n_fluid = (int64_t)nf;
+  o.mass = v[kStatMass];
+  o.momentum[0] = v[kStatMomX];
+  o.momentum[1] = v[kStatMomY];
+  o.momentum[2] = v[kStatMomZ];
+  o.ke_raw = v[kStatKeRaw] / Nd;
+  o.ke_masked = v[kStatKeMasked] / Nd;
+  o.ke_fluid = v[kStatKeFluid] / nfd;
+  o.eps_raw = v[kStatEpsRaw] / Nd;
+  o.eps_masked = v[kStatEpsMasked] / Nd;
+  o.eps_fluid = v[kStatEpsFluid] / nfd;
+  o.umax = sqrt(v[kStatUmax2]);
+  o.bulk_u = v[kStatBulk] / nfd;
+  for (size_t p = 0; p < np; ++p) {
+    const double m = rp[p] * (4.0 / 3.0) * M_PI * r[p] * r[p] * r[p];
+    const double I = 0.4 * m * r[p] * r[p];
+    double u2 = 0.0, w2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      u2 += U[3 * p + k] * U[3 * p + k];
+      w2 += Om[3 * p + k] * Om[3 * p + k];
+    }
+    o.particle_ke += 0.5 * m * u2;
+    o.particle_ke_rot += 0.5 * I * w2;
+  }
+  *out = o;
+  if (hist && nbins > 0) std::copy(v.begin() + kStatScalars, v.end(), hist);
+  return LBM_OK;
 }
 
 int lbm_sync(lbm_ctx* h) {

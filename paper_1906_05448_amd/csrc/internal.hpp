@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "d3q19.hpp"
@@ -175,6 +176,7 @@ struct Ctx {
   void* f_nxt;
   uint32_t* err;    // latched error bits (one word)
   double* scratch_d;  // small FP64 scratch for reductions
+  double* stats_part; // [kStatGrid + 1][kStatStride] statistics partial sums
   int64_t step;
   Profiler prof;
   // Particles.
@@ -238,6 +240,20 @@ hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, flo
 hipError_t launch_particle_update(const Ctx& c);
 hipError_t launch_release_average(const Ctx& c, const float* u, double* Uout);
 hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U);
+// Statistics (stats.hip). Columns of the per-block partial sums; the
+// histograms follow as [5][nbins] (count, sum 1/2|u|^2, sum eps, sum u_z,
+// sum u_z^2).
+enum {
+  kStatNf, kStatMass, kStatMomX, kStatMomY, kStatMomZ, kStatKeRaw, kStatKeFluid, kStatEpsRaw, kStatUmax2, kStatBulk,
+  kStatKeMasked, kStatEpsMasked, kStatEpsFluid, kStatScalars
+};
+constexpr int kStatGrid = 1024;  // workgroups of the grid-stride passes
+constexpr int kStatStride = kStatScalars + 5 * LBM_STATS_MAX_BINS;
+size_t stats_part_bytes();
+// u, rho: the extracted field; key: [N] scratch. Writes kStatScalars + 5 nbins
+// sums to out (device).
+hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t* key, int nbins, double width,
+                        const double* X, const double* U, const double* Om, double* part, double* out);
 
 }  // namespace lbm
 

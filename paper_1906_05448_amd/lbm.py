@@ -47,6 +47,20 @@ class _CConfig(ctypes.Structure):
     ]
 
 
+class _CStats(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+        ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+        ("ke_raw", ctypes.c_double), ("ke_masked", ctypes.c_double), ("ke_fluid", ctypes.c_double),
+        ("eps_raw", ctypes.c_double), ("eps_masked", ctypes.c_double), ("eps_fluid", ctypes.c_double),
+        ("umax", ctypes.c_double), ("bulk_u", ctypes.c_double),
+        ("particle_ke", ctypes.c_double), ("particle_ke_rot", ctypes.c_double),
+    ]
+
+
+STATS_MAX_BINS = 256
+
+
 def lib() -> ctypes.CDLL:
     """Load liblbm.so; raises if it has not been built."""
     global _lib
@@ -75,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "lbm_link_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
         "lbm_profile_enable": (ctypes.c_int, [P, I32]),
         "lbm_profile_read": (ctypes.c_int, [P, P, P]),
         "lbm_destroy": (None, [P]),
@@ -256,6 +271,19 @@ class Lattice:
         s, l = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().lbm_geometry_counts(self._h, ctypes.byref(s), ctypes.byref(l)), "lbm_geometry_counts")
         return s.value, l.value
+
+    def stats(self, nbins: int = 32, bin_width: float = 0.25) -> dict:
+        """Statistics of the current snapshot (lbm_stats): a dict with the
+        lbm_stats_t fields (momentum as an array) and "hist" [5][nbins]
+        (count, sum 1/2|u|^2, sum eps, sum u_z, sum u_z^2 per distance bin)."""
+        out = _CStats()
+        hist = np.zeros((5, max(int(nbins), 0)), np.float64)
+        _check(lib().lbm_stats(self._h, int(nbins), float(bin_width), ctypes.byref(out),
+                               hist.ctypes.data_as(ctypes.c_void_p) if nbins > 0 else None), "lbm_stats")
+        d = {name: getattr(out, name) for name, _ in _CStats._fields_}
+        d["momentum"] = np.array(list(out.momentum))
+        d["hist"] = hist
+        return d
 
     # -- time stepping -------------------------------------------------
     def step(self, n: int = 1) -> None:
