@@ -11,6 +11,8 @@ All randomness is numpy ``default_rng(seed)`` (PCG64).
 from .fields import (HitSpectrum, hit_spectrum, hit_field, hit_field_at,
                      pipe_initial_velocity, random_density, random_velocity)
 from .particles import random_spheres
+from .weights import mlp_initial_params
 
 __all__ = ["HitSpectrum", "hit_spectrum", "hit_field", "hit_field_at",
-           "pipe_initial_velocity", "random_density", "random_velocity", "random_spheres"]
+           "pipe_initial_velocity", "random_density", "random_velocity", "random_spheres",
+           "mlp_initial_params"]
