@@ -207,6 +207,70 @@ typedef struct {
  * bin_width <= 0, out NULL). */
 int lbm_stats(lbm_ctx* ctx, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist);
 
+/* ---- Gradient-corrector network ----------------------------------------
+ * The paper finds the immersed boundary smears near-surface velocity
+ * gradients, so the local dissipation next to particles differs from the
+ * bounce-back result (Sec. 4.2, conclusions). The corrector maps the
+ * neighbourhood of an interface cell to its velocity gradient: a multilayer
+ * perceptron 85 -> 64 -> 64 -> 9 with SiLU activations,
+ *   z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, h2 = silu(z2),
+ *   y = W3 h2 + b3,
+ * trained on the mean squared error with Adam. Parameters are one FP32
+ * vector of LBM_MLP_PARAMS: W1 (64x85, [out][in]), b1, W2 (64x64), b2,
+ * W3 (9x64), b3. Matrix products run on the matrix cores with BF16 weights
+ * and activations and FP32 accumulation; the master parameters and the
+ * Adam moments are FP32.
+ * Features: device BF16 rows of LBM_MLP_IN_STRIDE (entries 85..95 zero).
+ * Targets and outputs: device FP32 rows of LBM_MLP_OUT_STRIDE (9 used). */
+#define LBM_MLP_IN 85
+#define LBM_MLP_IN_STRIDE 96
+#define LBM_MLP_OUT 9
+#define LBM_MLP_OUT_STRIDE 16
+#define LBM_MLP_PARAMS 10249
+
+typedef struct lbm_mlp lbm_mlp;
+
+/* Bytes of the device workspace of one network (parameters, Adam moments,
+ * gradient and reduction partials). */
+size_t lbm_mlp_workspace_size(void);
+
+/* Binds a network to a caller-allocated device workspace (256-byte aligned,
+ * at least lbm_mlp_workspace_size() bytes, outliving the handle) and the
+ * caller's hipStream_t; copies the host parameters and zeroes the Adam
+ * state. Sync. Errors: LBM_E_ARG, LBM_E_SIZE. */
+int lbm_mlp_init(void* workspace, size_t bytes, const float* params_host, void* hip_stream, lbm_mlp** out);
+
+/* Replaces the parameters (host) and resets the Adam state. Sync. */
+int lbm_mlp_set_params(lbm_mlp* mlp, const float* params_host);
+
+/* Current parameters to host. Sync. */
+int lbm_mlp_get_params(lbm_mlp* mlp, float* params_host);
+
+/* Device address of the FP32 parameter vector (for lbm_corrector_set). */
+const float* lbm_mlp_device_params(const lbm_mlp* mlp);
+
+/* y[n][16] = network(x[n][96]) for n >= 0 samples (device buffers). Async. */
+int lbm_mlp_forward(lbm_mlp* mlp, const uint16_t* x_dev, int64_t n, float* y_dev);
+
+/* Gradient of L = mean over the n samples and 9 outputs of (y - t)^2 at the
+ * current parameters, kept for lbm_mlp_adam_step. If loss or grad (host,
+ * LBM_MLP_PARAMS) is non-NULL the call syncs and returns them. Errors:
+ * LBM_E_ARG (n <= 0). */
+int lbm_mlp_gradient(lbm_mlp* mlp, const uint16_t* x_dev, const float* t_dev, int64_t n, double* loss,
+                     float* grad_host);
+
+/* One Adam step (Kingma & Ba) with the last gradient:
+ *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ *   theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * Async. Errors: LBM_E_ARG (no gradient yet, or rates out of range). */
+int lbm_mlp_adam_step(lbm_mlp* mlp, double lr, double beta1, double beta2, double eps);
+
+/* Waits for the network's stream. */
+int lbm_mlp_sync(lbm_mlp* mlp);
+
+/* Releases the handle (not the workspace). NULL is ignored. */
+void lbm_mlp_destroy(lbm_mlp* mlp);
+
 /* Kernel classes for lbm_profile_read(). */
 enum {
   LBM_K_STREAM_COLLIDE = 0, /* fused pull-stream + MRT collision, all nodes  */

@@ -252,6 +252,16 @@ constexpr int kStatStride = kStatScalars + 5 * LBM_STATS_MAX_BINS;
 size_t stats_part_bytes();
 // u, rho: the extracted field; key: [N] scratch. Writes kStatScalars + 5 nbins
 // sums to out (device).
+// Corrector network (mlp.hip). part: [kMlpGrid][10249] FP32, lpart:
+// [kMlpGrid] FP64.
+constexpr int kMlpGrid = 256;
+size_t mlp_train_lds_bytes();
+size_t mlp_forward_lds_bytes();
+hipError_t launch_mlp_forward(hipStream_t st, const float* theta, const uint16_t* X, int64_t n, float* Y);
+hipError_t launch_mlp_gradient(hipStream_t st, const float* theta, const uint16_t* X, const float* T, int64_t n,
+                               float* part, double* lpart, float* grad, double* loss);
+hipError_t launch_mlp_adam(hipStream_t st, float* theta, float* m, float* v, const float* g, float lr, float b1,
+                           float b2, float eps, float c1, float c2);
 hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t* key, int nbins, double width,
                         const double* X, const double* U, const double* Om, double* part, double* out);
 

@@ -90,6 +90,16 @@ def lib() -> ctypes.CDLL:
         "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
+        "lbm_mlp_workspace_size": (SZ, []),
+        "lbm_mlp_init": (ctypes.c_int, [P, SZ, P, P, ctypes.POINTER(P)]),
+        "lbm_mlp_set_params": (ctypes.c_int, [P, P]),
+        "lbm_mlp_get_params": (ctypes.c_int, [P, P]),
+        "lbm_mlp_device_params": (P, [P]),
+        "lbm_mlp_forward": (ctypes.c_int, [P, P, I64, P]),
+        "lbm_mlp_gradient": (ctypes.c_int, [P, P, P, I64, ctypes.POINTER(ctypes.c_double), P]),
+        "lbm_mlp_adam_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+        "lbm_mlp_sync": (ctypes.c_int, [P]),
+        "lbm_mlp_destroy": (None, [P]),
         "lbm_profile_enable": (ctypes.c_int, [P, I32]),
         "lbm_profile_read": (ctypes.c_int, [P, P, P]),
         "lbm_destroy": (None, [P]),
@@ -312,6 +322,82 @@ class Lattice:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MLP_IN, MLP_IN_STRIDE, MLP_OUT, MLP_OUT_STRIDE, MLP_PARAMS = 85, 96, 9, 16, 10249
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """The gradient-corrector network on the current GPU (lbm_mlp_*).
+
+    Features are torch bfloat16 CUDA tensors [n, 96]; targets and outputs
+    float32 [n, 16]. Parameters are a float vector of 10,249 entries."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+        self._torch = torch
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = L.lbm_mlp_workspace_size()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(MLP_PARAMS))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.lbm_mlp_init(_dev(self.workspace), ctypes.c_size_t(nbytes), _host_ptr(p),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "lbm_mlp_init")
+        self._h = h
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(MLP_PARAMS))
+        _check(lib().lbm_mlp_set_params(self._h, _host_ptr(p)), "lbm_mlp_set_params")
+
+    def params(self) -> np.ndarray:
+        p = np.empty(MLP_PARAMS, np.float32)
+        _check(lib().lbm_mlp_get_params(self._h, _host_ptr(p)), "lbm_mlp_get_params")
+        return p
+
+    def _rows(self, x):
+        t = self._torch
+        assert x.is_cuda and x.dtype == t.bfloat16 and x.is_contiguous() and x.shape[-1] == MLP_IN_STRIDE
+        return x.shape[0]
+
+    def forward(self, x):
+        n = self._rows(x)
+        y = self._torch.empty((n, MLP_OUT_STRIDE), dtype=self._torch.float32, device=self.device)
+        _check(lib().lbm_mlp_forward(self._h, _dev(x) if n else None, n, _dev(y) if n else None), "lbm_mlp_forward")
+        return y
+
+    def gradient(self, x, t, want_grad=False):
+        """(loss, gradient or None) at the current parameters."""
+        n = self._rows(x)
+        assert t.is_cuda and t.dtype == self._torch.float32 and t.is_contiguous() and t.shape == (n, MLP_OUT_STRIDE)
+        loss = ctypes.c_double()
+        g = np.empty(MLP_PARAMS, np.float32) if want_grad else None
+        _check(lib().lbm_mlp_gradient(self._h, _dev(x), _dev(t), n, ctypes.byref(loss),
+                                      _host_ptr(g) if want_grad else None), "lbm_mlp_gradient")
+        return loss.value, g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+        _check(lib().lbm_mlp_adam_step(self._h, lr, beta1, beta2, eps), "lbm_mlp_adam_step")
+
+    def sync(self) -> None:
+        _check(lib().lbm_mlp_sync(self._h), "lbm_mlp_sync")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lbm_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):
