@@ -127,8 +127,11 @@ int lbm_step_count(const lbm_ctx* ctx, int64_t* step);
  * starts with the fluid velocity averaged over its volume (weighted by the
  * cell solid fraction) and zero angular velocity, and the populations at its
  * nodes are reset once to the equilibrium of the local density and that
- * velocity. LBM_SET_STATE takes u and omega as given. */
-enum { LBM_SET_STATE = 0, LBM_RELEASE = 1 };
+ * velocity. LBM_SET_STATE takes u and omega as given. LBM_SET_RIGID takes
+ * them as given and resets the populations at the particle's nodes once to
+ * the equilibrium of the local density and the rigid-body velocity
+ * U + Omega x (x - X) (the rigid interior of Sec. 3.1 with a given motion). */
+enum { LBM_SET_STATE = 0, LBM_RELEASE = 1, LBM_SET_RIGID = 2 };
 /* Particle motion: free (equations of motion with hydrodynamic and contact
  * forces), fixed in place, or prescribed (centres advance with the given
  * constant velocities). Forces are evaluated in every mode. */
@@ -193,6 +196,9 @@ typedef struct {
   double eps_raw, eps_masked, eps_fluid;
   double umax, bulk_u;
   double particle_ke, particle_ke_rot;
+  double eps_fluid_corrected;  /* eps_fluid with the corrector's gradients at
+                                  its cells (= eps_fluid without one)     */
+  int64_t n_corrected;         /* cells the corrector handled             */
 } lbm_stats_t;
 
 #define LBM_STATS_MAX_BINS 256
@@ -200,11 +206,14 @@ typedef struct {
 /* Computes the statistics of the current field and particle state. Local
  * profiles (Sec. 4.2): fluid node x falls in bin floor(d / bin_width) of
  * d = min(min_p |x - X_p| - r_p, R - |x_perp - c| with a pipe), if that bin
- * is below nbins. hist (host, [5][nbins], may be NULL; ignored if nbins is
+ * is below nbins. hist (host, [6][nbins], may be NULL; ignored if nbins is
  * 0) receives per bin the node count and the sums of 1/2 |u|^2, eps (of the
- * masked field), u_z and u_z^2. Uses the idle population buffer as scratch.
- * Sync. Errors: LBM_E_ARG (nbins outside 0 .. LBM_STATS_MAX_BINS,
- * bin_width <= 0, out NULL). */
+ * masked field), u_z, u_z^2 and the corrected eps. With a corrector attached
+ * (lbm_corrector_set), eps at its interface cells is recomputed from the
+ * predicted gradient (eps_fluid_corrected, hist row 5). Uses the idle
+ * population buffer as scratch. Sync. Errors: LBM_E_ARG (nbins outside
+ * 0 .. LBM_STATS_MAX_BINS, bin_width <= 0, out NULL), LBM_E_SIZE (corrector
+ * zone larger than the lattice, or more interface cells than scratch). */
 int lbm_stats(lbm_ctx* ctx, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist);
 
 /* ---- Gradient-corrector network ----------------------------------------
@@ -270,6 +279,40 @@ int lbm_mlp_sync(lbm_mlp* mlp);
 
 /* Releases the handle (not the workspace). NULL is ignored. */
 void lbm_mlp_destroy(lbm_mlp* mlp);
+
+/* ---- Corrector on a lattice ---------------------------------------------
+ * Interface cells of sphere p: fluid nodes with r_p <= |x - X_p| <
+ * r_p - r_d + 2 (r_d = ibm_retraction: the marker radius plus the reach of
+ * the 4-point delta) and d = |x - X_p| - r_p in [d_min, d_max]; a cell falls
+ * back to the plain central difference when another sphere q has
+ * |x - X_q| < r_q - r_d + 2 + sqrt(3) (its band or interior within the 3x3x3
+ * stencil, or a gap below two spacings). Distances are periodic minimum-image,
+ * squared as ((dx dx + dy dy) + dz dz) and compared squared.
+ * Features (85): for the 27 offsets o (z slowest, x fastest, each -1, 0, 1)
+ * and components c, (u_c(x + o) - [U_p + Omega_p x (x + o - X_p)]_c) / u_rms
+ * of the lattice field; then d; then (x - X_p) / |x - X_p|. Outputs and
+ * labels (9): G_ij / u_rms = (d_j u_i) / u_rms, row-major in (i, j), labels
+ * by central differences of the masked field (as lbm_stats). All three calls
+ * require 2 (max_radius - r_d + 2 + sqrt(3)) + 3 <= min(nx, ny, nz)
+ * (LBM_E_SIZE otherwise). */
+
+/* Interface cells of the current state in ascending node order: node index
+ * (x + nx (y + ny z)) and sphere of up to cap cells into device int32
+ * arrays, and, if x_dev (device, 16-byte aligned, [cap][96] BF16) is not
+ * NULL, their features. *n gets the number of cells; LBM_E_SIZE if it
+ * exceeds cap (nothing beyond cap is written). Sync. */
+int lbm_corrector_cells(lbm_ctx* ctx, double d_min, double d_max, double u_rms, int64_t cap, int32_t* node_dev,
+                        int32_t* particle_dev, uint16_t* x_dev, int64_t* n);
+
+/* Training labels at n given nodes (device int32): the masked central-
+ * difference gradient of this lattice's field / u_rms into t_dev
+ * ([n][16] FP32, entries 9..15 zero). Sync. */
+int lbm_corrector_labels(lbm_ctx* ctx, const int32_t* node_dev, int64_t n, double u_rms, float* t_dev);
+
+/* Attaches a network for lbm_stats (params_dev: lbm_mlp_device_params(), must
+ * stay valid while attached; NULL detaches) with the training range of d and
+ * the velocity scale of the features. */
+int lbm_corrector_set(lbm_ctx* ctx, const float* params_dev, double d_min, double d_max, double u_rms);
 
 /* Kernel classes for lbm_profile_read(). */
 enum {

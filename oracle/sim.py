@@ -40,7 +40,7 @@ from .lattice import CF, OPP, DEFAULT_RATES, relaxation_vector
 from .particles import Particles, advance, contact_forces
 
 # set_particles modes
-SET_STATE, RELEASE = 0, 1
+SET_STATE, RELEASE, SET_RIGID = 0, 1, 2
 
 
 @dataclass
@@ -161,7 +161,8 @@ class Sim:
         """Places spheres. RELEASE (Sec. 3.1): U = fluid velocity averaged over
         the particle volume (Kempe-fraction weighted), Omega = 0, and the
         velocity inside the particle is overwritten once by the rigid-body
-        motion (equilibrium at the local density)."""
+        motion (equilibrium at the local density). SET_RIGID: U and Omega as
+        given, the interior overwritten once by U + Omega x (x - X)."""
         st = self.state
         X = np.atleast_2d(np.asarray(X, np.float64)).copy()
         n = len(X)
@@ -177,11 +178,16 @@ class Sim:
                 uu = st.u[:, nodes[:, 2], nodes[:, 1], nodes[:, 0]]
                 U[p] = (uu * alpha[None]).sum(1) / alpha.sum()
             Om[:] = 0.0
+        if mode in (RELEASE, SET_RIGID):
+            # interior: equilibrium of the local density and the rigid-body
+            # velocity U + Omega x (x - X)
             inside = geo.owner_map(shape, X, r, None)
             for p in range(n):
                 zz, yy, xx = np.nonzero(inside == p)
                 rho = st.rho[zz, yy, xx]
-                urig = np.broadcast_to(U[p][:, None], (3, len(zz)))
+                d = np.stack([geo.min_image(xx - X[p, 0], shape[0]), geo.min_image(yy - X[p, 1], shape[1]),
+                              geo.min_image(zz - X[p, 2], shape[2])], -1)
+                urig = (U[p][None, :] + np.cross(np.broadcast_to(Om[p], d.shape), d)).T
                 st.ft[:, zz, yy, xx] = col.equilibrium(rho, urig)
                 st.u[:, zz, yy, xx] = urig
         st.P = Particles(X, U, Om, r, rho_p, motion)

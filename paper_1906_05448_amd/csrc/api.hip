@@ -600,7 +600,7 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
   if (cfg.bc == LBM_BC_NONE || cfg.wall != LBM_WALL_NONE) return LBM_E_ARG;
   if (np < 0 || np > cfg.max_particles) return LBM_E_SIZE;
   if (np > 0 && (!x || !radius)) return LBM_E_ARG;
-  if (mode != LBM_SET_STATE && mode != LBM_RELEASE) return LBM_E_ARG;
+  if (mode != LBM_SET_STATE && mode != LBM_RELEASE && mode != LBM_SET_RIGID) return LBM_E_ARG;
   if (motion != LBM_MOTION_FREE && motion != LBM_MOTION_FIXED && motion != LBM_MOTION_PRESCRIBED) return LBM_E_ARG;
   const double L[3] = {(double)cfg.nx, (double)cfg.ny, (double)cfg.nz};
   std::vector<double> X(3 * (size_t)np), U(3 * (size_t)np, 0.0), W(3 * (size_t)np, 0.0), R(np), RHO(np, 1.0);
@@ -655,9 +655,11 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
     if (e == hipSuccess) e = launch_release_average(c, ufield, U0);
     if (e == hipSuccess) e = hipMemcpyAsync(c.P.U[0], U0, vb, hipMemcpyDeviceToDevice, c.stream);
     if (e == hipSuccess) e = hipMemsetAsync(c.P.Om[0], 0, vb, c.stream);
-    if (e == hipSuccess) e = launch_release_overwrite(c, c.f_cur, c.ibb.owner[0], c.P.U[0]);
+    if (e == hipSuccess) e = launch_release_overwrite(c, c.f_cur, c.ibb.owner[0], c.P.U[0], c.P.Om[0]);
     if (e == hipSuccess) e = hipMemsetAsync(c.P.F_h, 0, vb, c.stream);
   }
+  if (e == hipSuccess && mode == LBM_SET_RIGID && np > 0)
+    e = launch_release_overwrite(c, c.f_cur, c.ibb.owner[0], c.P.U[0], c.P.Om[0]);
   // Both owner maps now hold (at most) the current spheres, so the box
   // positions recorded for each must be valid centres before the first
   // clear: clearing around the current centres in the other map is a no-op.
@@ -848,26 +850,97 @@ int lbm_get_fields(lbm_ctx* h, float* u, float* rho) {
   return drain_errors(c);
 }
 
+namespace {
+
+// Statistics and corrector scratch in the idle population buffer (at least
+// 38 bytes per node): u [3][N], rho [N], node keys [N], three bitmasks, the
+// bitmask rank and scan sums, counters, the sphere of each cell [N], then the
+// cell and sphere lists.
+struct Scratch {
+  float* u;
+  float* rho;
+  uint32_t* key;
+  CorrBufs cb;
+  uint32_t* list;
+  uint32_t* plist;
+  uint32_t cap;
+};
+
+Scratch scratch_layout(const Ctx& c) {
+  const size_t N = c.dims.N;
+  const size_t words = mask_words(c.dims.N);
+  char* base = (char*)c.f_nxt;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align_up(b);
+    return p;
+  };
+  Scratch s{};
+  s.u = (float*)take(3 * N * 4);
+  s.rho = (float*)take(N * 4);
+  s.key = (uint32_t*)take(N * 4);
+  s.cb.once = (uint32_t*)take(3 * words * 4);
+  s.cb.twice = s.cb.once + words;
+  s.cb.cellbits = s.cb.twice + words;
+  s.cb.rank = (uint32_t*)take(words * 4);
+  s.cb.bsums = (uint32_t*)take(bits_compact_scratch_words((uint32_t)words) * 4);
+  s.cb.count = (uint32_t*)take(4);
+  s.cb.err = (uint32_t*)take(4);
+  s.cb.cellp = (uint32_t*)take(N * 4);
+  const size_t total = pop_bytes(c.cfg);
+  const size_t left = total > off + 2 * kAlign ? total - off - 2 * kAlign : 0;
+  s.cap = (uint32_t)std::min<size_t>(N, left / 8);
+  s.list = (uint32_t*)take((size_t)s.cap * 4);
+  s.plist = (uint32_t*)take((size_t)s.cap * 4);
+  return s;
+}
+
+// The exclusion zone of every sphere must fit in the lattice once.
+bool corrector_fits(const Ctx& c) {
+  const double re = (c.cfg.max_radius - c.cfg.ibm_retraction) + 2.0 + 1.7320508075688772;
+  const double side = 2.0 * re + 3.0;
+  return side <= (double)c.dims.nx && side <= (double)c.dims.ny && side <= (double)c.dims.nz;
+}
+
+}  // namespace
+
 int lbm_stats(lbm_ctx* h, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist) {
   if (!h || !out || nbins < 0 || nbins > LBM_STATS_MAX_BINS || !(bin_width > 0.0)) return LBM_E_ARG;
   Ctx& c = h->c;
   const size_t N = c.dims.N;
-  // u [3][N], rho [N] and the node keys [N] fit in the idle population
-  // buffer (at least 38 bytes per node).
-  float* su = (float*)c.f_nxt;
-  float* sr = su + 3 * N;
-  uint32_t* key = (uint32_t*)(sr + N);
+  const Scratch sc = scratch_layout(c);
+  float* su = sc.u;
+  float* sr = sc.rho;
+  uint32_t* key = sc.key;
   int st = lbm_get_fields_device(h, su, sr);
   if (st != LBM_OK) return st;
   const int pc = c.pcur;
   double* part = c.stats_part;
   double* dout = part + (size_t)kStatGrid * kStatStride;
+  double* cout = dout + kStatStride;
   hipError_t e = timed(c, LBM_K_STATS, [&] {
     return launch_stats(c, su, sr, key, nbins, bin_width, c.P.X[pc], c.P.U[pc], c.P.Om[pc], part, dout);
   });
   if (e != hipSuccess) return LBM_E_HIP;
-  std::vector<double> v((size_t)kStatScalars + 5 * (size_t)nbins);
+  const bool corr = c.corr_theta && c.np > 0;
+  if (corr) {
+    if (!corrector_fits(c)) return LBM_E_SIZE;
+    e = timed(c, LBM_K_CORRECTOR, [&] {
+      hipError_t r = launch_corrector_cells(c, c.P.X[pc], c.corr_dmin, c.corr_dmax, sc.cb, sc.list, sc.plist, sc.cap);
+      if (r != hipSuccess) return r;
+      return launch_corrector_stats(c, c.corr_theta, su, key, sc.list, sc.plist, sc.cb.count, sc.cap, c.P.X[pc],
+                                    c.P.U[pc], c.P.Om[pc], c.corr_urms, nbins, part, cout);
+    });
+    if (e != hipSuccess) return LBM_E_HIP;
+  }
+  std::vector<double> v((size_t)kStatScalars + 5 * (size_t)nbins), cv(2 + (size_t)nbins, 0.0);
+  uint32_t ncells = 0;
   if (hipMemcpyAsync(v.data(), dout, v.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  if (corr && (hipMemcpyAsync(cv.data(), cout, cv.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream) !=
+                   hipSuccess ||
+               hipMemcpyAsync(&ncells, sc.cb.count, 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess))
     return LBM_E_HIP;
   const size_t np = (size_t)std::max(c.np, 0);
   std::vector<double> U(3 * np), Om(3 * np), r(np), rp(np);
@@ -908,9 +981,73 @@ int lbm_stats(lbm_ctx* h, int32_t nbins, double bin_width, lbm_stats_t* out, dou
     o.particle_ke += 0.5 * m * u2;
     o.particle_ke_rot += 0.5 * I * w2;
   }
+  if (corr && ncells > sc.cap) return LBM_E_SIZE;
+  o.eps_fluid_corrected = (v[kStatEpsFluid] + cv[0]) / nfd;
+  o.n_corrected = (int64_t)cv[1];
   *out = o;
-  if (hist && nbins > 0) std::copy(v.begin() + kStatScalars, v.end(), hist);
+  if (hist && nbins > 0) {
+    std::copy(v.begin() + kStatScalars, v.end(), hist);
+    for (int b = 0; b < nbins; ++b) hist[5 * (size_t)nbins + b] = hist[2 * (size_t)nbins + b] + cv[2 + b];
+  }
   return LBM_OK;
+}
+
+int lbm_corrector_set(lbm_ctx* h, const float* params_dev, double d_min, double d_max, double u_rms) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (!params_dev) {
+    c.corr_theta = nullptr;
+    return LBM_OK;
+  }
+  if (!(u_rms > 0.0) || !(d_max >= d_min)) return LBM_E_ARG;
+  if (!corrector_fits(c)) return LBM_E_SIZE;
+  c.corr_theta = params_dev;
+  c.corr_dmin = d_min;
+  c.corr_dmax = d_max;
+  c.corr_urms = u_rms;
+  return LBM_OK;
+}
+
+int lbm_corrector_cells(lbm_ctx* h, double d_min, double d_max, double u_rms, int64_t cap, int32_t* node_dev,
+                        int32_t* particle_dev, uint16_t* x_dev, int64_t* n) {
+  if (!h || !n || cap < 0 || cap > (int64_t)UINT32_MAX || !(u_rms > 0.0) || !(d_max >= d_min)) return LBM_E_ARG;
+  if (cap > 0 && (!node_dev || !particle_dev)) return LBM_E_ARG;
+  if (x_dev && ((uintptr_t)x_dev % 16)) return LBM_E_ARG;
+  Ctx& c = h->c;
+  *n = 0;
+  if (!corrector_fits(c)) return LBM_E_SIZE;
+  const Scratch sc = scratch_layout(c);
+  int st = lbm_get_fields_device(h, sc.u, nullptr);
+  if (st != LBM_OK) return st;
+  const int pc = c.pcur;
+  const uint32_t ucap = (uint32_t)cap;
+  hipError_t e = launch_corrector_cells(c, c.P.X[pc], d_min, d_max, sc.cb, (uint32_t*)node_dev,
+                                        (uint32_t*)particle_dev, ucap);
+  if (e == hipSuccess && x_dev)
+    e = launch_corrector_features(c, sc.u, (const uint32_t*)node_dev, (const uint32_t*)particle_dev, sc.cb.count,
+                                  ucap, c.P.X[pc], c.P.U[pc], c.P.Om[pc], u_rms, x_dev);
+  if (e != hipSuccess) return LBM_E_HIP;
+  uint32_t count = 0;
+  if (hipMemcpyAsync(&count, sc.cb.count, 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+  st = drain_errors(c);
+  if (st != LBM_OK) return st;
+  *n = count;
+  return count > ucap ? LBM_E_SIZE : LBM_OK;
+}
+
+int lbm_corrector_labels(lbm_ctx* h, const int32_t* node_dev, int64_t n, double u_rms, float* t_dev) {
+  if (!h || n < 0 || n > (int64_t)UINT32_MAX || !(u_rms > 0.0) || (n > 0 && (!node_dev || !t_dev))) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const Scratch sc = scratch_layout(c);
+  int st = lbm_get_fields_device(h, sc.u, nullptr);
+  if (st != LBM_OK) return st;
+  const int pc = c.pcur;
+  hipError_t e = launch_stats_keys(c, sc.key, 0, 1.0, c.P.X[pc]);
+  if (e == hipSuccess)
+    e = launch_corrector_labels(c, sc.u, sc.key, (const uint32_t*)node_dev, (uint32_t)n, c.P.X[pc], c.P.U[pc],
+                                c.P.Om[pc], u_rms, t_dev);
+  if (e != hipSuccess) return LBM_E_HIP;
+  return drain_errors(c);
 }
 
 int lbm_sync(lbm_ctx* h) {

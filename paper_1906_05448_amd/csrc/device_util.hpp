@@ -195,6 +195,14 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
   __syncthreads();
 }
 
+// Value of a double in lane src (src uniform across the wavefront).
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const unsigned long long b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // N block sums whose results only thread 0 needs: lanes 0 .. N-1 of the first
 // wavefront add the wavefront partials in index order, so the result matches
 // block_sum_n bit for bit. Every thread must call it.

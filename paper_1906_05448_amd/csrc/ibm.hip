@@ -540,6 +540,20 @@ size_t pass_lds_bytes(const Ctx& c) {
 
 size_t ibm_pass_lds_bytes(const Ctx& c) { return pass_lds_bytes(c); }
 
+size_t bits_compact_scratch_words(uint32_t nwords) { return (nwords + kScanWords - 1) / kScanWords + 2; }
+
+hipError_t launch_bits_compact(hipStream_t st, const uint32_t* bits, uint32_t nwords, uint32_t* rank,
+                               uint32_t* block_sums, uint32_t* count, uint32_t* list, uint32_t cap, uint32_t* err) {
+  const uint32_t nblk = (nwords + kScanWords - 1) / kScanWords;
+  hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kBlock), 0, st, bits, nwords, rank, block_sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, block_sums, nblk, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kBlock), 0, st, bits, nwords, rank, block_sums, list, cap, err);
+  return hipGetLastError();
+}
+
 hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
   const uint32_t words = mask_words(c.dims.N);
   IbmBufs& m = c.ibm;
@@ -552,15 +566,9 @@ hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
                        m.R_b, m.side, c.dims, m.bits[buf], m.shared, m.rowbits, m.fcount, m.fcap, c.err);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const uint32_t nblk = (words + kScanWords - 1) / kScanWords;
-  hipLaunchKernelGGL(k_scan_block, dim3(nblk), dim3(kBlock), 0, c.stream, m.bits[buf], words, m.rank[buf],
-                     m.block_sums);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c.stream, m.block_sums, nblk, m.count[buf]);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kBlock), 0, c.stream, m.bits[buf], words, m.rank[buf],
-                     m.block_sums, m.list, m.s_cap, c.err);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_bits_compact(c.stream, m.bits[buf], words, m.rank[buf], m.block_sums, m.count[buf], m.list,
+                               m.s_cap, c.err)) != hipSuccess)
+    return e;
   if (c.np > 0) {
     hipLaunchKernelGGL(k_ibm_slots, dim3(c.np), dim3(kBlock), 0, c.stream, X, m.R_b, m.side, c.dims, m.bits[buf],
                        m.rank[buf], m.rowbits, m.fcount, m.fcap, m.fslot);

@@ -189,6 +189,9 @@ struct Ctx {
   IbbBufs ibb;
   IbmBufs ibm;
   double max_radius_set; // largest radius of the particles set
+  // Gradient corrector attached for the statistics (lbm_corrector_set).
+  const float* corr_theta;  // device FP32 network parameters, null: off
+  double corr_dmin, corr_dmax, corr_urms;
 };
 
 // Runs a launcher, bracketed by timing events when profiling is on.
@@ -234,12 +237,20 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
 hipError_t launch_ibm_kempe(const Ctx& c, const double* X, double* Iu, double* IL);
 hipError_t launch_kempe_dense(const Ctx& c, const float* u, const double* X, double* Iu, double* IL);
 hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B);
+// Set bits of a node bitmask -> ascending node list: rank[w] = set bits
+// before word w, *count = total, list[i] = i-th set node (entries beyond cap
+// dropped, *err |= capacity bit). block_sums: bits_compact_scratch_words().
+size_t bits_compact_scratch_words(uint32_t nwords);
+hipError_t launch_bits_compact(hipStream_t st, const uint32_t* bits, uint32_t nwords, uint32_t* rank,
+                               uint32_t* block_sums, uint32_t* count, uint32_t* list, uint32_t cap, uint32_t* err);
 hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, float* rho);
 
 // Particles (particles.hip).
 hipError_t launch_particle_update(const Ctx& c);
 hipError_t launch_release_average(const Ctx& c, const float* u, double* Uout);
-hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U);
+// Interior populations of every sphere -> equilibrium of the local density
+// and the rigid-body velocity U + Omega x (x - X).
+hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U, const double* Om);
 // Statistics (stats.hip). Columns of the per-block partial sums; the
 // histograms follow as [5][nbins] (count, sum 1/2|u|^2, sum eps, sum u_z,
 // sum u_z^2).
@@ -262,6 +273,27 @@ hipError_t launch_mlp_gradient(hipStream_t st, const float* theta, const uint16_
                                float* part, double* lpart, float* grad, double* loss);
 hipError_t launch_mlp_adam(hipStream_t st, float* theta, float* m, float* v, const float* g, float lr, float b1,
                            float b2, float eps, float c1, float c2);
+// Gradient corrector (corrector.hip). once, twice and cellbits are
+// consecutive [mask_words] bitmasks.
+struct CorrBufs {
+  uint32_t *once, *twice, *cellbits, *rank, *bsums, *count, *err;
+  uint32_t* cellp;  // [N] sphere of each cell node
+};
+hipError_t launch_corrector_cells(const Ctx& c, const double* X, double dmin, double dmax, const CorrBufs& b,
+                                  uint32_t* list, uint32_t* plist, uint32_t cap);
+hipError_t launch_corrector_features(const Ctx& c, const float* u, const uint32_t* list, const uint32_t* plist,
+                                     const uint32_t* count, uint32_t cap, const double* X, const double* U,
+                                     const double* Om, double u_rms, uint16_t* out);
+hipError_t launch_corrector_labels(const Ctx& c, const float* u, const uint32_t* key, const uint32_t* list, uint32_t n,
+                                   const double* X, const double* U, const double* Om, double u_rms, float* out);
+size_t corrector_stats_lds_bytes();
+// Writes (sum of eps corrected - eps plain, cells, per-bin sums) to out.
+hipError_t launch_corrector_stats(const Ctx& c, const float* theta, const float* u, const uint32_t* key,
+                                  const uint32_t* list, const uint32_t* plist, const uint32_t* count, uint32_t cap,
+                                  const double* X, const double* U, const double* Om, double u_rms, int nbins,
+                                  double* part, double* out);
+// Node keys only (see stats_device.hpp).
+hipError_t launch_stats_keys(const Ctx& c, uint32_t* key, int nbins, double width, const double* X);
 hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t* key, int nbins, double width,
                         const double* X, const double* U, const double* Om, double* part, double* out);
 

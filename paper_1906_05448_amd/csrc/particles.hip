@@ -138,16 +138,24 @@ k_release_average(const float* __restrict__ u, Dims d, const double* __restrict_
 template <int STORE>
 __global__ void __launch_bounds__(256)
 k_release_overwrite(typename Pop<STORE>::T* f, Dims d, const uint32_t* __restrict__ owner,
-                    const double* __restrict__ X, const double* __restrict__ rad, const double* __restrict__ U) {
+                    const double* __restrict__ X, const double* __restrict__ rad, const double* __restrict__ U,
+                    const double* __restrict__ Om) {
   const uint32_t p = blockIdx.x;
-  const Box b = make_box(X + 3 * p, rad[p] + 1.0);
+  const double* Xp = X + 3 * p;
+  const double* W = Om + 3 * p;
+  const Box b = make_box(Xp, rad[p] + 1.0);
   const uint32_t cnt = b.count();
-  const float ux = (float)U[3 * p], uy = (float)U[3 * p + 1], uz = (float)U[3 * p + 2];
   for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
     int x, y, z;
     box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     if (owner[n] != p) continue;
+    // rigid-body velocity U + Omega x (x - X), minimum image
+    const double r0 = min_image((double)x - Xp[0], d.nx), r1 = min_image((double)y - Xp[1], d.ny),
+                 r2 = min_image((double)z - Xp[2], d.nz);
+    const float ux = (float)(U[3 * p] + (W[1] * r2 - W[2] * r1));
+    const float uy = (float)(U[3 * p + 1] + (W[2] * r0 - W[0] * r2));
+    const float uz = (float)(U[3 * p + 2] + (W[0] * r1 - W[1] * r0));
     float dr = 0.0f;
     for (int k = 0; k < kQ; ++k) dr += Pop<STORE>::load(f + (size_t)k * d.N + n);
     const float rho = 1.0f + dr;
@@ -175,14 +183,14 @@ hipError_t launch_release_average(const Ctx& c, const float* u, double* Uout) {
   return hipGetLastError();
 }
 
-hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U) {
+hipError_t launch_release_overwrite(const Ctx& c, void* f, const uint32_t* owner, const double* U, const double* Om) {
   if (c.np <= 0) return hipSuccess;
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL(k_release_overwrite<0>, dim3(c.np), dim3(256), 0, c.stream, (float*)f, c.dims, owner,
-                       c.P.X[c.pcur], c.P.r, U);
+                       c.P.X[c.pcur], c.P.r, U, Om);
   else
     hipLaunchKernelGGL(k_release_overwrite<1>, dim3(c.np), dim3(256), 0, c.stream, (_Float16*)f, c.dims, owner,
-                       c.P.X[c.pcur], c.P.r, U);
+                       c.P.X[c.pcur], c.P.r, U, Om);
   return hipGetLastError();
 }
 

@@ -19,15 +19,13 @@
 //   reduce   one workgroup per column adds the per-block partials in order
 #include "device_util.hpp"
 #include "internal.hpp"
+#include "stats_device.hpp"
 
 namespace lbm {
 
 namespace {
 
 constexpr int kSBlock = 256;
-constexpr uint32_t kKeyWall = 0u;
-constexpr uint32_t kKeyFluid = 0x80000000u;
-constexpr uint32_t kKeyFar = 0xFFFFFFFFu;
 
 __device__ __forceinline__ bool binned_bin(double d, double width, int nbins, uint32_t& b) {
   if (!(d < (double)nbins * width)) return false;
@@ -81,89 +79,6 @@ k_stats_spheres(const double* __restrict__ X, const double* __restrict__ rad, Di
   }
 }
 
-struct Neigh {
-  uint32_t c, xm, xp, ym, yp, zm, zp;
-  int x, y, z;
-};
-
-__device__ __forceinline__ Neigh neighbours(uint32_t n, const Dims& d) {
-  Neigh g;
-  node_coords(n, d.nx, d.ny, g.x, g.y, g.z);
-  g.c = n;
-  const int xm = g.x == 0 ? d.nx - 1 : g.x - 1, xp = g.x == d.nx - 1 ? 0 : g.x + 1;
-  const int ym = g.y == 0 ? d.ny - 1 : g.y - 1, yp = g.y == d.ny - 1 ? 0 : g.y + 1;
-  const int zm = g.z == 0 ? d.nz - 1 : g.z - 1, zp = g.z == d.nz - 1 ? 0 : g.z + 1;
-  g.xm = node_index(xm, g.y, g.z, d.nx, d.ny);
-  g.xp = node_index(xp, g.y, g.z, d.nx, d.ny);
-  g.ym = node_index(g.x, ym, g.z, d.nx, d.ny);
-  g.yp = node_index(g.x, yp, g.z, d.nx, d.ny);
-  g.zm = node_index(g.x, g.y, zm, d.nx, d.ny);
-  g.zp = node_index(g.x, g.y, zp, d.nx, d.ny);
-  return g;
-}
-
-// Velocity source: the raw field, or the field masked by the key.
-struct RawVel {
-  const float* u;
-  uint32_t N;
-  __device__ void at(uint32_t n, double v[3]) const {
-    v[0] = u[n];
-    v[1] = u[(size_t)N + n];
-    v[2] = u[2 * (size_t)N + n];
-  }
-};
-
-struct MaskedVel {
-  const float* u;
-  const uint32_t* key;
-  const double *X, *U, *Om;
-  Dims d;
-  __device__ void at(uint32_t n, double v[3]) const {
-    const uint32_t k = key[n];
-    if (k >= kKeyFluid) {
-      v[0] = u[n];
-      v[1] = u[(size_t)d.N + n];
-      v[2] = u[2 * (size_t)d.N + n];
-      return;
-    }
-    if (k == kKeyWall) {
-      v[0] = v[1] = v[2] = 0.0;
-      return;
-    }
-    const uint32_t p = k - 1u;
-    int x, y, z;
-    node_coords(n, d.nx, d.ny, x, y, z);
-    const double r[3] = {min_image((double)x - X[3 * p], d.nx), min_image((double)y - X[3 * p + 1], d.ny),
-                         min_image((double)z - X[3 * p + 2], d.nz)};
-    const double* w = Om + 3 * p;
-    v[0] = U[3 * p] + (w[1] * r[2] - w[2] * r[1]);
-    v[1] = U[3 * p + 1] + (w[2] * r[0] - w[0] * r[2]);
-    v[2] = U[3 * p + 2] + (w[0] * r[1] - w[1] * r[0]);
-  }
-};
-
-// eps = 2 nu s_ij s_ij with G_ij = d_j u_i by central differences.
-template <class V>
-__device__ __forceinline__ double dissipation(const V& vel, const Neigh& g, double nu) {
-  double a[3], b[3], G[3][3];
-  vel.at(g.xp, a);
-  vel.at(g.xm, b);
-  for (int i = 0; i < 3; ++i) G[i][0] = 0.5 * (a[i] - b[i]);
-  vel.at(g.yp, a);
-  vel.at(g.ym, b);
-  for (int i = 0; i < 3; ++i) G[i][1] = 0.5 * (a[i] - b[i]);
-  vel.at(g.zp, a);
-  vel.at(g.zm, b);
-  for (int i = 0; i < 3; ++i) G[i][2] = 0.5 * (a[i] - b[i]);
-  double ss = 0.0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      const double s = 0.5 * (G[i][j] + G[j][i]);
-      ss += s * s;
-    }
-  return 2.0 * nu * ss;
-}
-
 __global__ void __launch_bounds__(kSBlock)
 k_stats_raw(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key, Dims d,
             double nu, double* __restrict__ part, int stride) {
@@ -205,13 +120,6 @@ k_stats_raw(const float* __restrict__ u, const float* __restrict__ rho, const ui
       if (k != kStatUmax2) out[k] = s[k];
     out[kStatUmax2] = mx[0];
   }
-}
-
-__device__ __forceinline__ double readlane_d(double v, int src) {
-  const unsigned long long b = __double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Histograms: lane l of a wavefront owns bins l, l + 64, ...; the binned
@@ -319,7 +227,21 @@ k_stats_reduce(const double* __restrict__ part, int nblocks, int stride, double*
 }  // namespace
 
 size_t stats_part_bytes() {
-  return ((size_t)kStatGrid * kStatStride + kStatStride) * sizeof(double);
+  // per-block partials, the statistics sums, the corrector sums
+  return ((size_t)kStatGrid * kStatStride + 2 * kStatStride) * sizeof(double);
+}
+
+hipError_t launch_stats_keys(const Ctx& c, uint32_t* key, int nbins, double width, const double* X) {
+  const Dims& d = c.dims;
+  hipLaunchKernelGGL(k_stats_key, dim3((d.N + kSBlock - 1) / kSBlock), dim3(kSBlock), 0, c.stream, d, c.cfg.wall,
+                     c.cfg.pipe_radius, c.cfg.pipe_cx, c.cfg.pipe_cy, nbins, width, key);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (c.np > 0) {
+    hipLaunchKernelGGL(k_stats_spheres, dim3(c.np), dim3(kSBlock), 0, c.stream, X, c.P.r, d, nbins, width, key);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t* key, int nbins, double width,
@@ -328,14 +250,8 @@ hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t
   const double nu = (c.cfg.tau - 0.5) / 3.0;
   const int stride = kStatScalars + 5 * nbins;
   const int grid = (int)std::min<uint32_t>((uint32_t)kStatGrid, (d.N + kSBlock - 1) / kSBlock);
-  hipLaunchKernelGGL(k_stats_key, dim3((d.N + kSBlock - 1) / kSBlock), dim3(kSBlock), 0, c.stream, d, c.cfg.wall,
-                     c.cfg.pipe_radius, c.cfg.pipe_cx, c.cfg.pipe_cy, nbins, width, key);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_stats_keys(c, key, nbins, width, X);
   if (e != hipSuccess) return e;
-  if (c.np > 0) {
-    hipLaunchKernelGGL(k_stats_spheres, dim3(c.np), dim3(kSBlock), 0, c.stream, X, c.P.r, d, nbins, width, key);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_stats_raw, dim3(grid), dim3(kSBlock), 0, c.stream, u, rho, key, d, nu, part, stride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (nbins <= 64)

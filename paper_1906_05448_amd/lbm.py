@@ -17,7 +17,7 @@ _lib = None
 BC_NONE, BC_IBB, BC_IBM = 0, 1, 2
 STORE_F32, STORE_F16S = 0, 1
 WALL_NONE, WALL_PIPE_Z = 0, 1
-SET_STATE, RELEASE = 0, 1
+SET_STATE, RELEASE, SET_RIGID = 0, 1, 2
 MOTION_FREE, MOTION_FIXED, MOTION_PRESCRIBED = 0, 1, 2
 KERNEL_CLASSES = ("stream_collide", "geometry", "ibb_links", "refill", "ibm_prepass", "ibm_forcing",
                   "particle", "stats", "corrector")
@@ -55,6 +55,7 @@ class _CStats(ctypes.Structure):
         ("eps_raw", ctypes.c_double), ("eps_masked", ctypes.c_double), ("eps_fluid", ctypes.c_double),
         ("umax", ctypes.c_double), ("bulk_u", ctypes.c_double),
         ("particle_ke", ctypes.c_double), ("particle_ke_rot", ctypes.c_double),
+        ("eps_fluid_corrected", ctypes.c_double), ("n_corrected", ctypes.c_int64),
     ]
 
 
@@ -90,6 +91,10 @@ def lib() -> ctypes.CDLL:
         "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
+        "lbm_corrector_cells": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P,
+                                                ctypes.POINTER(I64)]),
+        "lbm_corrector_labels": (ctypes.c_int, [P, P, I64, ctypes.c_double, P]),
+        "lbm_corrector_set": (ctypes.c_int, [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "lbm_mlp_workspace_size": (SZ, []),
         "lbm_mlp_init": (ctypes.c_int, [P, SZ, P, P, ctypes.POINTER(P)]),
         "lbm_mlp_set_params": (ctypes.c_int, [P, P]),
@@ -284,16 +289,52 @@ class Lattice:
 
     def stats(self, nbins: int = 32, bin_width: float = 0.25) -> dict:
         """Statistics of the current snapshot (lbm_stats): a dict with the
-        lbm_stats_t fields (momentum as an array) and "hist" [5][nbins]
-        (count, sum 1/2|u|^2, sum eps, sum u_z, sum u_z^2 per distance bin)."""
+        lbm_stats_t fields (momentum as an array) and "hist" [6][nbins]
+        (count, sum 1/2|u|^2, sum eps, sum u_z, sum u_z^2, sum corrected eps
+        per distance bin)."""
         out = _CStats()
-        hist = np.zeros((5, max(int(nbins), 0)), np.float64)
+        hist = np.zeros((6, max(int(nbins), 0)), np.float64)
         _check(lib().lbm_stats(self._h, int(nbins), float(bin_width), ctypes.byref(out),
                                hist.ctypes.data_as(ctypes.c_void_p) if nbins > 0 else None), "lbm_stats")
         d = {name: getattr(out, name) for name, _ in _CStats._fields_}
         d["momentum"] = np.array(list(out.momentum))
         d["hist"] = hist
         return d
+
+    # -- gradient corrector ---------------------------------------------
+    def corrector_cells(self, u_rms, d_min=0.0, d_max=10.0, cap=None, features=True):
+        """(nodes int32, spheres int32, features bf16 [n, 96] or None) of the
+        interface cells, as torch CUDA tensors."""
+        t = self._torch
+        if cap is None:
+            n = ctypes.c_int64()
+            st = lib().lbm_corrector_cells(self._h, d_min, d_max, u_rms, 0, None, None, None, ctypes.byref(n))
+            if st not in (0, -3):
+                _check(st, "lbm_corrector_cells")
+            cap = n.value
+        node = t.empty(max(cap, 1), dtype=t.int32, device=self.device)
+        part = t.empty(max(cap, 1), dtype=t.int32, device=self.device)
+        x = t.empty((max(cap, 1), MLP_IN_STRIDE), dtype=t.bfloat16, device=self.device) if features else None
+        n = ctypes.c_int64()
+        _check(lib().lbm_corrector_cells(self._h, d_min, d_max, u_rms, cap, _dev(node), _dev(part),
+                                         _dev(x) if features else None, ctypes.byref(n)), "lbm_corrector_cells")
+        k = n.value
+        return node[:k], part[:k], (x[:k] if features else None)
+
+    def corrector_labels(self, nodes, u_rms):
+        """[n, 16] float32 CUDA labels at the given nodes (int32 CUDA tensor)."""
+        t = self._torch
+        n = int(nodes.shape[0])
+        out = t.empty((max(n, 1), MLP_OUT_STRIDE), dtype=t.float32, device=self.device)
+        _check(lib().lbm_corrector_labels(self._h, _dev(nodes) if n else None, n, u_rms, _dev(out)),
+               "lbm_corrector_labels")
+        return out[:n]
+
+    def corrector_set(self, mlp=None, d_min=0.0, d_max=10.0, u_rms=0.03) -> None:
+        """Attach an Mlp for stats() (None detaches); keeps a reference."""
+        self._corrector = mlp
+        ptr = lib().lbm_mlp_device_params(mlp._h) if mlp is not None else None
+        _check(lib().lbm_corrector_set(self._h, ptr, d_min, d_max, u_rms), "lbm_corrector_set")
 
     # -- time stepping -------------------------------------------------
     def step(self, n: int = 1) -> None:

@@ -1,0 +1,139 @@
+"""Parity of the HIP gradient-corrector plumbing with the FP64 oracle:
+rigid-interior particle setting, interface cells (bit-exact), features
+(to BF16 rounding), training labels, and the corrected statistics."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import corrector as oc
+from oracle import mlp as om
+from oracle import stats as ostats
+from oracle.sim import SET_RIGID, Config as OConfig, Sim as OSim
+from paper_1906_05448_amd import lbm
+from tests.helpers import gpu_config, gpu_lattice, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (56, 48, 52)
+R = 6.0
+RD = 0.4
+URMS = 0.03
+X0 = np.array([[14.0, 14.5, 15.0], [28.6, 14.9, 15.2], [40.0, 34.0, 36.0], [54.0, 3.0, 48.5]])
+U0 = np.array([[0.01, 0.0, -0.005], [0.0, 0.012, 0.0], [-0.008, 0.006, 0.004], [0.003, -0.002, 0.002]])
+W0 = np.array([[0.001, 0.0, 0.0], [0.0, 0.0, -0.0015], [0.0005, 0.001, 0.0], [0.0, 0.0012, 0.0]])
+
+
+def _lattice(bc, store=0, tau=0.55):
+    cfg = gpu_config(nx=SHAPE[0], ny=SHAPE[1], nz=SHAPE[2], tau=tau, bc=bc, ibm_retraction=RD if bc == 2 else 0.0,
+                     store=store, max_particles=4, max_radius=R)
+    return cfg, gpu_lattice(cfg)
+
+
+def _field(seed=3):
+    return synth.hit_field(synth.hit_spectrum(seed=seed, u_rms=URMS, kcut=10), SHAPE)
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_set_rigid_matches_oracle(bc):
+    cfg, g = _lattice(bc)
+    o = OSim(OConfig(shape=SHAPE, tau=0.55, bc="ibb" if bc == 1 else "ibm", ibm_retraction=RD if bc == 2 else 0.0))
+    u0 = _field()
+    g.set_fields(u0)
+    o.set_fields(u0)
+    g.set_particles(X0, R, u=U0, omega=W0, mode=lbm.SET_RIGID, motion=lbm.MOTION_PRESCRIBED)
+    o.set_particles(X0, U=U0, Om=W0, r=np.full(4, R), mode=SET_RIGID, motion="prescribed")
+    for nsteps in (0, 5):
+        g.step(nsteps)
+        o.step(nsteps)
+        fluid = o.fluid_mask()  # the spheres move
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        assert rel_l2(ug, uo, fluid) < 1e-5, nsteps
+    g.close()
+
+
+def test_cells_and_features_exact_input():
+    cfg, g = _lattice(2)
+    g.set_fields(_field())
+    g.set_particles(X0, R, u=U0, omega=W0, mode=lbm.SET_RIGID, motion=lbm.MOTION_PRESCRIBED)
+    g.step(6)
+    X, U, W = g.get_particles()
+    u, _ = g.get_fields()
+    for dmin, dmax in ((0.0, 10.0), (0.3, 1.1)):
+        nodes, parts, x = g.corrector_cells(URMS, dmin, dmax)
+        flat, part = oc.interface_cells(SHAPE, X, np.full(4, R), RD, dmin, dmax)
+        assert np.array_equal(nodes.cpu().numpy(), flat)
+        assert np.array_equal(parts.cpu().numpy(), part)
+        if dmin == 0.0:
+            assert len(flat) > 3000 and set(part.tolist()) == {0, 1, 2, 3}
+        F = oc.features(u.astype(np.float64), flat, part, X, U, W, np.full(4, R), URMS, SHAPE)
+        xg = x.float().cpu().numpy()
+        assert np.all(xg[:, 85:] == 0.0)
+        err = np.abs(xg[:, :85] - F)
+        assert np.all(err <= 2.0 ** -8 * np.abs(F) + 1e-6), err.max()
+    # capacity: too small a buffer is reported with the needed count
+    n_all = len(oc.interface_cells(SHAPE, X, np.full(4, R), RD, 0.0, 10.0)[0])
+    with pytest.raises(lbm.LbmError):
+        g.corrector_cells(URMS, 0.0, 10.0, cap=n_all - 1)
+    g.close()
+
+
+def test_labels_exact_input_on_bounce_back_field():
+    cfg, g = _lattice(1)
+    g.set_fields(_field(4))
+    g.set_particles(X0, R, u=U0, omega=W0, mode=lbm.SET_RIGID, motion=lbm.MOTION_PRESCRIBED)
+    g.step(8)
+    X, U, W = g.get_particles()
+    u, _ = g.get_fields()
+    flat, part = oc.interface_cells(SHAPE, X, np.full(4, R), RD, 0.0, 10.0)
+    import torch
+    nodes = torch.from_numpy(flat.astype(np.int32)).cuda()
+    t = g.corrector_labels(nodes, URMS).cpu().numpy()
+    owner, _ = ostats.classify(SHAPE, X, np.full(4, R))
+    T = oc.labels(u.astype(np.float64), owner, X, U, W, flat, URMS, SHAPE)
+    assert np.all(t[:, 9:] == 0.0)
+    assert rel_l2(t[:, :9], T) < 1e-6
+    g.close()
+
+
+def test_corrected_statistics_exact_input():
+    """The fused statistics kernel against the oracle statistics given the
+    network outputs of the same features (lbm_mlp_forward)."""
+    cfg, g = _lattice(2)
+    g.set_fields(_field(5))
+    g.set_particles(X0, R, u=U0, omega=W0, mode=lbm.SET_RIGID, motion=lbm.MOTION_PRESCRIBED)
+    g.step(4)
+    theta = synth.mlp_initial_params(2) * 0.3
+    net = lbm.Mlp(theta)
+    g.corrector_set(net, 0.0, 10.0, URMS)
+    s = g.stats(nbins=16)
+    nodes, parts, x = g.corrector_cells(URMS, 0.0, 10.0)
+    y = net.forward(x).cpu().numpy()[:, :9].astype(np.float64)
+    X, U, W = g.get_particles()
+    u, rho = g.get_fields()
+    flat = nodes.cpu().numpy().astype(np.int64)
+    o = ostats.statistics(u.astype(np.float64), rho.astype(np.float64), (0.55 - 0.5) / 3, SHAPE, X, U, W,
+                          np.full(4, R), None, nbins=16, corrected=(flat, y * URMS))
+    assert s["n_corrected"] == o["n_corrected"] == len(flat)
+    assert abs(s["eps_fluid_corrected"] - o["eps_fluid_corrected"]) <= 1e-9 * o["eps_fluid_corrected"]
+    assert abs(s["eps_fluid"] - o["eps_fluid"]) <= 1e-10 * o["eps_fluid"]
+    assert np.allclose(s["hist"][5], o["hist"][5], rtol=1e-9, atol=1e-9 * np.abs(o["hist"][5]).max())
+    assert np.array_equal(s["hist"][0], o["hist"][0])
+    # a network that predicts the rigid rotation of sphere 0 everywhere: its
+    # dissipation is zero, so the corrected cells contribute nothing
+    A = np.array([[0, -W0[0, 2], W0[0, 1]], [W0[0, 2], 0, -W0[0, 0]], [-W0[0, 1], W0[0, 0], 0]])
+    th = np.zeros(om.N_PARAMS)
+    th[-9:] = A.ravel() / URMS
+    net.set_params(th)
+    s2 = g.stats(nbins=16)
+    o2 = ostats.statistics(u.astype(np.float64), rho.astype(np.float64), (0.55 - 0.5) / 3, SHAPE, X, U, W,
+                           np.full(4, R), None, nbins=16,
+                           corrected=(flat, np.broadcast_to(th[-9:].astype(np.float32) * URMS, (len(flat), 9))))
+    assert abs(s2["eps_fluid_corrected"] - o2["eps_fluid_corrected"]) <= 1e-9 * o2["eps_fluid_corrected"]
+    assert s2["eps_fluid_corrected"] < s2["eps_fluid"]
+    g.corrector_set(None)
+    s3 = g.stats(nbins=16)
+    assert s3["n_corrected"] == 0 and s3["eps_fluid_corrected"] == s3["eps_fluid"]
+    assert np.array_equal(s3["hist"][5], s3["hist"][2])
+    net.close()
+    g.close()

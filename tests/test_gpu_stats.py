@@ -155,7 +155,7 @@ def test_stats_argument_errors_and_empty_histogram():
         with pytest.raises(lbm.LbmError):
             g.stats(nbins=nb, bin_width=w)
     s = g.stats(nbins=0)
-    assert s["hist"].shape == (5, 0) and s["n_fluid"] == 16 ** 3
+    assert s["hist"].shape == (6, 0) and s["n_fluid"] == 16 ** 3
     assert s["ke_raw"] == 0.0 and s["eps_raw"] == 0.0 and abs(s["mass"] - 16 ** 3) < 1e-9
     s = g.stats(nbins=lbm.STATS_MAX_BINS)
     assert s["hist"][0].sum() == 0  # no surface: nothing binned
