@@ -210,7 +210,7 @@ typedef struct {
  * 0) receives per bin the node count and the sums of 1/2 |u|^2, eps (of the
  * masked field), u_z, u_z^2 and the corrected eps. With a corrector attached
  * (lbm_corrector_set), eps at its interface cells is recomputed from the
- * predicted gradient (eps_fluid_corrected, hist row 5). Uses the idle
+ * corrected gradient (eps_fluid_corrected, hist row 5). Uses the idle
  * population buffer as scratch. Sync. Errors: LBM_E_ARG (nbins outside
  * 0 .. LBM_STATS_MAX_BINS, bin_width <= 0, out NULL), LBM_E_SIZE (corrector
  * zone larger than the lattice, or more interface cells than scratch). */
@@ -290,9 +290,13 @@ void lbm_mlp_destroy(lbm_mlp* mlp);
  * squared as ((dx dx + dy dy) + dz dz) and compared squared.
  * Features (85): for the 27 offsets o (z slowest, x fastest, each -1, 0, 1)
  * and components c, (u_c(x + o) - [U_p + Omega_p x (x + o - X_p)]_c) / u_rms
- * of the lattice field; then d; then (x - X_p) / |x - X_p|. Outputs and
- * labels (9): G_ij / u_rms = (d_j u_i) / u_rms, row-major in (i, j), labels
- * by central differences of the masked field (as lbm_stats). All three calls
+ * of the lattice field; then d; then (x - X_p) / |x - X_p|. Labels (9):
+ * G_ij / u_rms = (d_j u_i) / u_rms, row-major in (i, j), by central
+ * differences of the masked field (as lbm_stats). The network predicts the
+ * correction of the plain immersed-boundary gradient, y = (G_ref - G_plain) /
+ * u_rms with G_ref from a paired bounce-back run: its training targets are
+ * the bounce-back labels minus the immersed-boundary labels at the same
+ * cells, and the corrected gradient is G_plain + u_rms y. All three calls
  * require 2 (max_radius - r_d + 2 + sqrt(3)) + 3 <= min(nx, ny, nz)
  * (LBM_E_SIZE otherwise). */
 
@@ -304,10 +308,12 @@ void lbm_mlp_destroy(lbm_mlp* mlp);
 int lbm_corrector_cells(lbm_ctx* ctx, double d_min, double d_max, double u_rms, int64_t cap, int32_t* node_dev,
                         int32_t* particle_dev, uint16_t* x_dev, int64_t* n);
 
-/* Training labels at n given nodes (device int32): the masked central-
- * difference gradient of this lattice's field / u_rms into t_dev
- * ([n][16] FP32, entries 9..15 zero). Sync. */
-int lbm_corrector_labels(lbm_ctx* ctx, const int32_t* node_dev, int64_t n, double u_rms, float* t_dev);
+/* Labels at n given nodes (device int32): the masked central-difference
+ * gradient of this lattice's field / u_rms, written to t_dev ([n][16] FP32,
+ * entries 9..15 zero), or subtracted from its entries if subtract != 0 (the
+ * reference labels minus this lattice's: a training target). Sync. */
+int lbm_corrector_labels(lbm_ctx* ctx, const int32_t* node_dev, int64_t n, double u_rms, int32_t subtract,
+                         float* t_dev);
 
 /* Attaches a network for lbm_stats (params_dev: lbm_mlp_device_params(), must
  * stay valid while attached; NULL detaches) with the training range of d and

@@ -20,11 +20,15 @@ corrector is this build's addition; its readings:
   and the 3 components, (u(x + o) - [U_p + Omega_p x (x + o - X_p)]) / u_rms
   of the immersed-boundary field as it is; then d; then the unit normal
   (x - X_p) / |x - X_p|. Offsets are minimum-image.
-* Outputs (9): G_ij / u_rms = (d_j u_i) / u_rms, row-major in (i, j).
-* Labels: the same central-difference gradient of the paired bounce-back
-  field, masked by the rigid-body motion (Sec. 4.1).
+* Outputs (9): the correction of the plain gradient, (G_ref - G_plain) / u_rms
+  row-major in (i, j), G_ij = d_j u_i: G_plain is the central difference of
+  the masked immersed-boundary field, G_ref the same operator on the paired
+  bounce-back field (Sec. 4.1 masking). The corrected gradient is
+  G_plain + u_rms y. Predicting the correction rather than G itself keeps the
+  particle's rigid rotation, which the relative-velocity features cannot see,
+  inside G_plain.
 * Corrected dissipation: eps = 2 nu s_ij s_ij with s the symmetric part of
-  the predicted G at corrected cells, the plain masked value elsewhere.
+  the corrected G at corrected cells, the plain masked value elsewhere.
 
 Distances follow the classification recipe of the statistics: minimum-image
 offsets, squared distance ((dx dx + dy dy) + dz dz), comparisons on squared
@@ -111,9 +115,21 @@ def gradient_at(u_masked, flat, shape):
 
 
 def labels(u_pair, pair_owner, X, U, Om, flat, u_rms, shape):
-    """Targets: masked central-difference gradient of the paired field / u_rms."""
+    """Masked central-difference gradient of a field at the cells / u_rms
+    (of the bounce-back field: the reference; of the immersed-boundary field:
+    the plain gradient)."""
     um = stats.masked_velocity(u_pair, pair_owner, X, U, Om, shape)
     return gradient_at(um, flat, shape) / u_rms
+
+
+def targets(labels_ref, labels_plain):
+    """Training targets: the correction (G_ref - G_plain) / u_rms."""
+    return np.asarray(labels_ref, np.float64) - np.asarray(labels_plain, np.float64)
+
+
+def corrected_gradient(labels_plain, y, u_rms):
+    """G = G_plain + u_rms y from the plain labels (G_plain / u_rms)."""
+    return (np.asarray(labels_plain, np.float64) + np.asarray(y, np.float64)) * u_rms
 
 
 dissipation_from_gradient = stats.dissipation_from_gradient

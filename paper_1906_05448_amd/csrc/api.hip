@@ -1035,7 +1035,8 @@ int lbm_corrector_cells(lbm_ctx* h, double d_min, double d_max, double u_rms, in
   return count > ucap ? LBM_E_SIZE : LBM_OK;
 }
 
-int lbm_corrector_labels(lbm_ctx* h, const int32_t* node_dev, int64_t n, double u_rms, float* t_dev) {
+int lbm_corrector_labels(lbm_ctx* h, const int32_t* node_dev, int64_t n, double u_rms, int32_t subtract,
+                         float* t_dev) {
   if (!h || n < 0 || n > (int64_t)UINT32_MAX || !(u_rms > 0.0) || (n > 0 && (!node_dev || !t_dev))) return LBM_E_ARG;
   Ctx& c = h->c;
   const Scratch sc = scratch_layout(c);
@@ -1045,7 +1046,7 @@ int lbm_corrector_labels(lbm_ctx* h, const int32_t* node_dev, int64_t n, double 
   hipError_t e = launch_stats_keys(c, sc.key, 0, 1.0, c.P.X[pc]);
   if (e == hipSuccess)
     e = launch_corrector_labels(c, sc.u, sc.key, (const uint32_t*)node_dev, (uint32_t)n, c.P.X[pc], c.P.U[pc],
-                                c.P.Om[pc], u_rms, t_dev);
+                                c.P.Om[pc], u_rms, subtract != 0, t_dev);
   if (e != hipSuccess) return LBM_E_HIP;
   return drain_errors(c);
 }

@@ -12,7 +12,10 @@
 // Features (85 per cell, BF16 rows of 96): for the 27 offsets o, z slowest
 // and x fastest, and components c, (u_c(x + o) - [U_p + Omega_p x
 // (x + o - X_p)]_c) / u_rms; then d; then (x - X_p) / |x - X_p|. Labels:
-// central-difference G_ij = d_j u_i of the masked field, / u_rms, rows of 16.
+// central-difference G_ij = d_j u_i of the masked field, / u_rms, rows of 16
+// (written, or subtracted from what the rows hold: the training target is
+// the reference labels minus the plain immersed-boundary labels). The
+// network output y corrects the plain gradient: G = G_plain + u_rms y.
 // The statistics kernel gathers each wavefront's 16 cells' features into an
 // LDS tile, runs the network on the matrix cores, and adds eps(predicted G)
 // - eps(central difference) per cell, in a fixed order.
@@ -149,7 +152,7 @@ k_corr_features(const uint32_t* __restrict__ list, const uint32_t* __restrict__ 
 __global__ void __launch_bounds__(kCBlock)
 k_corr_labels(const uint32_t* __restrict__ list, uint32_t n, const float* __restrict__ u,
               const uint32_t* __restrict__ key, const double* __restrict__ X, const double* __restrict__ U,
-              const double* __restrict__ Om, Dims d, double u_rms, float* __restrict__ out) {
+              const double* __restrict__ Om, Dims d, double u_rms, int subtract, float* __restrict__ out) {
   const uint32_t i = blockIdx.x * kCBlock + threadIdx.x;
   if (i >= n) return;
   const MaskedVel vel{u, key, X, U, Om, d};
@@ -157,7 +160,10 @@ k_corr_labels(const uint32_t* __restrict__ list, uint32_t n, const float* __rest
   velocity_gradient(vel, neighbours(list[i], d), G);
   float* o = out + (size_t)i * kMlpOutPad;
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) o[3 * a + b] = (float)(G[a][b] / u_rms);
+    for (int b = 0; b < 3; ++b) {
+      const float g = (float)(G[a][b] / u_rms);
+      o[3 * a + b] = subtract ? o[3 * a + b] - g : g;
+    }
   for (int k = kMlpOut; k < kMlpOutPad; ++k) o[k] = 0.0f;
 }
 
@@ -169,7 +175,8 @@ struct CorrLds {
   double hs[kCBlock / 64][4 * 64];
 };
 
-// Sum over corrected cells of eps(predicted G) - eps(central difference),
+// Sum over corrected cells of eps(G_plain + u_rms y) - eps(G_plain), with
+// G_plain the central difference of the masked field,
 // their number and the per-bin sums. part: [gridDim.x][stride], columns
 // (sum, count, bins...).
 template <int SLOTS>
@@ -217,11 +224,12 @@ k_corr_stats(const float* __restrict__ theta, const uint32_t* __restrict__ list,
     uint32_t bin = 0;
     double delta = 0.0;
     if (grp == 0 && valid) {
-      double G[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) G[i][j] = (double)s.ys[wave][col][3 * i + j] * u_rms;
       const uint32_t node = list[ci];
-      delta = dissipation_of(G, nu) - dissipation(vel, neighbours(node, d), nu);
+      double Gp[3][3], G[3][3];
+      velocity_gradient(vel, neighbours(node, d), Gp);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i][j] = Gp[i][j] + (double)s.ys[wave][col][3 * i + j] * u_rms;
+      delta = dissipation_of(G, nu) - dissipation_of(Gp, nu);
       sum += delta;
       cnt += 1.0;
       const uint32_t k = key[node];
@@ -305,10 +313,11 @@ hipError_t launch_corrector_features(const Ctx& c, const float* u, const uint32_
 }
 
 hipError_t launch_corrector_labels(const Ctx& c, const float* u, const uint32_t* key, const uint32_t* list, uint32_t n,
-                                   const double* X, const double* U, const double* Om, double u_rms, float* out) {
+                                   const double* X, const double* U, const double* Om, double u_rms, int subtract,
+                                   float* out) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_corr_labels, dim3((n + kCBlock - 1) / kCBlock), dim3(kCBlock), 0, c.stream, list, n, u, key, X,
-                     U, Om, c.dims, u_rms, out);
+                     U, Om, c.dims, u_rms, subtract, out);
   return hipGetLastError();
 }
 

@@ -285,7 +285,8 @@ hipError_t launch_corrector_features(const Ctx& c, const float* u, const uint32_
                                      const uint32_t* count, uint32_t cap, const double* X, const double* U,
                                      const double* Om, double u_rms, uint16_t* out);
 hipError_t launch_corrector_labels(const Ctx& c, const float* u, const uint32_t* key, const uint32_t* list, uint32_t n,
-                                   const double* X, const double* U, const double* Om, double u_rms, float* out);
+                                   const double* X, const double* U, const double* Om, double u_rms, int subtract,
+                                   float* out);
 size_t corrector_stats_lds_bytes();
 // Writes (sum of eps corrected - eps plain, cells, per-bin sums) to out.
 hipError_t launch_corrector_stats(const Ctx& c, const float* theta, const float* u, const uint32_t* key,

@@ -93,7 +93,7 @@ def lib() -> ctypes.CDLL:
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
         "lbm_corrector_cells": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P,
                                                 ctypes.POINTER(I64)]),
-        "lbm_corrector_labels": (ctypes.c_int, [P, P, I64, ctypes.c_double, P]),
+        "lbm_corrector_labels": (ctypes.c_int, [P, P, I64, ctypes.c_double, I32, P]),
         "lbm_corrector_set": (ctypes.c_int, [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "lbm_mlp_workspace_size": (SZ, []),
         "lbm_mlp_init": (ctypes.c_int, [P, SZ, P, P, ctypes.POINTER(P)]),
@@ -321,12 +321,19 @@ class Lattice:
         k = n.value
         return node[:k], part[:k], (x[:k] if features else None)
 
-    def corrector_labels(self, nodes, u_rms):
-        """[n, 16] float32 CUDA labels at the given nodes (int32 CUDA tensor)."""
+    def corrector_labels(self, nodes, u_rms, subtract_from=None):
+        """[n, 16] float32 CUDA labels at the given nodes (int32 CUDA tensor);
+        with subtract_from (a label tensor, updated in place) its entries
+        minus this lattice's labels."""
         t = self._torch
         n = int(nodes.shape[0])
-        out = t.empty((max(n, 1), MLP_OUT_STRIDE), dtype=t.float32, device=self.device)
-        _check(lib().lbm_corrector_labels(self._h, _dev(nodes) if n else None, n, u_rms, _dev(out)),
+        if subtract_from is None:
+            out = t.empty((max(n, 1), MLP_OUT_STRIDE), dtype=t.float32, device=self.device)
+        else:
+            out = subtract_from
+            assert out.is_contiguous() and out.dtype == t.float32 and out.shape == (n, MLP_OUT_STRIDE)
+        _check(lib().lbm_corrector_labels(self._h, _dev(nodes) if n else None, n, u_rms,
+                                          0 if subtract_from is None else 1, _dev(out) if n else None),
                "lbm_corrector_labels")
         return out[:n]
 

@@ -93,12 +93,17 @@ def test_labels_exact_input_on_bounce_back_field():
     T = oc.labels(u.astype(np.float64), owner, X, U, W, flat, URMS, SHAPE)
     assert np.all(t[:, 9:] == 0.0)
     assert rel_l2(t[:, :9], T) < 1e-6
+    # subtract mode: the lattice's own labels cancel exactly
+    d = g.corrector_labels(nodes, URMS)
+    g.corrector_labels(nodes, URMS, subtract_from=d)
+    assert np.abs(d.cpu().numpy()).max() == 0.0
     g.close()
 
 
 def test_corrected_statistics_exact_input():
     """The fused statistics kernel against the oracle statistics given the
-    network outputs of the same features (lbm_mlp_forward)."""
+    network outputs of the same features (lbm_mlp_forward): corrected
+    gradient = plain masked central difference + u_rms y."""
     cfg, g = _lattice(2)
     g.set_fields(_field(5))
     g.set_particles(X0, R, u=U0, omega=W0, mode=lbm.SET_RIGID, motion=lbm.MOTION_PRESCRIBED)
@@ -112,25 +117,32 @@ def test_corrected_statistics_exact_input():
     X, U, W = g.get_particles()
     u, rho = g.get_fields()
     flat = nodes.cpu().numpy().astype(np.int64)
-    o = ostats.statistics(u.astype(np.float64), rho.astype(np.float64), (0.55 - 0.5) / 3, SHAPE, X, U, W,
-                          np.full(4, R), None, nbins=16, corrected=(flat, y * URMS))
+    owner, _ = ostats.classify(SHAPE, X, np.full(4, R))
+    plain = oc.labels(u.astype(np.float64), owner, X, U, W, flat, URMS, SHAPE)
+    nu = (0.55 - 0.5) / 3
+
+    def oracle(yy):
+        return ostats.statistics(u.astype(np.float64), rho.astype(np.float64), nu, SHAPE, X, U, W, np.full(4, R),
+                                 None, nbins=16, corrected=(flat, oc.corrected_gradient(plain, yy, URMS)))
+
+    o = oracle(y)
     assert s["n_corrected"] == o["n_corrected"] == len(flat)
     assert abs(s["eps_fluid_corrected"] - o["eps_fluid_corrected"]) <= 1e-9 * o["eps_fluid_corrected"]
     assert abs(s["eps_fluid"] - o["eps_fluid"]) <= 1e-10 * o["eps_fluid"]
     assert np.allclose(s["hist"][5], o["hist"][5], rtol=1e-9, atol=1e-9 * np.abs(o["hist"][5]).max())
     assert np.array_equal(s["hist"][0], o["hist"][0])
-    # a network that predicts the rigid rotation of sphere 0 everywhere: its
-    # dissipation is zero, so the corrected cells contribute nothing
-    A = np.array([[0, -W0[0, 2], W0[0, 1]], [W0[0, 2], 0, -W0[0, 0]], [-W0[0, 1], W0[0, 0], 0]])
+    # zero weights and biases: no correction at all, bit for bit
+    net.set_params(np.zeros(om.N_PARAMS))
+    s0 = g.stats(nbins=16)
+    assert s0["n_corrected"] == len(flat) and s0["eps_fluid_corrected"] == s0["eps_fluid"]
+    assert np.array_equal(s0["hist"][5], s0["hist"][2])
+    # biases only: a constant correction of every gradient
     th = np.zeros(om.N_PARAMS)
-    th[-9:] = A.ravel() / URMS
+    th[-9:] = np.linspace(-0.3, 0.5, 9)
     net.set_params(th)
-    s2 = g.stats(nbins=16)
-    o2 = ostats.statistics(u.astype(np.float64), rho.astype(np.float64), (0.55 - 0.5) / 3, SHAPE, X, U, W,
-                           np.full(4, R), None, nbins=16,
-                           corrected=(flat, np.broadcast_to(th[-9:].astype(np.float32) * URMS, (len(flat), 9))))
-    assert abs(s2["eps_fluid_corrected"] - o2["eps_fluid_corrected"]) <= 1e-9 * o2["eps_fluid_corrected"]
-    assert s2["eps_fluid_corrected"] < s2["eps_fluid"]
+    s1 = g.stats(nbins=16)
+    o1 = oracle(np.broadcast_to(th[-9:].astype(np.float32).astype(np.float64), (len(flat), 9)))
+    assert abs(s1["eps_fluid_corrected"] - o1["eps_fluid_corrected"]) <= 1e-9 * o1["eps_fluid_corrected"]
     g.corrector_set(None)
     s3 = g.stats(nbins=16)
     assert s3["n_corrected"] == 0 and s3["eps_fluid_corrected"] == s3["eps_fluid"]

@@ -105,6 +105,9 @@ def test_rigid_rotation_gives_zero_features_and_exact_labels():
     A = np.array([[0, -Om[2], Om[1]], [Om[2], 0, -Om[0]], [-Om[1], Om[0], 0]])
     assert np.allclose(T, np.broadcast_to(A.ravel() / 0.03, T.shape), rtol=0, atol=1e-13)
     assert np.abs(oc.dissipation_from_gradient(T * 0.03, 0.01)).max() < 1e-25
+    # identical paired fields: zero targets; a zero correction leaves G_plain
+    assert np.abs(oc.targets(T, T)).max() == 0.0
+    assert np.array_equal(oc.corrected_gradient(T, np.zeros_like(T), 0.03), T * 0.03)
 
 
 def _count_in_sphere(X, R, shape):
