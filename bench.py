@@ -4,10 +4,13 @@
 Workload (production case): 512^3 periodic decaying isotropic turbulence,
 D3Q19 MRT, tau 0.52, seeded random-phase field with E(k) ~ k^4 exp(-2 (k/4)^2)
 and u_rms 0.03, 6250 freely moving spheres of radius 8 (volume fraction
-~10%, density ratio 4 as in the paper's case) released into the field (velocity = fluid average over
-the particle, zero spin), soft-sphere contacts. A step is one full lbm_step:
-boundary treatment, fused stream + collide, particle forces and motion,
-geometry rebuild and refilling.
+~10%, density ratio 4 as in the paper's case) released into the field
+(velocity = fluid average over the particle, zero spin), soft-sphere
+contacts. A step is one full lbm_step: boundary treatment, fused stream +
+collide, particle forces and motion, geometry rebuild and refilling; every
+--stats-every steps the FP64 statistics (lbm_stats) run inside the timed
+region too, with the learned corrector in the ibmc variant (trained at
+start on paired 64^3 runs through the same library).
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value        million lattice-node updates per second (MLUPS) over all N
@@ -18,6 +21,10 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   cpu_baseline the FP64 oracle, single-threaded, on a bounded sample of the
                same recipe on this host
   variants     every variant measured (boundary treatment x storage)
+  corrector    training throughput of the corrector network, MFMA
+               utilisation of its kernels, and its held-out gain
+  cpu_baseline also carries error_vs_fp64: relative L2 of the FP32 and FP16
+               velocity fields against the oracle on the same sample
 """
 import argparse
 import json
@@ -52,20 +59,37 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--n", type=int, default=512, help="lattice edge (production: 512)")
     p.add_argument("--particles", type=int, default=6250)
-    p.add_argument("--variants", default="ibb-f16s,ibb-f32,ibm-f16s,ibm-f32,none-f16s,none-f32",
-                   help="comma list of <bc>-<store>, bc in ibb|ibm|none, store in f16s|f32; the first is the "
-                        "headline")
+    p.add_argument("--variants", default="ibb-f16s,ibb-f32,ibm-f16s,ibmc-f16s,ibm-f32,none-f16s,none-f32",
+                   help="comma list of <bc>-<store>, bc in ibb|ibm|ibmc (immersed boundary with the learned "
+                        "corrector in the statistics)|none, store in f16s|f32; the first is the headline")
+    p.add_argument("--stats-every", type=int, default=100, help="steps between lbm_stats calls (0: none)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     return p.parse_args()
 
 
-def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup):
+def advance(lat, steps, every):
+    """steps time steps with lbm_stats every `every` steps; returns the last
+    statistics (or None)."""
+    s = None
+    done = 0
+    while done < steps:
+        k = steps - done if every <= 0 else min(every, steps - done)
+        lat.step(k)
+        done += k
+        if every > 0 and done % every == 0:
+            s = lat.stats(nbins=32)
+    return s
+
+
+def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=None):
     cfg = lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store, bc=bc, ibm_retraction=IBM_RD,
                      max_particles=len(X) if bc != lbm.BC_NONE else 0, max_radius=RADIUS)
     lat = lbm.Lattice(cfg)
     lat.set_fields_device(u0_dev)
     if bc != lbm.BC_NONE and len(X):
         lat.set_particles(X, RADIUS, rho_p=RHO_P, mode=lbm.RELEASE, motion=lbm.MOTION_FREE)
+    if corr is not None:
+        lat.corrector_set(corr, 0.0, 10.0, U_RMS)
     solid, links = lat.geometry_counts() if bc == lbm.BC_IBB else (0, 0)
     lat.step(warmup)
     lat.sync()
@@ -74,14 +98,14 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup):
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    lat.step(steps)
+    st = advance(lat, steps, every)
     t1.record(stream)
     torch.cuda.synchronize()
     lat.sync()
     ms = t0.elapsed_time(t1)
     # Second pass with per-kernel events for the roofline of the dominant kernel.
     lat.profile_enable(True)
-    lat.step(steps)
+    advance(lat, steps, every)
     prof = lat.profile_read()
     lat.profile_enable(False)
     lat.sync()
@@ -99,10 +123,78 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup):
     # boundary (8 bytes per 32 nodes).
     alg_bytes = 38 * s * N + (N // 4 if bc == lbm.BC_IBM else 0)
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
-    return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
-                kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes, achieved_gbs=achieved,
-                solid_nodes=solid, links=links,
-                kernels_ms_per_step={k: v[0] / max(v[1], 1) * v[1] / steps for k, v in prof.items() if v[1]})
+    out = dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
+               kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes, achieved_gbs=achieved,
+               solid_nodes=solid, links=links,
+               kernels_ms_per_step={k: v[0] / steps for k, v in prof.items() if v[1]})
+    if st is not None:
+        out["stats"] = {k: st[k] for k in ("ke_masked", "eps_fluid", "eps_fluid_corrected", "n_corrected",
+                                            "particle_ke")}
+    return out
+
+
+def train_corrector(torch, lbm):
+    """Trains the gradient corrector on paired 64^3 runs (seeds 0-1) through
+    the library and measures its held-out gain (seed 7) and the throughput
+    and MFMA utilisation of the network kernels."""
+    from paper_1906_05448_amd import corrector
+    import synth
+    cfg = corrector.PairConfig()
+    parts = [corrector.paired_samples(cfg, s) for s in (0, 1)]
+    x = torch.cat([p[0] for p in parts])
+    t = torch.cat([p[1] for p in parts])
+    net = lbm.Mlp(synth.mlp_initial_params(0))
+    steps, batch = 1500, 4096
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    losses = corrector.train(net, x, t, steps=steps, batch=batch, lr=1e-3, seed=0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    # network kernels alone: gradient (forward + backward) and forward of one
+    # large batch, timed on the stream with no host work in between
+    xb, tb = x[:batch].contiguous(), t[:batch].contiguous()
+    xf = x.repeat(8, 1).contiguous()
+    e0.record(stream)
+    for _ in range(50):
+        if lbm.lib().lbm_mlp_gradient(net._h, lbm._dev(xb), lbm._dev(tb), batch, None, None) != 0:
+            raise RuntimeError("lbm_mlp_gradient failed")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    grad_ms = e0.elapsed_time(e1) / 50
+    e0.record(stream)
+    for _ in range(10):
+        y = net.forward(xf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    xe, te, tbe = corrector.paired_samples(cfg, 7)
+    y = net.forward(xe)
+    nu = (cfg.tau - 0.5) / 3
+
+    def eps(G):  # 2 nu s_ij s_ij per row of u_rms-scaled gradients (evaluation only)
+        G = G[:, :9].double().reshape(-1, 3, 3) * cfg.u_rms
+        S = 0.5 * (G + G.transpose(1, 2))
+        return 2 * nu * (S * S).sum((1, 2))
+
+    e_ref, e_ibm, e_cor = eps(te + tbe), eps(tbe), eps(tbe + y)
+    err_plain = float(torch.linalg.norm(e_ibm - e_ref) / torch.linalg.norm(e_ref))
+    err_corr = float(torch.linalg.norm(e_cor - e_ref) / torch.linalg.norm(e_ref))
+    # matrix-core work actually issued per sample (padded shapes 96-64-64-16):
+    # forward 2 (96*64 + 64*64 + 64*16) flop, gradient about 3x that
+    fwd_flop = 2 * (96 * 64 + 64 * 64 + 64 * 16)
+    peak = 2.5e15
+    info = dict(train_samples=int(x.shape[0]), steps=steps, batch=batch,
+                train_samples_per_s=round(steps * batch / (train_ms * 1e-3), 1),
+                loss_first=round(float(losses[:10].mean()), 5), loss_last=round(float(losses[-100:].mean()), 5),
+                heldout_eps_rel_l2_plain_ibm=round(err_plain, 4), heldout_eps_rel_l2_corrected=round(err_corr, 4),
+                gradient_kernel_ms_batch4096=round(grad_ms, 4),
+                gradient_mfma_util=round(3 * fwd_flop * batch / (grad_ms * 1e-3) / peak, 5),
+                forward_ms=round(fwd_ms, 4), forward_samples=int(xf.shape[0]),
+                forward_mfma_util=round(fwd_flop * xf.shape[0] / (fwd_ms * 1e-3) / peak, 5))
+    log(f"bench: corrector {info}")
+    return net, info
 
 
 def cpu_baseline():
@@ -129,9 +221,39 @@ def cpu_baseline():
         t = time.perf_counter()
         sim.step(steps)
         dt = time.perf_counter() - t
-    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{n}^3 box of the same recipe with 12 spheres r=8 (bounce-back, FP64), {steps} steps, "
-                       f"{dt:.1f} s, numpy single thread")
+    out = dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+               sample=f"{n}^3 box of the same recipe with 12 spheres r=8 (bounce-back, FP64), {steps} steps, "
+                      f"{dt:.1f} s, numpy single thread")
+    out["error_vs_fp64"] = gpu_error_vs_oracle(sim, u0, X, steps + 2)
+    return out
+
+
+def gpu_error_vs_oracle(sim, u0, X, steps):
+    """The same sample on the GPU in FP32 and FP16 storage: relative L2 of the
+    velocity over fluid nodes and relative error of the fluid dissipation
+    against the FP64 oracle state (the metric's error column)."""
+    from oracle import stats as ostats
+    from paper_1906_05448_amd import lbm
+    n = sim.cfg.shape[0]
+    uo, ro = sim.fields()
+    P = sim.state.P
+    nu = (TAU - 0.5) / 3
+    so = ostats.statistics(uo, ro, nu, sim.cfg.shape, P.X, P.U, P.Om, P.r, P.rho, nbins=0)
+    fluid = sim.fluid_mask()
+    res = {"steps": steps}
+    for name, store in (("f32", lbm.STORE_F32), ("f16s", lbm.STORE_F16S)):
+        lat = lbm.Lattice(lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store, bc=lbm.BC_IBB,
+                                     max_particles=len(X), max_radius=RADIUS))
+        lat.set_fields(u0)
+        lat.set_particles(X, RADIUS, rho_p=RHO_P, mode=lbm.RELEASE, motion=lbm.MOTION_FREE)
+        lat.step(steps)
+        ug, _ = lat.get_fields()
+        sg = lat.stats(nbins=0)
+        lat.close()
+        du = (ug.astype(np.float64) - uo)[:, fluid]
+        res[name] = {"u_rel_l2": float(np.linalg.norm(du) / np.linalg.norm(uo[:, fluid])),
+                     "eps_fluid_rel": float(abs(sg["eps_fluid"] - so["eps_fluid"]) / so["eps_fluid"])}
+    return res
 
 
 def main():
@@ -147,9 +269,13 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.n
-    bcs = {"ibb": lbm.BC_IBB, "ibm": lbm.BC_IBM, "none": lbm.BC_NONE}
+    bcs = {"ibb": lbm.BC_IBB, "ibm": lbm.BC_IBM, "ibmc": lbm.BC_IBM, "none": lbm.BC_NONE}
     stores = {"f32": lbm.STORE_F32, "f16s": lbm.STORE_F16S}
     variants = [v.split("-") for v in args.variants.split(",")]
+    net, cinfo = None, None
+    if any(bc == "ibmc" for bc, _ in variants):
+        log("bench: training the gradient corrector on paired 64^3 runs")
+        net, cinfo = train_corrector(torch, lbm)
     log(f"bench: {n}^3 seeded turbulence field and {args.particles} sphere centres")
     spec = synth.hit_spectrum(seed=0, u_rms=U_RMS)
     u0 = torch.from_numpy(synth.hit_field(spec, (n, n, n), dtype=np.float32)).cuda()
@@ -158,7 +284,8 @@ def main():
     for bc, st in variants:
         name = f"{bc}-{st}"
         log(f"bench: variant {name}: warmup {args.warmup}, timed {args.steps} steps")
-        results[name] = run_variant(torch, lbm, n, bcs[bc], stores[st], u0, X, args.steps, args.warmup)
+        results[name] = run_variant(torch, lbm, n, bcs[bc], stores[st], u0, X, args.steps, args.warmup,
+                                    args.stats_every, net if bc == "ibmc" else None)
         r = results[name]
         log(f"bench: {name}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, stream_collide "
             f"{r['kernel_avg_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s; per step {r['kernels_ms_per_step']}")
@@ -185,7 +312,9 @@ def main():
                    "density_ratio": RHO_P,
                    "boundary": {"ibb": "interpolated bounce-back (quadratic, fallback chain, refill)",
                                 "ibm": f"immersed boundary, r_d={IBM_RD}, 1+2 forcing passes, Kempe inertia",
+                                "ibmc": f"immersed boundary, r_d={IBM_RD}, with the learned gradient corrector",
                                 "none": "no particles"}[hb],
+                   "stats_every": args.stats_every,
                    "storage": {"f16s": "FP16 shifted populations, FP32 collision",
                                "f32": "FP32 shifted populations"}[hs]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
@@ -195,6 +324,8 @@ def main():
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
     }
+    if cinfo is not None:
+        out["corrector"] = cinfo
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a bounded CPU sample")
         out["cpu_baseline"] = cpu_baseline()
