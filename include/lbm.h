@@ -172,7 +172,7 @@ int lbm_get_links(lbm_ctx* ctx, int64_t cap, int32_t* node, int32_t* dir, int32_
  * Sync. */
 int lbm_geometry_counts(lbm_ctx* ctx, int64_t* solid_nodes, int64_t* links);
 
-/* Statistics of the current snapshot (Sec. 4). Every sum is FP64, reduced
+/* Statistics of the current snapshot (Sec. 3.2). Every sum is FP64, reduced
  * in a fixed order (bit-reproducible). Means are over all N nodes (raw and
  * masked) or over the N_f fluid nodes (*_fluid, bulk_u). A node is inside
  * sphere p iff its periodic minimum-image squared distance to X_p is below
@@ -180,13 +180,13 @@ int lbm_geometry_counts(lbm_ctx* ctx, int64_t* solid_nodes, int64_t* links);
  * (x - cx)^2 + (y - cy)^2 >= R^2 (the wall wins).
  *   ke = 1/2 <|u|^2>; eps = 2 nu <s_ij s_ij>, nu = (tau - 1/2)/3, with
  *   s_ij = (d_i u_j + d_j u_i)/2 by periodic central differences
- *   (Sec. 4.1; the paper evaluates them spectrally).
+ *   (Sec. 3.2.1; the paper evaluates them spectrally).
  *   masked: u replaced by U_p + Omega_p x (x - X_p) inside particles and by
  *   0 inside the wall; raw: the lattice field as it is (not a physical field
  *   inside bounce-back solids).
  *   umax: max |u| over fluid nodes; bulk_u: <u_z> over fluid nodes (pipe).
  *   particle_ke = 1/2 sum m |U|^2, particle_ke_rot = 1/2 sum I |Omega|^2,
- *   m = rho_p 4/3 pi r^3, I = 2/5 m r^2 (Sec. 4.3). */
+ *   m = rho_p 4/3 pi r^3, I = 2/5 m r^2 (Sec. 3.2.2). */
 typedef struct {
   int64_t step;
   int64_t n_nodes, n_fluid;
@@ -204,7 +204,7 @@ typedef struct {
 #define LBM_STATS_MAX_BINS 256
 
 /* Computes the statistics of the current field and particle state. Local
- * profiles (Sec. 4.2): fluid node x falls in bin floor(d / bin_width) of
+ * profiles (Sec. 3.2.1): fluid node x falls in bin floor(d / bin_width) of
  * d = min(min_p |x - X_p| - r_p, R - |x_perp - c| with a pipe), if that bin
  * is below nbins. hist (host, [6][nbins], may be NULL; ignored if nbins is
  * 0) receives per bin the node count and the sums of 1/2 |u|^2, eps (of the
@@ -219,7 +219,7 @@ int lbm_stats(lbm_ctx* ctx, int32_t nbins, double bin_width, lbm_stats_t* out, d
 /* ---- Gradient-corrector network ----------------------------------------
  * The paper finds the immersed boundary smears near-surface velocity
  * gradients, so the local dissipation next to particles differs from the
- * bounce-back result (Sec. 4.2, conclusions). The corrector maps the
+ * bounce-back result (Sec. 3.2.1, Sec. 4). The corrector maps the
  * neighbourhood of an interface cell to its velocity gradient: a multilayer
  * perceptron 85 -> 64 -> 64 -> 9 with SiLU activations,
  *   z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, h2 = silu(z2),

@@ -6,7 +6,7 @@ baseline use this module.
 
 The paper observes that the immersed boundary method smears the velocity
 gradient next to the surface, so the local dissipation there differs from
-the interpolated bounce-back result (Sec. 4.2, Figs. 9-10, conclusions). The
+the interpolated bounce-back result (Sec. 3.2.1, Sec. 4). The
 corrector is this build's addition; its readings:
 
 * Interface cells of sphere p: fluid nodes with r_p <= |x - X_p| <
@@ -23,7 +23,7 @@ corrector is this build's addition; its readings:
 * Outputs (9): the correction of the plain gradient, (G_ref - G_plain) / u_rms
   row-major in (i, j), G_ij = d_j u_i: G_plain is the central difference of
   the masked immersed-boundary field, G_ref the same operator on the paired
-  bounce-back field (Sec. 4.1 masking). The corrected gradient is
+  bounce-back field (Sec. 3.2.1 masking). The corrected gradient is
   G_plain + u_rms y. Predicting the correction rather than G itself keeps the
   particle's rigid rotation, which the relative-velocity features cannot see,
   inside G_plain.

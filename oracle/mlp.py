@@ -5,7 +5,7 @@ Test infrastructure: only the tests, the smoke check and the benchmark's CPU
 baseline use this module.
 
 The paper motivates a correction of the near-surface velocity gradients of
-the immersed boundary method (Sec. 4.2 and the conclusions) without
+the immersed boundary method (Sec. 3.2.1 and Sec. 4) without
 specifying one. Reading: a multilayer perceptron 85 -> 64 -> 64 -> 9 with
 SiLU activations,
     z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, h2 = silu(z2),

@@ -5,18 +5,18 @@ host energy spectra.
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU
 baseline use this module.
 
-* Kinetic energy (Sec. 4.1, Fig. 6): 1/2 <|u|^2> over the lattice.
-* Dissipation rate (Sec. 4.1): eps = 2 nu <s_ij s_ij>, s_ij = (d_i u_j +
+* Kinetic energy (Sec. 3.2.1): 1/2 <|u|^2> over the lattice.
+* Dissipation rate (Sec. 3.2.1): eps = 2 nu <s_ij s_ij>, s_ij = (d_i u_j +
   d_j u_i) / 2. The paper evaluates global statistics spectrally; here the
   velocity gradient is the second-order central difference on the periodic
   lattice, d_x u(x) = (u(x + e_x) - u(x - e_x)) / 2 (reading; the GPU path
   uses the same operator, so the two are comparable).
-* Masking (Sec. 4.1): inside a particle the velocity is replaced by the
+* Masking (Sec. 3.2.1): inside a particle the velocity is replaced by the
   rigid-body motion U + Omega x (x - X) before averaging and differencing;
   inside the pipe wall by zero. Unmasked values use the lattice field as it
   is (meaningful for the immersed boundary method, whose interior fluid
   evolves, and for runs without particles).
-* Local profiles (Sec. 4.2, Figs. 9-10): fluid nodes binned by their distance
+* Local profiles (Sec. 3.2.1): fluid nodes binned by their distance
   to the nearest surface, d(x) = min over particles of (|x - X_p| - r_p) and,
   with a pipe, R - |x_perp - c|; every node is counted once, in the bin
   floor(d / width). Per bin: node count and the sums of 1/2 |u|^2, eps (of
@@ -26,9 +26,9 @@ baseline use this module.
   handles, eps from the symmetric part of the supplied gradient instead of
   the central difference; eps_fluid_corrected and a sixth histogram row
   (sum of corrected eps) report it, equal to the plain values without one.
-* Particle energies (Sec. 4.3): 1/2 sum m |U|^2 and 1/2 sum I |Omega|^2 with
+* Particle energies (Sec. 3.2.2): 1/2 sum m |U|^2 and 1/2 sum I |Omega|^2 with
   m = rho_p 4/3 pi r^3, I = 2/5 m r^2.
-* Spectra (Sec. 4.1, Table 2): E(k) by integer-shell binning of 1/2 |u_hat|^2,
+* Spectra (Sec. 3.2.1, Table 2): E(k) by integer-shell binning of 1/2 |u_hat|^2,
   D(k) = 2 nu k^2 E(k).
 
 A node is inside sphere p iff its minimum-image squared distance (summed as
@@ -41,7 +41,7 @@ import numpy as np
 
 from .geometry import dist2, min_image
 
-BIN_WIDTH = 0.25  # distance bins of a quarter lattice spacing (Sec. 4.2)
+BIN_WIDTH = 0.25  # distance bins of a quarter lattice spacing (Sec. 3.2.1)
 
 
 def node_coords(shape):

@@ -1,7 +1,7 @@
 """Training data and training loop of the near-surface gradient corrector.
 
 Pairing (reading; the paper motivates a correction of the immersed-boundary
-near-surface gradients, Sec. 4.2 and conclusions, without specifying one):
+near-surface gradients, Sec. 3.2.1 and Sec. 4, without specifying one):
 a bounce-back run (lattice A) carries the reference; from each of its
 snapshots an immersed-boundary run (lattice B) starts with the same field
 and the same particles, their interiors reset to the rigid-body motion;

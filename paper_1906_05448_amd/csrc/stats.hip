@@ -1,8 +1,8 @@
-// stats.hip - statistics of one snapshot (Sec. 4): kinetic energy and
+// stats.hip - statistics of one snapshot (Sec. 3.2): kinetic energy and
 // dissipation rate 2 nu <s_ij s_ij> (central differences), raw, masked by
 // the rigid-body motion inside particles (zero in the pipe wall), and over
 // fluid nodes; mass and momentum of the fluid; local profiles binned by the
-// distance to the nearest surface (Sec. 4.2). Per-node arithmetic is FP64 on
+// distance to the nearest surface (Sec. 3.2.1). Per-node arithmetic is FP64 on
 // the FP32 velocity field and every sum is reduced in a fixed order, so the
 // result does not change from run to run.
 //
