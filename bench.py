@@ -48,6 +48,37 @@ IBM_RD = 0.4           # Breugem retraction, the variant the paper recommends
 MIN_GAP = 2.0          # centre distance >= 2r + 2 at placement
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_traffic_512cubed.md")
+TRAFFIC_SOURCES = ("paper_1906_05448_amd/csrc/dense.hip", "paper_1906_05448_amd/csrc/d3q19.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(variant):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    rec = {}
+    for ln in lines:
+        parts = ln.strip().strip("`").split()
+        if len(parts) == 3 and parts[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            rec[(parts[0], parts[1])] = parts[2]
+    if rec.get(("source_sha256", "dense")) != kernel_source_hash():
+        return None
+    v = rec.get(("traffic_bytes_per_launch", variant))
+    return int(v) if v is not None else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -131,6 +162,31 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
         out["stats"] = {k: st[k] for k in ("ke_masked", "eps_fluid", "eps_fluid_corrected", "n_corrected",
                                             "particle_ke")}
     return out
+
+
+def copy_calibration(torch):
+    """A plain device-to-device copy of 2 GiB (the runtime's copy kernel):
+    the achievable streaming bandwidth next to the 8 TB/s peak, and the
+    known-size reference for scaling HBM byte counters."""
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * 4 * n
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n, "ms": round(ms, 4),
+            "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
 
 
 def train_corrector(torch, lbm):
@@ -280,6 +336,8 @@ def main():
     spec = synth.hit_spectrum(seed=0, u_rms=U_RMS)
     u0 = torch.from_numpy(synth.hit_field(spec, (n, n, n), dtype=np.float32)).cuda()
     X = synth.random_spheres(args.particles, (n, n, n), 2 * RADIUS + MIN_GAP, seed=0)
+    copy = copy_calibration(torch)
+    log(f"bench: device copy {copy}")
     results = {}
     for bc, st in variants:
         name = f"{bc}-{st}"
@@ -318,9 +376,11 @@ def main():
                    "storage": {"f16s": "FP16 shifted populations, FP32 collision",
                                "f32": "FP32 shifted populations"}[hs]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(head_name),
                      "kernel": "k_stream_collide", "alg_bytes_per_launch": head["alg_bytes"],
                      "avg_launch_ms": round(head["kernel_avg_ms"], 4)},
+        "stream_copy": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
     }

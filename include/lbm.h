@@ -85,7 +85,9 @@ typedef struct {
 void lbm_config_default(lbm_config* cfg);
 
 /* Bytes of device workspace a context with this configuration needs.
- * Errors: LBM_E_ARG for an invalid configuration. */
+ * Errors: LBM_E_ARG for an invalid configuration; LBM_E_SIZE if
+ * N = nx*ny*nz exceeds 2^31 - 1, or 2^30 with FP32 storage (one population
+ * array must stay within 4 GiB). */
 int lbm_workspace_size(const lbm_config* cfg, size_t* bytes);
 
 /* Creates a context on the current HIP device. workspace: device pointer,

@@ -228,6 +228,8 @@ int check_config(const lbm_config* c) {
   if (c->nx < 4 || c->ny < 4 || c->nz < 4) return LBM_E_ARG;
   const double N = (double)c->nx * (double)c->ny * (double)c->nz;
   if (N > 2147483647.0) return LBM_E_SIZE;
+  // one direction array must be addressable with a 32-bit byte offset
+  if (c->store == LBM_STORE_F32 && N > 1073741824.0) return LBM_E_SIZE;
   if (!(c->tau > 0.5) || !isfinite(c->tau)) return LBM_E_ARG;
   if (!rate_ok(c->s_e) || !rate_ok(c->s_eps) || !rate_ok(c->s_q) || !rate_ok(c->s_pi) || !rate_ok(c->s_m))
     return LBM_E_ARG;

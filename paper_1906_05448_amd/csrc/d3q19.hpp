@@ -70,7 +70,7 @@ __device__ __forceinline__ void mrt_collide(float (&g)[kQ], float Fx, float Fy, 
   const float jx = d1 + (d4 + d5) + (d6 + d7);
   const float jy = d2 + (d4 - d5) + (d8 + d9);
   const float jz = d3 + (d6 - d7) + (d8 - d9);
-  const float inv_rho = 1.0f / rho;
+  const float inv_rho = __builtin_amdgcn_rcpf(rho);  // hardware reciprocal, 1 ulp
   const float ux = (jx + 0.5f * Fx) * inv_rho;
   const float uy = (jy + 0.5f * Fy) * inv_rho;
   const float uz = (jz + 0.5f * Fz) * inv_rho;

@@ -27,10 +27,10 @@ __device__ __forceinline__ Tile tile_coords(const Dims& d) {
   const uint32_t logical = (b & 7u) * d.per_xcd + (b >> 3);
   Tile t;
   t.live = logical < d.ntiles;
-  const uint32_t bx = logical % d.gx;
-  const uint32_t rest = logical / d.gx;
-  const uint32_t by = rest % d.gy;
-  const uint32_t bz = rest / d.gy;
+  const uint32_t rest = fast_div(d.div_gx, logical);
+  const uint32_t bx = logical - rest * d.gx;
+  const uint32_t bz = fast_div(d.div_gy, rest);
+  const uint32_t by = rest - bz * d.gy;
   t.x = (int)(bx * 64u + (threadIdx.x & 63u));
   t.y = (int)(by * 4u + (threadIdx.x >> 6));
   t.z = (int)bz;
@@ -89,16 +89,24 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
       r00 + xp, rp0 + x, r0p + x,                                   // 10..12
       rp0 + xp, rm0 + xp, r0p + xp, r0m + xp, rpp + x, rpm + x};   // 13..18
 
+  // Direction i lives at the uniform base A + i N; the node offset in bytes
+  // fits 32 bits (N * sizeof(T) <= 4 GiB is checked at init), so each access
+  // is a scalar base plus one 32-bit vector offset.
+  using T = typename P::T;
   float g[kQ];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) g[i] = P::load(A + (size_t)i * N + src[i]);
+  for (int i = 0; i < kQ; ++i) {
+    const char* base = (const char*)(A + (size_t)i * N);
+    g[i] = P::load((const T*)(base + src[i] * (uint32_t)sizeof(T)));
+  }
 
   float rho, ux, uy, uz;
   mrt_collide(g, F.x, F.y, F.z, r, rho, ux, uy, uz);
 
   const uint32_t n = r00 + (uint32_t)x;
+  const uint32_t noff = n * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) P::store(B + (size_t)i * N + n, g[i]);
+  for (int i = 0; i < kQ; ++i) P::store((T*)((char*)(B + (size_t)i * N) + noff), g[i]);
 
   const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
   if (bad) atomicOr(err, kErrUnstable);

@@ -27,12 +27,37 @@ enum : uint32_t { kSchemeHalfway = 0, kSchemeLinear = 1, kSchemeQuadratic = 2 };
 // 64 x 4 threads (one wavefront per 64-node x-run); the flat block id is
 // remapped so that consecutive tiles land on the same XCD (the hardware deals
 // workgroups round-robin over the 8 XCDs, each with its own L2).
+// Unsigned division by an invariant divisor d >= 1 with one multiply-high
+// (Granlund & Montgomery 1994, round-up method):
+//   l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+//   q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = mulhi(m, n),
+// exact for every 32-bit n.
+struct FastDiv {
+  uint32_t m, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < (unsigned long long)d) ++l;
+  FastDiv f;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 0 ? l - 1 : 0;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fast_div(const FastDiv& f, uint32_t n) {
+  const uint32_t t = __umulhi(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 struct Dims {
   int nx, ny, nz;
   uint32_t N;       // nodes
   uint32_t gx, gy;  // tiles along x (64 wide) and y (4 tall)
   uint32_t ntiles;  // gx * gy * nz
   uint32_t per_xcd; // ceil(ntiles / 8)
+  FastDiv div_gx, div_gy;
 };
 
 inline Dims make_dims(int nx, int ny, int nz) {
@@ -45,6 +70,8 @@ inline Dims make_dims(int nx, int ny, int nz) {
   d.gy = (uint32_t)(ny + 3) / 4;
   d.ntiles = d.gx * d.gy * (uint32_t)nz;
   d.per_xcd = (d.ntiles + 7) / 8;
+  d.div_gx = make_fastdiv(d.gx);
+  d.div_gy = make_fastdiv(d.gy);
   return d;
 }
 
