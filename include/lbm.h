@@ -71,7 +71,9 @@ typedef struct {
   int32_t ibm_iters;         /* forcing passes after the first prediction;
                                 the paper uses 2 (Sec. 2.1)                  */
   int32_t store;             /* LBM_STORE_*                                  */
-  int32_t wall;              /* LBM_WALL_*                                   */
+  int32_t wall;              /* LBM_WALL_*; with LBM_BC_IBM the wall carries
+                                static ring markers and no particles may be
+                                set                                          */
   double pipe_radius, pipe_cx, pipe_cy; /* pipe wall, lattice units         */
   int32_t max_particles;     /* capacity reserved in the workspace           */
   double max_radius;         /* largest sphere radius that will be set       */

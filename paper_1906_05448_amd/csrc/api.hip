@@ -77,6 +77,50 @@ uint32_t wall_link_count(const lbm_config& c) {
   return (uint32_t)(n * (uint64_t)c.nz);
 }
 
+// Immersed-boundary pipe wall (Sec. 2.1): rings at every integer z of
+// N_theta = round(2 pi r_L) markers (ties to even), retracted into the wall,
+// r_L = R + r_d; theta_k = 2 pi k / N_theta; volume 2 pi r_L / N_theta.
+bool ibm_wall(const lbm_config& c) { return c.bc == LBM_BC_IBM && c.wall == LBM_WALL_PIPE_Z; }
+
+int pipe_ring_count(const lbm_config& c) {
+  return (int)std::nearbyint(2.0 * M_PI * (c.pipe_radius + c.ibm_retraction));
+}
+
+void pipe_markers(const lbm_config& c, std::vector<double>& xm, double& dV) {
+  const double r_l = c.pipe_radius + c.ibm_retraction;
+  const int n = pipe_ring_count(c);
+  xm.clear();
+  xm.reserve((size_t)3 * n * c.nz);
+  for (int z = 0; z < c.nz; ++z)
+    for (int k = 0; k < n; ++k) {
+      const double th = (2.0 * M_PI) * (double)k / (double)n;
+      xm.push_back(c.pipe_cx + r_l * cos(th));
+      xm.push_back(c.pipe_cy + r_l * sin(th));
+      xm.push_back((double)z);
+    }
+  dV = 2.0 * M_PI * r_l / (double)n;
+}
+
+// Union of the 4x4x4 delta stencils of the wall markers; returns its size.
+uint32_t pipe_support(const lbm_config& c, const std::vector<double>& xm, std::vector<uint32_t>& bits) {
+  const size_t N = (size_t)c.nx * c.ny * c.nz;
+  bits.assign((N + 31) / 32, 0u);
+  auto wrap = [](long v, int n) { return (int)(((v % n) + n) % n); };
+  for (size_t l = 0; l < xm.size() / 3; ++l) {
+    long b[3];
+    for (int k = 0; k < 3; ++k) b[k] = (long)floor(xm[3 * l + k]) - 1;
+    for (int jz = 0; jz < 4; ++jz)
+      for (int jy = 0; jy < 4; ++jy)
+        for (int jx = 0; jx < 4; ++jx) {
+          const size_t n = ((size_t)wrap(b[2] + jz, c.nz) * c.ny + wrap(b[1] + jy, c.ny)) * c.nx + wrap(b[0] + jx, c.nx);
+          bits[n >> 5] |= 1u << (n & 31);
+        }
+  }
+  uint32_t cnt = 0;
+  for (uint32_t w : bits) cnt += (uint32_t)__builtin_popcount(w);
+  return cnt;
+}
+
 // Immersed boundary marker layout (Uhlmann/Breugem count and a Fibonacci
 // lattice of directions; the paper only asks for a marker volume close to
 // the cell volume, Sec. 2.1).
@@ -151,8 +195,8 @@ struct Plan {
   uint32_t link_cap, wl_count;
   // immersed boundary
   size_t ib_bits[2], ib_rank[2], ib_count, ib_fib[2], ib_shared, ib_list, ib_us, ib_bsum, ib_dirs, ib_rowbits,
-      ib_fcount, ib_fslot;
-  uint32_t s_cap, fcap, n_markers;
+      ib_fcount, ib_fslot, ib_wmark, ib_wdF, ib_wsup;
+  uint32_t s_cap, fcap, n_markers, n_wall, wall_support;
   int side;
   size_t total;
 };
@@ -198,7 +242,15 @@ Plan plan(const lbm_config& c) {
     uint32_t forcing = 1, full = 1;
     if (P) ibm_support_bounds(c.max_radius, c.ibm_retraction, forcing, full);
     p.fcap = forcing;
-    p.s_cap = (uint32_t)std::min<uint64_t>((uint64_t)N, (uint64_t)P * full + 4096);
+    if (ibm_wall(c)) {
+      std::vector<double> xm;
+      std::vector<uint32_t> wb;
+      double dV = 0.0;
+      pipe_markers(c, xm, dV);
+      p.n_wall = (uint32_t)(xm.size() / 3);
+      p.wall_support = pipe_support(c, xm, wb);
+    }
+    p.s_cap = (uint32_t)std::min<uint64_t>((uint64_t)N, (uint64_t)P * full + p.wall_support + 4096);
     p.n_markers = P ? (uint32_t)marker_count(c.max_radius - c.ibm_retraction) : 0;
     p.side = P ? ibm_box_side(c.max_radius, c.ibm_retraction) : 0;
     const size_t rows = (size_t)p.side * p.side;
@@ -216,6 +268,9 @@ Plan plan(const lbm_config& c) {
     p.ib_rowbits = take(P * rows * 4 + 4);
     p.ib_fcount = take(P * 4 + 4);
     p.ib_fslot = take(P * (size_t)p.fcap * 4 + 4);
+    p.ib_wmark = take((size_t)p.n_wall * 3 * sizeof(double) + 8);
+    p.ib_wdF = take((size_t)p.n_wall * 3 * sizeof(float) + 4);
+    p.ib_wsup = take(p.n_wall ? words * 4 : 4);
   }
   p.total = off;
   return p;
@@ -238,9 +293,7 @@ int check_config(const lbm_config* c) {
   if (c->store != LBM_STORE_F32 && c->store != LBM_STORE_F16S) return LBM_E_ARG;
   if (c->bc != LBM_BC_NONE && c->bc != LBM_BC_IBB && c->bc != LBM_BC_IBM) return LBM_E_ARG;
   if (c->bc == LBM_BC_IBM) {
-    // The immersed boundary runs on spheres here; its box (side 2 R_b + 2)
-    // must fit a 32-bit row mask.
-    if (c->wall != LBM_WALL_NONE) return LBM_E_ARG;
+    // A sphere's box (side 2 R_b + 2) must fit a 32-bit row mask.
     if (!(c->ibm_retraction >= 0.0) || c->ibm_retraction > 2.0) return LBM_E_ARG;
     if (c->max_particles > 0) {
       if (!(c->max_radius - c->ibm_retraction > 1.0)) return LBM_E_ARG;
@@ -318,9 +371,11 @@ hipError_t step_ibm(Ctx& c) {
   const int pc = c.pcur, pn = 1 - c.pcur;
   hipError_t e = timed(c, LBM_K_IBM_PREPASS, [&] { return launch_ibm_prepass(c, c.f_cur); });
   if (e != hipSuccess) return e;
-  if (c.np > 0) {
+  if (c.np > 0 || c.ibm.n_wall > 0) {
     e = timed(c, LBM_K_IBM_FORCING, [&] { return launch_ibm_forcing_pass(c, c.P.X[pc], c.P.U[pc], c.P.Om[pc]); });
     if (e != hipSuccess) return e;
+  }
+  if (c.np > 0) {
     e = timed(c, LBM_K_PARTICLE, [&] {
       hipError_t r = launch_ibm_kempe(c, c.P.X[pc], c.P.Iu_new, c.P.IL_new);
       if (r == hipSuccess) r = launch_particle_update(c);
@@ -501,6 +556,10 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     m.side = p.side;
     m.R_b = (p.side - 2) / 2;
     m.cur = m.last = 0;
+    m.n_wall = p.n_wall;
+    m.wmark = (double*)(base + p.ib_wmark);
+    m.wdF = (float*)(base + p.ib_wdF);
+    m.wsup = (uint32_t*)(base + p.ib_wsup);
     if (has_particles(*cfg)) {
       int lds_max = 0;
       if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) != hipSuccess ||
@@ -550,13 +609,24 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.np = 0;
     e = zero_particle_accumulators(c);
   }
-  if (e == hipSuccess && cfg->bc == LBM_BC_IBM) {
+  if (e == hipSuccess && cfg->bc == LBM_BC_IBM && c.ibm.n_wall == 0) {
     // empty support until particles are set
     for (int b = 0; b < 2 && e == hipSuccess; ++b) {
       e = hipMemsetAsync(c.ibm.bits[b], 0, words * 4, c.stream);
       if (e == hipSuccess) e = hipMemsetAsync(c.ibm.rank[b], 0, words * 4, c.stream);
       if (e == hipSuccess) e = hipMemsetAsync(c.ibm.count[b], 0, sizeof(uint32_t), c.stream);
     }
+  }
+  std::vector<double> wxm;
+  std::vector<uint32_t> wbits;
+  if (e == hipSuccess && c.ibm.n_wall) {
+    // static pipe-wall markers and their support, in both support buffers
+    pipe_markers(*cfg, wxm, c.ibm.wdV);
+    (void)pipe_support(*cfg, wxm, wbits);
+    e = hipMemcpyAsync(c.ibm.wmark, wxm.data(), wxm.size() * sizeof(double), hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c.ibm.wsup, wbits.data(), wbits.size() * 4, hipMemcpyHostToDevice, c.stream);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = launch_ibm_support_build(c, b, nullptr);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
   if (e != hipSuccess) {

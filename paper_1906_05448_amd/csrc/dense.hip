@@ -45,7 +45,14 @@ struct IbView {
   const uint32_t* rank;
   const float* fib;  // [3][s_cap]
   uint32_t s_cap;
+  const uint32_t* nobody;  // nodes without body force (outside a pipe), or null
 };
+
+// Body force at node n: none where the mask says so.
+__device__ __forceinline__ float3 body_force_at(const IbView& v, uint32_t n, float3 F0) {
+  if (v.nobody && ((v.nobody[n >> 5] >> (n & 31u)) & 1u)) return make_float3(0.0f, 0.0f, 0.0f);
+  return F0;
+}
 
 __device__ __forceinline__ void add_ib_force(const IbView& v, uint32_t n, float3& F) {
   const uint32_t w = v.bits[n >> 5];
@@ -70,7 +77,11 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
   if (!t.live) return;
   const int x = t.x, y = t.y, z = t.z;
   float3 F = F0;
-  if (MODE == 2) add_ib_force(ib, ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x, F);
+  if (MODE == 2) {
+    const uint32_t n0 = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
+    F = body_force_at(ib, n0, F0);
+    add_ib_force(ib, n0, F);
+  }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -133,7 +144,10 @@ k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F0, Ib
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
   float3 F = F0;
-  if (MODE == 2) add_ib_force(ib, n, F);
+  if (MODE == 2) {
+    F = body_force_at(ib, n, F0);
+    add_ib_force(ib, n, F);
+  }
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -171,7 +185,7 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 // the node turns fluid.
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
-  const IbView none{nullptr, nullptr, nullptr, 0};
+  const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
                        c.rates, c.body_force, none, c.err);
@@ -184,7 +198,7 @@ hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
 hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
   const int b = c.ibm.cur;
-  const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap};
+  const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap, ibm_body_force_mask(c)};
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_stream_collide<0, 2>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
                        c.rates, c.body_force, ib, c.err);
@@ -197,7 +211,7 @@ hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
 hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho) {
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
-  const IbView none{nullptr, nullptr, nullptr, 0};
+  const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_fields<0, 0>), grid, block, 0, c.stream, (const float*)f, N, F, none, u, rho);
   else
@@ -210,7 +224,7 @@ hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float*
 hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, float* rho) {
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
-  const IbView ib{c.ibm.bits[buf], c.ibm.rank[buf], c.ibm.fib[buf], c.ibm.s_cap};
+  const IbView ib{c.ibm.bits[buf], c.ibm.rank[buf], c.ibm.fib[buf], c.ibm.s_cap, ibm_body_force_mask(c)};
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_fields<0, 2>), grid, block, 0, c.stream, (const float*)f, N, c.body_force, ib, u, rho);
   else

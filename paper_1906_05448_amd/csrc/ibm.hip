@@ -250,11 +250,14 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
 // -------------------------------------------------------------- prepass --
 template <int STORE>
 __global__ void __launch_bounds__(256)
-k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F, const uint32_t* __restrict__ list,
-              const uint32_t* __restrict__ count, uint32_t s_cap, float4* __restrict__ us, float* __restrict__ fib) {
+k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, const uint32_t* __restrict__ nobody,
+              const uint32_t* __restrict__ list, const uint32_t* __restrict__ count, uint32_t s_cap,
+              float4* __restrict__ us, float* __restrict__ fib) {
   const uint32_t s = blockIdx.x * 256u + threadIdx.x;
   if (s >= *count || s >= s_cap) return;
   const uint32_t n = list[s];
+  // no body force outside the pipe (the virtual fluid there is not driven)
+  const float3 F = (nobody && ((nobody[n >> 5] >> (n & 31u)) & 1u)) ? make_float3(0.0f, 0.0f, 0.0f) : F0;
   int x, y, z;
   node_coords(n, d.nx, d.ny, x, y, z);
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
@@ -480,6 +483,72 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   }
 }
 
+// ----------------------------------------------------------------- wall --
+// Static pipe-wall markers (rings at every integer z, desired velocity 0),
+// one thread per marker. A pass is split in two launches so every marker
+// interpolates the same velocity before any spread lands: interpolate and
+// store dF = 2 (0 - U_l), then spread dF delta dV with global atomics.
+__device__ __forceinline__ void wall_stencil(const double* __restrict__ xm, uint32_t l, int b[3], float w[3][4]) {
+  for (int k = 0; k < 3; ++k) {
+    const double X = xm[3 * l + k];
+    b[k] = (int)floor(X) - 1;
+    for (int j = 0; j < 4; ++j) w[k][j] = peskin((float)(X - (double)(b[k] + j)));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_ibm_wall_interp(const double* __restrict__ xm, uint32_t nm, Dims d, const uint32_t* __restrict__ bits,
+                  const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float* __restrict__ fib,
+                  uint32_t s_cap, float* __restrict__ dF) {
+  const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= nm) return;
+  int b[3];
+  float w[3][4];
+  wall_stencil(xm, l, b, w);
+  float U[3] = {0.0f, 0.0f, 0.0f};
+  for (int jz = 0; jz < 4; ++jz)
+    for (int jy = 0; jy < 4; ++jy) {
+      const float wyz = w[1][jy] * w[2][jz];
+      const int y = wrapi(b[1] + jy, d.ny), z = wrapi(b[2] + jz, d.nz);
+      for (int jx = 0; jx < 4; ++jx) {
+        uint32_t s;
+        if (!support_slot(bits, rank, node_index(wrapi(b[0] + jx, d.nx), y, z, d.nx, d.ny), s) || s >= s_cap)
+          continue;
+        const float4 v = us[s];
+        const float h = 0.5f / v.w;
+        const float wt = w[0][jx] * wyz;
+        U[0] += wt * (v.x + fib[s] * h);
+        U[1] += wt * (v.y + fib[(size_t)s_cap + s] * h);
+        U[2] += wt * (v.z + fib[2 * (size_t)s_cap + s] * h);
+      }
+    }
+  for (int k = 0; k < 3; ++k) dF[3 * (size_t)l + k] = -2.0f * U[k];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_ibm_wall_spread(const double* __restrict__ xm, uint32_t nm, float dV, Dims d, const uint32_t* __restrict__ bits,
+                  const uint32_t* __restrict__ rank, float* __restrict__ fib, uint32_t s_cap,
+                  const float* __restrict__ dF) {
+  const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= nm) return;
+  int b[3];
+  float w[3][4];
+  wall_stencil(xm, l, b, w);
+  const float f[3] = {dF[3 * (size_t)l] * dV, dF[3 * (size_t)l + 1] * dV, dF[3 * (size_t)l + 2] * dV};
+  for (int jz = 0; jz < 4; ++jz)
+    for (int jy = 0; jy < 4; ++jy) {
+      const float wyz = w[1][jy] * w[2][jz];
+      const int y = wrapi(b[1] + jy, d.ny), z = wrapi(b[2] + jz, d.nz);
+      for (int jx = 0; jx < 4; ++jx) {
+        uint32_t s;
+        if (!support_slot(bits, rank, node_index(wrapi(b[0] + jx, d.nx), y, z, d.nx, d.ny), s) || s >= s_cap)
+          continue;
+        const float wt = w[0][jx] * wyz;
+        for (int k = 0; k < 3; ++k) atomicAdd(fib + (size_t)k * s_cap + s, f[k] * wt);
+      }
+    }
+}
+
 // ---------------------------------------------------------------- kempe --
 // Sum alpha u and sum alpha (x - X) x u per sphere; u from the support
 // slots (u* + f_IB / (2 rho)) or, before the first step, a dense field.
@@ -557,7 +626,9 @@ hipError_t launch_bits_compact(hipStream_t st, const uint32_t* bits, uint32_t nw
 hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
   const uint32_t words = mask_words(c.dims.N);
   IbmBufs& m = c.ibm;
-  hipError_t e = hipMemsetAsync(m.bits[buf], 0, (size_t)words * 4, c.stream);
+  // the static wall support, if any, is part of every support set
+  hipError_t e = m.n_wall ? hipMemcpyAsync(m.bits[buf], m.wsup, (size_t)words * 4, hipMemcpyDeviceToDevice, c.stream)
+                          : hipMemsetAsync(m.bits[buf], 0, (size_t)words * 4, c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(m.shared, 0, (size_t)words * 4, c.stream);
   if (e != hipSuccess) return e;
   if (c.np > 0) {
@@ -581,21 +652,30 @@ hipError_t launch_ibm_prepass(const Ctx& c, const void* A) {
   const IbmBufs& m = c.ibm;
   const dim3 grid((m.s_cap + 255) / 256);
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_ibm_prepass<0>, grid, dim3(256), 0, c.stream, (const float*)A, c.dims, c.body_force, m.list,
-                       m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
+    hipLaunchKernelGGL(k_ibm_prepass<0>, grid, dim3(256), 0, c.stream, (const float*)A, c.dims, c.body_force,
+                       ibm_body_force_mask(c), m.list, m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
   else
     hipLaunchKernelGGL(k_ibm_prepass<1>, grid, dim3(256), 0, c.stream, (const _Float16*)A, c.dims, c.body_force,
-                       m.list, m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
+                       ibm_body_force_mask(c), m.list, m.count[m.cur], m.s_cap, m.us, m.fib[m.cur]);
   return hipGetLastError();
 }
 
 hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* U, const double* Om) {
-  if (c.np <= 0) return hipSuccess;
   const IbmBufs& m = c.ibm;
+  if (c.np <= 0 && m.n_wall == 0) return hipSuccess;
   const size_t lds = pass_lds_bytes(c);
   const int passes = 1 + c.cfg.ibm_iters;
+  const dim3 wgrid((m.n_wall + kBlock - 1) / kBlock);
   for (int k = 0; k < passes; ++k) {
-    if (m.n_markers <= kPassBlock)
+    if (m.n_wall) {
+      hipLaunchKernelGGL(k_ibm_wall_interp, wgrid, dim3(kBlock), 0, c.stream, m.wmark, m.n_wall, c.dims,
+                         m.bits[m.cur], m.rank[m.cur], m.us, m.fib[m.cur], m.s_cap, m.wdF);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (c.np <= 0) {
+      // wall only
+    } else if (m.n_markers <= kPassBlock)
       hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
                          m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
@@ -605,6 +685,11 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (m.n_wall) {
+      hipLaunchKernelGGL(k_ibm_wall_spread, wgrid, dim3(kBlock), 0, c.stream, m.wmark, m.n_wall, (float)m.wdV, c.dims,
+                         m.bits[m.cur], m.rank[m.cur], m.fib[m.cur], m.s_cap, m.wdF);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

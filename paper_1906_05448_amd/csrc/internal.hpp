@@ -189,6 +189,12 @@ struct IbmBufs {
   int side;              // 2 R_b + 2 (<= 32)
   int cur;               // support of the next collision
   int last;              // support used by the last collision
+  // Static pipe-wall markers (rings at every integer z), if any.
+  uint32_t n_wall;       // markers
+  double wdV;            // marker volume
+  double* wmark;         // [n_wall][3] positions
+  float* wdF;            // [n_wall][3] force of the current pass
+  uint32_t* wsup;        // [mask_words] support of the wall stencils
 };
 
 struct Ctx {
@@ -264,6 +270,11 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
 hipError_t launch_ibm_kempe(const Ctx& c, const double* X, double* Iu, double* IL);
 hipError_t launch_kempe_dense(const Ctx& c, const float* u, const double* X, double* Iu, double* IL);
 hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B);
+// Nodes without body force under the immersed boundary: outside the pipe
+// (null without a wall).
+inline const uint32_t* ibm_body_force_mask(const Ctx& c) {
+  return c.cfg.wall == LBM_WALL_PIPE_Z ? c.ibb.wall_bits : nullptr;
+}
 // Set bits of a node bitmask -> ascending node list: rank[w] = set bits
 // before word w, *count = total, list[i] = i-th set node (entries beyond cap
 // dropped, *err |= capacity bit). block_sums: bits_compact_scratch_words().
