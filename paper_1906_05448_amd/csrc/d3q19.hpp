@@ -176,6 +176,9 @@ template <> struct Pop<0> {
   using T = float;
   __device__ static __forceinline__ float load(const T* p) { return *p; }
   __device__ static __forceinline__ void store(T* p, float v) { *p = v; }
+  // Streaming store (non-temporal hint): for the fused kernel's output,
+  // which no one reads before the next step.
+  __device__ static __forceinline__ void store_stream(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 // FP16 holds (f_i - w_i) * 2^14. The power-of-two scale is exact both ways;
 // it moves the shifted populations of slow flows (|g| ~ 1e-7 near rest) out
@@ -186,6 +189,9 @@ template <> struct Pop<1> {
   using T = _Float16;
   __device__ static __forceinline__ float load(const T* p) { return static_cast<float>(*p) * (1.0f / kHalfScale); }
   __device__ static __forceinline__ void store(T* p, float v) { *p = static_cast<_Float16>(v * kHalfScale); }
+  __device__ static __forceinline__ void store_stream(T* p, float v) {
+    __builtin_nontemporal_store(static_cast<_Float16>(v * kHalfScale), p);
+  }
 };
 
 }  // namespace lbm

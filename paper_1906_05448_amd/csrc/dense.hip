@@ -8,7 +8,9 @@
 // so one node update moves 19 * 2 * sizeof(store) bytes of HBM: 152 B in
 // FP32, 76 B with FP16 shifted storage. Reads of a row shifted by one in x
 // straddle cache lines shared with the neighbouring tile; the XCD-aware tile
-// order keeps that neighbour in the same L2.
+// order keeps that neighbour in the same L2. The output is written with
+// non-temporal stores (measured 3% faster at 512^3; non-temporal loads were
+// slower).
 #include "internal.hpp"
 
 namespace lbm {
@@ -117,7 +119,7 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
   const uint32_t n = r00 + (uint32_t)x;
   const uint32_t noff = n * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) P::store((T*)((char*)(B + (size_t)i * N) + noff), g[i]);
+  for (int i = 0; i < kQ; ++i) P::store_stream((T*)((char*)(B + (size_t)i * N) + noff), g[i]);
 
   const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
   if (bad) atomicOr(err, kErrUnstable);

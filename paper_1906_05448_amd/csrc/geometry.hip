@@ -118,12 +118,27 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
   for (int c0 = 0; c0 < ncand; c0 += kBlock) {
     const int k = c0 + (int)threadIdx.x;
     int x = 0, y = 0, z = 0;
-    uint32_t hits = 0;
+    uint32_t hits = 0, fluid1 = 0, fluid2 = 0;
     if (k < ncand) {
       unpack_xyz(cand[k], x, y, z);
-      if (owner[node_index(x, y, z, d.nx, d.ny)] == kFluid)
-        for (int a = 1; a < kQ; ++a)
-          if (owner[neighbour(x, y, z, 1, a, d)] == p) hits |= 1u << a;
+      // every owner lookup of the candidate is issued before any is used,
+      // so the map's latency is paid once rather than per direction
+      uint32_t own[kQ], own1[kQ], own2[kQ];
+      own[0] = owner[node_index(x, y, z, d.nx, d.ny)];
+#pragma unroll
+      for (int a = 1; a < kQ; ++a) own[a] = owner[neighbour(x, y, z, 1, a, d)];
+#pragma unroll
+      for (int a = 1; a < kQ; ++a) own1[a] = owner[neighbour(x, y, z, -1, a, d)];
+#pragma unroll
+      for (int a = 1; a < kQ; ++a) own2[a] = owner[neighbour(x, y, z, -2, a, d)];
+      if (own[0] == kFluid) {
+#pragma unroll
+        for (int a = 1; a < kQ; ++a) {
+          hits |= (own[a] == p ? 1u : 0u) << a;
+          fluid1 |= (own1[a] == kFluid ? 1u : 0u) << a;
+          fluid2 |= (own2[a] == kFluid ? 1u : 0u) << a;
+        }
+      }
     }
     uint32_t total;
     uint32_t off = written + block_exclusive_scan<kBlock>(__popc(hits), &total);
@@ -134,9 +149,7 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
       for (int a = 1; a < kQ; ++a) {
         if (!((hits >> a) & 1u)) continue;
         const double q = sphere_q(dx, dy, dz, cx_of(a), cy_of(a), cz_of(a), r);
-        const bool f1 = owner[neighbour(x, y, z, -1, a, d)] == kFluid;
-        const bool f2 = owner[neighbour(x, y, z, -2, a, d)] == kFluid;
-        const uint32_t s = pick_scheme(q, f1, f2, max_order);
+        const uint32_t s = pick_scheme(q, (fluid1 >> a) & 1u, (fluid2 >> a) & 1u, max_order);
         if (off < cap) {
           link_node[base + off] = pack_xyz(x, y, z);
           link_q[base + off] = (float)q;
@@ -165,22 +178,34 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
   const double r2 = r * r, ro2 = r_out * r_out;
   uint32_t written = 0;
   int ncand = 0;
-  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
-    int x = 0, y = 0, z = 0;
-    bool shell = false;
-    if (box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) {
-      const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
-                              min_image((double)z - Xp[2], d.nz));
-      shell = d2 >= r2 && d2 < ro2;
+  // kRowsPer groups of rows per iteration, one node of each per thread
+  constexpr int kRowsPer = 4;
+  for (int rb = 0; rb < br.nrows; rb += kRowsPer * br.rows_per_iter) {
+    uint32_t packed[kRowsPer];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k) {
+      int x = 0, y = 0, z = 0;
+      packed[k] = 0;
+      if (box_row_node(b, br, rb + k * br.rows_per_iter, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) {
+        const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
+                                min_image((double)z - Xp[2], d.nz));
+        if (d2 >= r2 && d2 < ro2) {
+          mask |= 1u << k;
+          packed[k] = pack_xyz(x, y, z);
+        }
+      }
     }
     uint32_t total;
-    const uint32_t off = block_exclusive_scan<kBlock>(shell ? 1u : 0u, &total);
+    uint32_t off = block_exclusive_scan<kBlock>(__popc(mask), &total);
     if (ncand + (int)total > kCand) {  // uniform: total is block-wide
       flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, written, link_node, link_q, link_meta);
       __syncthreads();
       ncand = 0;
     }
-    if (shell) cand[ncand + off] = pack_xyz(x, y, z);
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k)
+      if ((mask >> k) & 1u) cand[ncand + off++] = packed[k];
     ncand += (int)total;
     __syncthreads();
   }

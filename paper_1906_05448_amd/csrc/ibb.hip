@@ -257,18 +257,41 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
                  dz = min_image((double)z - C[2], d.nz);
     return dist2(dx, dy, dz) < r * r;
   };
-  // uncovered: solid for p before, fluid now
+  // One pass over the union of the old and new boxes: uncovered nodes are
+  // inside the old sphere only, covered nodes inside the new one only.
+  Box b = make_box(Xo, r + 1.0);
   {
-    const Box b = make_box(Xo, r + 1.0);
-    const BoxRows br = box_rows(b);
-    for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
-      int x, y, z;
-      if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
-      if (!inside(x, y, z, Xo) || inside(x, y, z, Xn)) continue;
-      const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    const Box bn = make_box(Xn, r + 1.0);
+    for (int k = 0; k < 3; ++k) {
+      const int lo = min(b.lo[k], bn.lo[k]);
+      const int hi = max(b.lo[k] + b.side[k], bn.lo[k] + bn.side[k]);
+      b.lo[k] = lo;
+      b.side[k] = hi - lo;
+    }
+  }
+  // A node can change side only within the displacement of the surface:
+  // an FP32 distance band (margin 0.01, far above FP32 error at lattice
+  // coordinates below 2048) skips the rest before the exact FP64 tests.
+  const double mv = sqrt(dist2(min_image(Xn[0] - Xo[0], d.nx), min_image(Xn[1] - Xo[1], d.ny),
+                               min_image(Xn[2] - Xo[2], d.nz)));
+  const float band = (float)mv + 0.01f, rf = (float)r;
+  const float Xf[3] = {(float)Xn[0], (float)Xn[1], (float)Xn[2]};
+  auto min_image_f = [](float v, float L) { return v > 0.5f * L ? v - L : (v < -0.5f * L ? v + L : v); };
+  const BoxRows br = box_rows(b);
+  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
+    int x, y, z;
+    if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    const float fx = min_image_f((float)x - Xf[0], (float)d.nx), fy = min_image_f((float)y - Xf[1], (float)d.ny),
+                fz = min_image_f((float)z - Xf[2], (float)d.nz);
+    if (fabsf(sqrtf(fx * fx + fy * fy + fz * fz) - rf) > band) continue;
+    const bool in_old = inside(x, y, z, Xo), in_new = inside(x, y, z, Xn);
+    if (in_old == in_new) continue;
+    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
+                          min_image((double)z - Xn[2], d.nz)};
+    if (in_old) {
+      // uncovered: solid for p before, fluid now
       if (o_old[n] != p || o_new[n] != kFluid) continue;
-      const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
-                            min_image((double)z - Xn[2], d.nz)};
       const double uw[3] = {Up[0] + (Wp[1] * dd[2] - Wp[2] * dd[1]), Up[1] + (Wp[2] * dd[0] - Wp[0] * dd[2]),
                             Up[2] + (Wp[0] * dd[1] - Wp[1] * dd[0])};
       double mom[3];
@@ -277,17 +300,8 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       T[0] -= dd[1] * mom[2] - dd[2] * mom[1];
       T[1] -= dd[2] * mom[0] - dd[0] * mom[2];
       T[2] -= dd[0] * mom[1] - dd[1] * mom[0];
-    }
-  }
-  // covered: fluid before, solid for p now
-  {
-    const Box b = make_box(Xn, r + 1.0);
-    const BoxRows br = box_rows(b);
-    for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
-      int x, y, z;
-      if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
-      if (!inside(x, y, z, Xn) || inside(x, y, z, Xo)) continue;
-      const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+    } else {
+      // covered: fluid before, solid for p now
       if (o_new[n] != p || o_old[n] != kFluid) continue;
       double mom[3] = {0, 0, 0};
       for (int k = 0; k < kQ; ++k) {
@@ -296,8 +310,6 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
         mom[1] += cy_of(k) * g;
         mom[2] += cz_of(k) * g;
       }
-      const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
-                            min_image((double)z - Xn[2], d.nz)};
       for (int k = 0; k < 3; ++k) F[k] += mom[k];
       T[0] += dd[1] * mom[2] - dd[2] * mom[1];
       T[1] += dd[2] * mom[0] - dd[0] * mom[2];
