@@ -110,19 +110,21 @@ __device__ __forceinline__ uint32_t neighbour(int x, int y, int z, int k, int i,
 }
 
 // Examines the buffered shell candidates and writes their links from slot
-// `written` on. Every thread must call it.
+// `written` on. Every thread must call it. Per chunk of kBlock candidates the
+// lanes first find each candidate's links (owner lookups, all issued before
+// any is used), list them in LDS in candidate-then-direction order, and then
+// evaluate q and the scheme with one link per lane, so the FP64 root is
+// computed with every lane busy and the records are written contiguously.
 __device__ void flush_candidates(const uint32_t* __restrict__ owner, const double* Xp, double r, const Dims& d,
                                  int max_order, uint32_t p, uint32_t cap, size_t base, const uint32_t* cand,
-                                 int ncand, uint32_t& written, uint32_t* __restrict__ link_node,
+                                 int ncand, uint16_t* lbuf, uint32_t& written, uint32_t* __restrict__ link_node,
                                  float* __restrict__ link_q, uint8_t* __restrict__ link_meta) {
   for (int c0 = 0; c0 < ncand; c0 += kBlock) {
     const int k = c0 + (int)threadIdx.x;
-    int x = 0, y = 0, z = 0;
     uint32_t hits = 0, fluid1 = 0, fluid2 = 0;
     if (k < ncand) {
+      int x, y, z;
       unpack_xyz(cand[k], x, y, z);
-      // every owner lookup of the candidate is issued before any is used,
-      // so the map's latency is paid once rather than per direction
       uint32_t own[kQ], own1[kQ], own2[kQ];
       own[0] = owner[node_index(x, y, z, d.nx, d.ny)];
 #pragma unroll
@@ -141,24 +143,33 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
       }
     }
     uint32_t total;
-    uint32_t off = written + block_exclusive_scan<kBlock>(__popc(hits), &total);
-    if (hits) {
+    uint32_t off = block_exclusive_scan<kBlock>(__popc(hits), &total);
+    // entry: candidate within the chunk (8 bits), direction (5), x_f - c fluid, x_f - 2c fluid
+    for (uint32_t h = hits; h; h &= h - 1u) {
+      const uint32_t a = (uint32_t)__builtin_ctz(h);
+      lbuf[off++] = (uint16_t)(threadIdx.x | (a << 8) | (((fluid1 >> a) & 1u) << 13) | (((fluid2 >> a) & 1u) << 14));
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < total; j += kBlock) {
+      const uint32_t e = lbuf[j];
+      const uint32_t xyz = cand[c0 + (int)(e & 0xFFu)];
+      const int a = (int)((e >> 8) & 31u);
+      int x, y, z;
+      unpack_xyz(xyz, x, y, z);
       const double dx = min_image((double)x - Xp[0], d.nx);
       const double dy = min_image((double)y - Xp[1], d.ny);
       const double dz = min_image((double)z - Xp[2], d.nz);
-      for (int a = 1; a < kQ; ++a) {
-        if (!((hits >> a) & 1u)) continue;
-        const double q = sphere_q(dx, dy, dz, cx_of(a), cy_of(a), cz_of(a), r);
-        const uint32_t s = pick_scheme(q, (fluid1 >> a) & 1u, (fluid2 >> a) & 1u, max_order);
-        if (off < cap) {
-          link_node[base + off] = pack_xyz(x, y, z);
-          link_q[base + off] = (float)q;
-          link_meta[base + off] = (uint8_t)(a | (s << 5));
-        }
-        ++off;
+      const double q = sphere_q(dx, dy, dz, cx_of(a), cy_of(a), cz_of(a), r);
+      const uint32_t sch = pick_scheme(q, (e >> 13) & 1u, (e >> 14) & 1u, max_order);
+      const uint32_t slot = written + j;
+      if (slot < cap) {
+        link_node[base + slot] = xyz;
+        link_q[base + slot] = (float)q;
+        link_meta[base + slot] = (uint8_t)(a | (sch << 5));
       }
     }
     written += total;
+    __syncthreads();  // lbuf is refilled by the next chunk
   }
 }
 
@@ -167,6 +178,7 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
               int max_order, uint32_t cap, uint32_t* __restrict__ link_node, float* __restrict__ link_q,
               uint8_t* __restrict__ link_meta, uint32_t* __restrict__ link_count, uint32_t* __restrict__ err) {
   __shared__ uint32_t cand[kCand];
+  __shared__ uint16_t lbuf[kBlock * (kQ - 1)];  // a chunk's links, at most every direction of every candidate
   const uint32_t p = blockIdx.x;
   const double r = rad[p];
   const double* Xp = X + 3 * p;
@@ -199,7 +211,7 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
     uint32_t total;
     uint32_t off = block_exclusive_scan<kBlock>(__popc(mask), &total);
     if (ncand + (int)total > kCand) {  // uniform: total is block-wide
-      flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, written, link_node, link_q, link_meta);
+      flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, lbuf, written, link_node, link_q, link_meta);
       __syncthreads();
       ncand = 0;
     }
@@ -209,7 +221,7 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
     ncand += (int)total;
     __syncthreads();
   }
-  flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, written, link_node, link_q, link_meta);
+  flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, lbuf, written, link_node, link_q, link_meta);
   if (threadIdx.x == 0) {
     if (written > cap) {
       atomicOr(err, kErrCapacity);

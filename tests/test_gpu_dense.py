@@ -52,11 +52,26 @@ def test_dense_hit_field_100_steps(store):
     assert rel_l2(ug, uo) < TOL[store]
 
 
-def test_dense_minimum_box():
+@pytest.mark.parametrize("store", [0, 1])
+def test_dense_minimum_box(store):
     shape = (4, 4, 4)
     u0 = synth.random_velocity(shape, 0.03, seed=3)
-    ug, rg, uo, ro = _run_pair(shape, 0.9, (1e-4, 0, 0), u0, None, 10, 0)
-    assert rel_l2(ug, uo) < 1e-5
+    ug, rg, uo, ro = _run_pair(shape, 0.9, (1e-4, 0, 0), u0, None, 10, store)
+    assert rel_l2(ug, uo) < TOL[store]
+
+
+@pytest.mark.parametrize("shape", [(71, 6, 5), (130, 5, 4), (6, 6, 5), (128, 4, 4)])
+def test_dense_fp16_row_lengths(shape):
+    # FP16 storage over row lengths around the 64-node tile: an odd row (71),
+    # one node past two tiles (130), a row shorter than a wavefront (6) and
+    # exactly two tiles (128); the x-wrap of the shifted directions is
+    # exercised at both ends of every row.
+    F = (2e-5, 1e-5, -1e-5)
+    u0 = synth.random_velocity(shape, 0.05, seed=21)
+    r0 = synth.random_density(shape, 0.01, seed=22)
+    ug, rg, uo, ro = _run_pair(shape, 0.6, F, u0, r0, 15, 1)
+    assert rel_l2(ug, uo) < TOL[1]
+    assert rel_l2(rg - 1, ro - 1) < 50 * TOL[1]
 
 
 def test_dense_zero_steps_returns_initial_state():
