@@ -87,6 +87,35 @@ __device__ __forceinline__ bool box_row_node(const Box& b, const BoxRows& br, in
   return true;
 }
 
+// Box traversal by linear raster index with every lane busy. i / s is a
+// multiply-high by m = ceil(2^32 / s), exact while i * s < 2^32: box sides
+// stay below 64 (radius <= 28) and indices below 64^3, so i * s < 2^30.
+struct BoxLin {
+  uint32_t sx, sxy, count, mx, mxy;
+};
+
+__device__ __forceinline__ BoxLin box_lin(const Box& b) {
+  BoxLin L;
+  L.sx = (uint32_t)b.side[0];
+  L.sxy = L.sx * (uint32_t)b.side[1];
+  L.count = L.sxy * (uint32_t)b.side[2];
+  L.mx = (uint32_t)((0x100000000ull + L.sx - 1u) / L.sx);
+  L.mxy = (uint32_t)((0x100000000ull + L.sxy - 1u) / L.sxy);
+  return L;
+}
+
+// Node i (< L.count) of the box, wrapped into the lattice.
+__device__ __forceinline__ void box_lin_node(const Box& b, const BoxLin& L, uint32_t i, int nx, int ny, int nz, int& x,
+                                             int& y, int& z) {
+  const uint32_t iz = __umulhi(i, L.mxy);
+  const uint32_t rem = i - iz * L.sxy;
+  const uint32_t iy = __umulhi(rem, L.mx);
+  const uint32_t ix = rem - iy * L.sx;
+  x = wrap1(b.lo[0] + (int)ix, nx);
+  y = wrap1(b.lo[1] + (int)iy, ny);
+  z = wrap1(b.lo[2] + (int)iz, nz);
+}
+
 // Link nodes are stored as packed coordinates x | y << 11 | z << 22.
 __device__ __forceinline__ uint32_t pack_xyz(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);

@@ -45,10 +45,10 @@ __global__ void __launch_bounds__(kBlock) k_owner_clear(uint32_t* __restrict__ o
   const double r = rad[p];
   const double* Xp = Xold + 3 * p;
   const Box b = make_box(Xp, r + 1.0);
-  const BoxRows br = box_rows(b);
-  for (int base = 0; base < br.nrows; base += br.rows_per_iter) {
+  const BoxLin L = box_lin(b);
+  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
     int x, y, z;
-    if (!box_row_node(b, br, base, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
     if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     if (owner[n] != kWall) owner[n] = kFluid;
@@ -61,10 +61,10 @@ __global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ own
   const double r = rad[p];
   const double* Xp = X + 3 * p;
   const Box b = make_box(Xp, r + 1.0);
-  const BoxRows br = box_rows(b);
-  for (int base = 0; base < br.nrows; base += br.rows_per_iter) {
+  const BoxLin L = box_lin(b);
+  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
     int x, y, z;
-    if (!box_row_node(b, br, base, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
     if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
     atomicMin(owner + node_index(x, y, z, d.nx, d.ny), (uint32_t)p);
   }
@@ -183,23 +183,25 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
   const double r = rad[p];
   const double* Xp = X + 3 * p;
   const Box b = make_box(Xp, r + 2.0);
-  const BoxRows br = box_rows(b);
+  const BoxLin L = box_lin(b);
   const size_t base = (size_t)p * cap;
   // The outer bound only prunes, so it carries a margin.
   const double r_out = r + 1.4142135623730951 + 1e-6;
   const double r2 = r * r, ro2 = r_out * r_out;
   uint32_t written = 0;
   int ncand = 0;
-  // kRowsPer groups of rows per iteration, one node of each per thread
-  constexpr int kRowsPer = 4;
-  for (int rb = 0; rb < br.nrows; rb += kRowsPer * br.rows_per_iter) {
-    uint32_t packed[kRowsPer];
+  // kPer nodes per thread per iteration
+  constexpr int kPer = 4;
+  for (uint32_t i0 = 0; i0 < L.count; i0 += kPer * kBlock) {
+    uint32_t packed[kPer];
     uint32_t mask = 0;
 #pragma unroll
-    for (int k = 0; k < kRowsPer; ++k) {
+    for (int k = 0; k < kPer; ++k) {
       int x = 0, y = 0, z = 0;
       packed[k] = 0;
-      if (box_row_node(b, br, rb + k * br.rows_per_iter, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) {
+      const uint32_t i = i0 + (uint32_t)(k * kBlock) + threadIdx.x;
+      if (i < L.count) {
+        box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
         const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
                                 min_image((double)z - Xp[2], d.nz));
         if (d2 >= r2 && d2 < ro2) {
@@ -216,7 +218,7 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
       ncand = 0;
     }
 #pragma unroll
-    for (int k = 0; k < kRowsPer; ++k)
+    for (int k = 0; k < kPer; ++k)
       if ((mask >> k) & 1u) cand[ncand + off++] = packed[k];
     ncand += (int)total;
     __syncthreads();

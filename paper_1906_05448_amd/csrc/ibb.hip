@@ -258,10 +258,14 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
     return dist2(dx, dy, dz) < r * r;
   };
   // One pass over the union of the old and new boxes: uncovered nodes are
-  // inside the old sphere only, covered nodes inside the new one only.
+  // inside the old sphere only, covered nodes inside the new one only. The
+  // new box is placed at the old centre plus the minimum-image displacement,
+  // so a sphere that crossed a periodic face still has a compact union.
   Box b = make_box(Xo, r + 1.0);
   {
-    const Box bn = make_box(Xn, r + 1.0);
+    const double Xn_near[3] = {Xo[0] + min_image(Xn[0] - Xo[0], d.nx), Xo[1] + min_image(Xn[1] - Xo[1], d.ny),
+                               Xo[2] + min_image(Xn[2] - Xo[2], d.nz)};
+    const Box bn = make_box(Xn_near, r + 1.0);
     for (int k = 0; k < 3; ++k) {
       const int lo = min(b.lo[k], bn.lo[k]);
       const int hi = max(b.lo[k] + b.side[k], bn.lo[k] + bn.side[k]);
@@ -277,10 +281,10 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   const float band = (float)mv + 0.01f, rf = (float)r;
   const float Xf[3] = {(float)Xn[0], (float)Xn[1], (float)Xn[2]};
   auto min_image_f = [](float v, float L) { return v > 0.5f * L ? v - L : (v < -0.5f * L ? v + L : v); };
-  const BoxRows br = box_rows(b);
-  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
+  const BoxLin L = box_lin(b);
+  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
     int x, y, z;
-    if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
     const float fx = min_image_f((float)x - Xf[0], (float)d.nx), fy = min_image_f((float)y - Xf[1], (float)d.ny),
                 fz = min_image_f((float)z - Xf[2], (float)d.nz);
     if (fabsf(sqrtf(fx * fx + fy * fy + fz * fz) - rf) > band) continue;

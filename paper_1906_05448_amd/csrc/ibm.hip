@@ -561,11 +561,11 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
   const double* Xp = X + 3 * p;
   const double r = rad[p];
   const Box b = make_box(Xp, r + 1.0);
-  const BoxRows br = box_rows(b);
+  const BoxLin L = box_lin(b);
   double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int rb = 0; rb < br.nrows; rb += br.rows_per_iter) {
+  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
     int x, y, z;
-    if (!box_row_node(b, br, rb, threadIdx.x, d.nx, d.ny, d.nz, x, y, z)) continue;
+    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
     const double dx = min_image((double)x - Xp[0], d.nx), dy = min_image((double)y - Xp[1], d.ny),
                  dz = min_image((double)z - Xp[2], d.nz);
     const double a = kempe_alpha(dx, dy, dz, r);

@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle.lattice import C as OC
-from oracle.sim import RELEASE, SET_STATE, Config as OConfig, Sim as OSim
+from oracle.sim import RELEASE, SET_RIGID, SET_STATE, Config as OConfig, Sim as OSim
 from tests.helpers import gpu_config, gpu_lattice, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -155,4 +155,43 @@ def test_pipe_wall_linear_ibb():
     ug, _ = g.get_fields()
     uo, _ = o.fields()
     assert rel_l2(ug, uo, o.fluid_mask()) < 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_prescribed_spheres_cross_periodic_faces(store):
+    """Two spheres with prescribed velocity and spin cross periodic faces
+    (x and z for one, y for the other) while they move: the wrapped
+    positions, the refill of uncovered nodes and the cover/uncover momentum
+    must follow the oracle across the wrap."""
+    shape = (28, 26, 30)
+    X = np.array([[0.6, 12.0, 29.5], [14.0, 25.4, 15.0]])
+    U = np.array([[-0.06, 0.01, 0.05], [0.02, 0.07, -0.01]])
+    W = np.array([[0.0, 0.004, -0.003], [0.002, 0.0, 0.005]])
+    r = np.array([4.3, 3.8])
+    o, g = _pair(shape, tau=0.6, store=store, max_np=2, max_r=4.5)
+    spec = synth.hit_spectrum(seed=5, u_rms=0.02, kcut=6)
+    u0 = synth.hit_field(spec, shape)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, U=U, Om=W, r=r, mode=SET_RIGID, motion="prescribed")
+    g.set_particles(X, r, u=U, omega=W, mode=2, motion=MOTION["prescribed"])
+    uncovered = 0
+    for _ in range(4):
+        o.step(6)
+        g.step(6)
+        uncovered += o.state.extra["uncovered"]
+        Xg, _, _ = g.get_particles()
+        assert np.abs(Xg - o.state.P.X).max() < 1e-9
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        tol = 1e-5 if store == 0 else 2e-3
+        assert rel_l2(ug, uo, o.fluid_mask()) < tol, o.state.step
+        Fg, _, _ = g.forces()
+        Fo, _, _ = o.forces()
+        assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
+    # both spheres wrapped at least once
+    Xf = o.state.P.X
+    assert Xf[0, 0] > 20 and Xf[0, 2] < 5 and Xf[1, 1] < 5
+    assert uncovered > 0
     g.close()
