@@ -216,6 +216,10 @@ __device__ __forceinline__ bool support_slot(const uint32_t* bits, const uint32_
 }
 
 // Per sphere: global slot of every forcing-support node, in box raster order.
+// A box row (side <= 32 nodes) touches at most two words of the support
+// bitmask per contiguous x segment, and there are two segments when the row
+// wraps around x. Those words and their ranks are loaded once per row, all
+// together, and every slot of the row is formed from them.
 __global__ void __launch_bounds__(kBlock)
 k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint32_t* __restrict__ bits,
             const uint32_t* __restrict__ rank, const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount,
@@ -234,11 +238,32 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
     if (m) {
       const int ly = row % side, lz = row / side;
       const int y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+      const uint32_t rowbase = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx;
+      const int xa = wrap1(lo[0] + (__ffs(m) - 1), d.nx), xb = wrap1(lo[0] + (31 - __clz(m)), d.nx);
+      // words of the first node of each segment and the one after it
+      uint32_t w[4], wb[4], wr[4];
+      w[0] = (rowbase + (uint32_t)xa) >> 5;
+      w[2] = rowbase >> 5;  // wrapped segment starts at x = 0
+      const uint32_t last1 = xa <= xb ? (rowbase + (uint32_t)xb) >> 5 : (rowbase + (uint32_t)d.nx - 1u) >> 5;
+      const bool wrapped = xa > xb;
+      const uint32_t last2 = wrapped ? (rowbase + (uint32_t)xb) >> 5 : 0u;
+      w[1] = last1 > w[0] ? w[0] + 1u : w[0];
+      w[3] = wrapped && last2 > w[2] ? w[2] + 1u : w[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool use = k < 2 || wrapped;
+        wb[k] = use ? bits[w[k]] : 0u;
+        wr[k] = use ? rank[w[k]] : 0u;
+      }
       while (m) {
         const int lx = __ffs(m) - 1;
         m &= m - 1u;
-        uint32_t slot = 0;
-        (void)support_slot(bits, rank, node_index(wrap1(lo[0] + lx, d.nx), y, z, d.nx, d.ny), slot);
+        const uint32_t n = rowbase + (uint32_t)wrap1(lo[0] + lx, d.nx);
+        const uint32_t wn = n >> 5;
+        const int k = wn == w[0] ? 0 : (wn == w[1] ? 1 : (wn == w[2] ? 2 : 3));
+        const uint32_t word = k == 0 ? wb[0] : (k == 1 ? wb[1] : (k == 2 ? wb[2] : wb[3]));
+        const uint32_t rk = k == 0 ? wr[0] : (k == 1 ? wr[1] : (k == 2 ? wr[2] : wr[3]));
+        const uint32_t slot = rk + __popc(word & ((1u << (n & 31u)) - 1u));
         if (j < cap) fslot[(size_t)p * fcap + j] = slot;
         ++j;
       }
@@ -280,10 +305,12 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 
 // --------------------------------------------------------------- passes --
 // One 1024-thread workgroup per sphere, MPT markers per thread.
-// LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 24
+// LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 12
 // bytes holding first the staged velocities (float3 per node) and, once every
-// marker has interpolated, the spread sums (3 x int64 per node), then fcap/32
-// u32 (shared flags).
+// marker has interpolated, the spread sums of one velocity component (int64
+// per node; the three components are spread one after the other), then
+// fcap/32 u32 (shared flags). About 56 KB for r = 8, so two spheres share a
+// compute unit and one's memory trips overlap the other's LDS work.
 //
 // The spread sums are 64-bit fixed point in units of 2^-50: LDS integer
 // atomics run at about the rate of plain LDS accesses, while LDS float
@@ -293,7 +320,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // a node receives sum to O(1) and |dF| < 1.4 below the Mach limit that the
 // collision kernel latches as unstable.
 constexpr int kPassBlock = 1024;
-constexpr int kStage = 5;  // support nodes per thread per staging round
+constexpr int kStage = 3;  // support nodes per thread per staging round
 constexpr double kFixScale = 0x1p50;
 constexpr double kFixUnit = 0x1p-50;
 
@@ -303,7 +330,9 @@ __device__ __forceinline__ unsigned long long to_fix(float v) {
 __device__ __forceinline__ float from_fix(unsigned long long a) { return (float)((double)(long long)a * kFixUnit); }
 
 template <int MPT>
-__global__ void __launch_bounds__(kPassBlock)
+// One marker per thread: 8 waves per SIMD (<= 64 VGPRs), two workgroups per
+// CU; two markers per thread keep one workgroup per CU.
+__global__ void __launch_bounds__(kPassBlock, MPT == 1 ? 8 : 4)
 k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om,
            const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
@@ -316,7 +345,7 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   uint32_t* rp = rb + rows;
   float* uj = (float*)(rp + rows);
   unsigned long long* acc = (unsigned long long*)(rp + rows);  // rows * 8 bytes in: 8-byte aligned
-  uint32_t* sh = (uint32_t*)(acc + 3 * (size_t)fcap);
+  uint32_t* sh = (uint32_t*)(uj + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
   const uint32_t* slots = fslot + (size_t)p * fcap;
@@ -418,67 +447,69 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     fsum[4] -= arm[2] * f[0] - arm[0] * f[2];
     fsum[5] -= arm[0] * f[1] - arm[1] * f[0];
   }
-  __syncthreads();
-  for (uint32_t j = threadIdx.x; j < 3 * cnt; j += kPassBlock) acc[j] = 0ull;
-  __syncthreads();
-  // spread dF delta dV into the fixed-point sums
-#pragma unroll
-  for (int m = 0; m < MPT; ++m) {
-    const int l = threadIdx.x + m * kPassBlock;
-    if (l >= nmk) continue;
-    const uint32_t below = (1u << st[m].bx) - 1u;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int jy = q & 3, jz = q >> 2;
-      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
-      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
-      const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
-#pragma unroll
-      for (int jx = 0; jx < 4; ++jx) {
-        const float w = st[m].wx[jx] * wyz;
-        const uint32_t j = j0 + jx;
-        atomicAdd(&acc[3 * j], to_fix(dF[m][0] * w));
-        atomicAdd(&acc[3 * j + 1], to_fix(dF[m][1] * w));
-        atomicAdd(&acc[3 * j + 2], to_fix(dF[m][2] * w));
-      }
-    }
-  }
-  __syncthreads();
-  // add the pass's spread to the slot forces: plain read-modify-write where
-  // this sphere owns the node alone, global atomics where supports meet
-  for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
-    uint32_t s[kStage];
-    float old[kStage][3];
-    bool shr[kStage];
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) {
-      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-      s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
-      shr[i] = j < cnt && ((sh[j >> 5] >> (j & 31u)) & 1u);
-    }
-#pragma unroll
-    for (int i = 0; i < kStage; ++i)
-      if (s[i] < s_cap && !shr[i])
-        for (int k = 0; k < 3; ++k) old[i][k] = fib[(size_t)k * s_cap + s[i]];
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) {
-      if (s[i] >= s_cap) continue;
-      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-      for (int k = 0; k < 3; ++k) {
-        float* fk = fib + (size_t)k * s_cap + s[i];
-        const float v = from_fix(acc[3 * j + k]);
-        if (shr[i])
-          atomicAdd(fk, v);
-        else
-          *fk = old[i][k] + v;
-      }
-    }
-  }
+  // the particle's force and torque are complete once every marker has
+  // interpolated
   block_sum_first<kPassBlock, 6>(fsum);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       F_ib[3 * p + k] = (first ? 0.0 : F_ib[3 * p + k]) + fsum[k];
       T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + fsum[3 + k];
+    }
+  }
+  // spread dF delta dV into the fixed-point sums, one component at a time,
+  // and add each to the slot forces: plain read-modify-write where this
+  // sphere owns the node alone, global atomics where supports meet
+  for (int comp = 0; comp < 3; ++comp) {
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += kPassBlock) acc[j] = 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MPT; ++m) {
+      const int l = threadIdx.x + m * kPassBlock;
+      if (l >= nmk) continue;
+      // The stencil is the same for the three components; this empty asm
+      // keeps the compiler from holding its 64 addresses and weights live
+      // across the loop (recomputing them is cheaper than spilling them).
+      asm volatile("" : "+v"(st[m].wx[0]), "+v"(st[m].wx[1]), "+v"(st[m].wx[2]), "+v"(st[m].wx[3]),
+                   "+v"(st[m].wy[0]), "+v"(st[m].wy[1]), "+v"(st[m].wy[2]), "+v"(st[m].wy[3]),
+                   "+v"(st[m].wz[0]), "+v"(st[m].wz[1]), "+v"(st[m].wz[2]), "+v"(st[m].wz[3]),
+                   "+v"(st[m].bx), "+v"(st[m].by), "+v"(st[m].bz));
+      const uint32_t below = (1u << st[m].bx) - 1u;
+      const float dFc = comp == 0 ? dF[m][0] : (comp == 1 ? dF[m][1] : dF[m][2]);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int jy = q & 3, jz = q >> 2;
+        const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+        const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+        const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
+#pragma unroll
+        for (int jx = 0; jx < 4; ++jx) atomicAdd(&acc[j0 + jx], to_fix(dFc * (st[m].wx[jx] * wyz)));
+      }
+    }
+    __syncthreads();
+    float* fc = fib + (size_t)comp * s_cap;
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
+      uint32_t s[kStage];
+      float old[kStage];
+      bool shr[kStage];
+#pragma unroll
+      for (int i = 0; i < kStage; ++i) {
+        const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+        s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
+        shr[i] = j < cnt && ((sh[j >> 5] >> (j & 31u)) & 1u);
+      }
+#pragma unroll
+      for (int i = 0; i < kStage; ++i)
+        if (s[i] < s_cap && !shr[i]) old[i] = fc[s[i]];
+#pragma unroll
+      for (int i = 0; i < kStage; ++i) {
+        if (s[i] >= s_cap) continue;
+        const float v = from_fix(acc[j0 + threadIdx.x + i * kPassBlock]);
+        if (shr[i])
+          atomicAdd(fc + s[i], v);
+        else
+          fc[s[i]] = old[i] + v;
+      }
     }
   }
 }
@@ -602,7 +633,7 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
 
 size_t pass_lds_bytes(const Ctx& c) {
   const size_t rows = (size_t)c.ibm.side * c.ibm.side;
-  return rows * 8 + (size_t)c.ibm.fcap * 24 + ((c.ibm.fcap + 31) / 32) * 4;
+  return rows * 8 + (size_t)c.ibm.fcap * 12 + ((c.ibm.fcap + 31) / 32) * 4;
 }
 
 }  // namespace
