@@ -250,7 +250,9 @@ Plan plan(const lbm_config& c) {
       p.n_wall = (uint32_t)(xm.size() / 3);
       p.wall_support = pipe_support(c, xm, wb);
     }
-    p.s_cap = (uint32_t)std::min<uint64_t>((uint64_t)N, (uint64_t)P * full + p.wall_support + 4096);
+    // below 2^31: the forcing slot lists keep a shared-node flag in bit 31
+    p.s_cap = (uint32_t)std::min<uint64_t>(std::min<uint64_t>((uint64_t)N, 0x7FFFFFFFull),
+                                           (uint64_t)P * full + p.wall_support + 4096);
     p.n_markers = P ? (uint32_t)marker_count(c.max_radius - c.ibm_retraction) : 0;
     p.side = P ? ibm_box_side(c.max_radius, c.ibm_retraction) : 0;
     const size_t rows = (size_t)p.side * p.side;

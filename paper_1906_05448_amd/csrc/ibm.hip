@@ -215,15 +215,20 @@ __device__ __forceinline__ bool support_slot(const uint32_t* bits, const uint32_
   return true;
 }
 
-// Per sphere: global slot of every forcing-support node, in box raster order.
-// A box row (side <= 32 nodes) touches at most two words of the support
-// bitmask per contiguous x segment, and there are two segments when the row
-// wraps around x. Those words and their ranks are loaded once per row, all
-// together, and every slot of the row is formed from them.
+// Per sphere: global slot of every forcing-support node, in box raster order,
+// with bit 31 set where another support shares the node (slots stay below
+// 2^31). A box row (side <= 32 nodes) touches at most two words of the
+// support bitmask per contiguous x segment, and there are two segments when
+// the row wraps around x. Those words, their ranks and their shared bits are
+// loaded once per row, all together, and every slot of the row is formed
+// from them.
+constexpr uint32_t kSlotShared = 0x80000000u;
+
 __global__ void __launch_bounds__(kBlock)
 k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint32_t* __restrict__ bits,
-            const uint32_t* __restrict__ rank, const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount,
-            uint32_t fcap, uint32_t* __restrict__ fslot) {
+            const uint32_t* __restrict__ rank, const uint32_t* __restrict__ shared,
+            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
+            uint32_t* __restrict__ fslot) {
   const int rows = side * side;
   const int p = blockIdx.x;
   int lo[3];
@@ -241,7 +246,7 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
       const uint32_t rowbase = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx;
       const int xa = wrap1(lo[0] + (__ffs(m) - 1), d.nx), xb = wrap1(lo[0] + (31 - __clz(m)), d.nx);
       // words of the first node of each segment and the one after it
-      uint32_t w[4], wb[4], wr[4];
+      uint32_t w[4], wb[4], wr[4], ws[4];
       w[0] = (rowbase + (uint32_t)xa) >> 5;
       w[2] = rowbase >> 5;  // wrapped segment starts at x = 0
       const uint32_t last1 = xa <= xb ? (rowbase + (uint32_t)xb) >> 5 : (rowbase + (uint32_t)d.nx - 1u) >> 5;
@@ -254,6 +259,7 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
         const bool use = k < 2 || wrapped;
         wb[k] = use ? bits[w[k]] : 0u;
         wr[k] = use ? rank[w[k]] : 0u;
+        ws[k] = use ? shared[w[k]] : 0u;
       }
       while (m) {
         const int lx = __ffs(m) - 1;
@@ -263,8 +269,9 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
         const int k = wn == w[0] ? 0 : (wn == w[1] ? 1 : (wn == w[2] ? 2 : 3));
         const uint32_t word = k == 0 ? wb[0] : (k == 1 ? wb[1] : (k == 2 ? wb[2] : wb[3]));
         const uint32_t rk = k == 0 ? wr[0] : (k == 1 ? wr[1] : (k == 2 ? wr[2] : wr[3]));
+        const uint32_t sw = k == 0 ? ws[0] : (k == 1 ? ws[1] : (k == 2 ? ws[2] : ws[3]));
         const uint32_t slot = rk + __popc(word & ((1u << (n & 31u)) - 1u));
-        if (j < cap) fslot[(size_t)p * fcap + j] = slot;
+        if (j < cap) fslot[(size_t)p * fcap + j] = slot | (((sw >> (n & 31u)) & 1u) ? kSlotShared : 0u);
         ++j;
       }
     }
@@ -308,9 +315,10 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 12
 // bytes holding first the staged velocities (float3 per node) and, once every
 // marker has interpolated, the spread sums of one velocity component (int64
-// per node; the three components are spread one after the other), then
-// fcap/32 u32 (shared flags). About 56 KB for r = 8, so two spheres share a
-// compute unit and one's memory trips overlap the other's LDS work.
+// per node; the three components are spread one after the other), then fcap
+// u32 (the nodes' slots with their shared flag, kept for the write-back).
+// About 72 KB for r = 8, so two spheres share a compute unit and one's
+// memory trips overlap the other's LDS work.
 //
 // The spread sums are 64-bit fixed point in units of 2^-50: LDS integer
 // atomics run at about the rate of plain LDS accesses, while LDS float
@@ -336,8 +344,7 @@ __global__ void __launch_bounds__(kPassBlock, MPT == 1 ? 8 : 4)
 k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om,
            const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
-           const uint32_t* __restrict__ fslot, const uint32_t* __restrict__ list, const uint32_t* __restrict__ shared,
-           const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap, double* __restrict__ F_ib,
+           const uint32_t* __restrict__ fslot, const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap, double* __restrict__ F_ib,
            double* __restrict__ T_ib, int first) {
   extern __shared__ uint32_t lds[];
   const int rows = side * side;
@@ -345,7 +352,7 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   uint32_t* rp = rb + rows;
   float* uj = (float*)(rp + rows);
   unsigned long long* acc = (unsigned long long*)(rp + rows);  // rows * 8 bytes in: 8-byte aligned
-  uint32_t* sh = (uint32_t*)(uj + 3 * (size_t)fcap);
+  uint32_t* sl = (uint32_t*)(uj + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
   const uint32_t* slots = fslot + (size_t)p * fcap;
@@ -368,24 +375,23 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   // A forcing support beyond the LDS capacity was latched as an error when it
   // was built; skip the sphere rather than index past the buffers.
   if (base > fcap || base != cnt) return;
-  for (uint32_t j = threadIdx.x; j < (fcap + 31) / 32; j += kPassBlock) sh[j] = 0u;
   __syncthreads();
   // Stage u = u* + f_IB / (2 rho): all loads of a round are issued before
-  // any is used, so a round costs three dependent trips to memory.
+  // any is used, so a round costs two dependent trips to memory.
   for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
-    uint32_t s[kStage], n[kStage];
+    uint32_t w[kStage], s[kStage];
     float4 v[kStage];
     float f[kStage][3];
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-      s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
+      w[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
+      s[i] = w[i] & ~kSlotShared;
     }
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
       if (s[i] < s_cap) {
         v[i] = us[s[i]];
-        n[i] = list[s[i]];
         for (int k = 0; k < 3; ++k) f[i][k] = fib[(size_t)k * s_cap + s[i]];
       }
     }
@@ -393,6 +399,7 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     for (int i = 0; i < kStage; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
       if (j >= cnt) continue;
+      sl[j] = w[i];
       if (s[i] >= s_cap) {
         uj[3 * j] = uj[3 * j + 1] = uj[3 * j + 2] = 0.0f;
         continue;
@@ -401,7 +408,6 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
       uj[3 * j] = v[i].x + f[i][0] * h;
       uj[3 * j + 1] = v[i].y + f[i][1] * h;
       uj[3 * j + 2] = v[i].z + f[i][2] * h;
-      if ((shared[n[i] >> 5] >> (n[i] & 31u)) & 1u) atomicOr(&sh[j >> 5], 1u << (j & 31u));
     }
   }
   __syncthreads();
@@ -495,8 +501,9 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
 #pragma unroll
       for (int i = 0; i < kStage; ++i) {
         const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-        s[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
-        shr[i] = j < cnt && ((sh[j >> 5] >> (j & 31u)) & 1u);
+        const uint32_t w = j < cnt ? sl[j] : 0xFFFFFFFFu;
+        s[i] = w & ~kSlotShared;
+        shr[i] = j < cnt && (w & kSlotShared);
       }
 #pragma unroll
       for (int i = 0; i < kStage; ++i)
@@ -633,7 +640,7 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
 
 size_t pass_lds_bytes(const Ctx& c) {
   const size_t rows = (size_t)c.ibm.side * c.ibm.side;
-  return rows * 8 + (size_t)c.ibm.fcap * 12 + ((c.ibm.fcap + 31) / 32) * 4;
+  return rows * 8 + (size_t)c.ibm.fcap * 16;
 }
 
 }  // namespace
@@ -673,7 +680,7 @@ hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
     return e;
   if (c.np > 0) {
     hipLaunchKernelGGL(k_ibm_slots, dim3(c.np), dim3(kBlock), 0, c.stream, X, m.R_b, m.side, c.dims, m.bits[buf],
-                       m.rank[buf], m.rowbits, m.fcount, m.fcap, m.fslot);
+                       m.rank[buf], m.shared, m.rowbits, m.fcount, m.fcap, m.fslot);
     e = hipGetLastError();
   }
   return e;
@@ -708,11 +715,11 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
       // wall only
     } else if (m.n_markers <= kPassBlock)
       hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
-                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
+                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.us,
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
     else
       hipLaunchKernelGGL(k_ibm_pass<2>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
-                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.list, m.shared, m.us,
+                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.us,
                          m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
