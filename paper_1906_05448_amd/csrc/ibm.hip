@@ -329,6 +329,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // collision kernel latches as unstable.
 constexpr int kPassBlock = 1024;
 constexpr int kStage = 3;  // support nodes per thread per staging round
+constexpr int kWrite = 5;  // support nodes per thread per write-back round
 constexpr double kFixScale = 0x1p50;
 constexpr double kFixUnit = 0x1p-50;
 
@@ -494,22 +495,22 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     }
     __syncthreads();
     float* fc = fib + (size_t)comp * s_cap;
-    for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
-      uint32_t s[kStage];
-      float old[kStage];
-      bool shr[kStage];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kWrite * kPassBlock) {
+      uint32_t s[kWrite];
+      float old[kWrite];
+      bool shr[kWrite];
 #pragma unroll
-      for (int i = 0; i < kStage; ++i) {
+      for (int i = 0; i < kWrite; ++i) {
         const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
         const uint32_t w = j < cnt ? sl[j] : 0xFFFFFFFFu;
         s[i] = w & ~kSlotShared;
         shr[i] = j < cnt && (w & kSlotShared);
       }
 #pragma unroll
-      for (int i = 0; i < kStage; ++i)
+      for (int i = 0; i < kWrite; ++i)
         if (s[i] < s_cap && !shr[i]) old[i] = fc[s[i]];
 #pragma unroll
-      for (int i = 0; i < kStage; ++i) {
+      for (int i = 0; i < kWrite; ++i) {
         if (s[i] >= s_cap) continue;
         const float v = from_fix(acc[j0 + threadIdx.x + i * kPassBlock]);
         if (shr[i])
