@@ -281,21 +281,29 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   const float band = (float)mv + 0.01f, rf = (float)r;
   const float Xf[3] = {(float)Xn[0], (float)Xn[1], (float)Xn[2]};
   auto min_image_f = [](float v, float L) { return v > 0.5f * L ? v - L : (v < -0.5f * L ? v + L : v); };
-  const BoxLin L = box_lin(b);
-  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
+  // The scan only finds the nodes that changed side (arithmetic, no memory
+  // traffic) and appends them to its wavefront's LDS list in lane order; the
+  // list is processed one node per lane when it would overflow and at the
+  // end, so the owner and population loads of a node's refill are paid once
+  // per list rather than once per scan iteration that finds a node. Refills
+  // read only nodes that are fluid in both maps, never another refilled
+  // node, so the processing order does not matter.
+  __shared__ uint32_t cand_all[kBlock];
+  uint32_t* cand = cand_all + (threadIdx.x & ~63u);
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t ncand = 0;
+  auto process = [&](uint32_t count) {
+    __builtin_amdgcn_wave_barrier();  // the list entries other lanes wrote
+    if (lane >= count) return;
     int x, y, z;
-    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-    const float fx = min_image_f((float)x - Xf[0], (float)d.nx), fy = min_image_f((float)y - Xf[1], (float)d.ny),
-                fz = min_image_f((float)z - Xf[2], (float)d.nz);
-    if (fabsf(sqrtf(fx * fx + fy * fy + fz * fz) - rf) > band) continue;
-    const bool in_old = inside(x, y, z, Xo), in_new = inside(x, y, z, Xn);
-    if (in_old == in_new) continue;
+    unpack_xyz(cand[lane], x, y, z);
+    const bool in_old = inside(x, y, z, Xo);
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
                           min_image((double)z - Xn[2], d.nz)};
     if (in_old) {
       // uncovered: solid for p before, fluid now
-      if (o_old[n] != p || o_new[n] != kFluid) continue;
+      if (o_old[n] != p || o_new[n] != kFluid) return;
       const double uw[3] = {Up[0] + (Wp[1] * dd[2] - Wp[2] * dd[1]), Up[1] + (Wp[2] * dd[0] - Wp[0] * dd[2]),
                             Up[2] + (Wp[0] * dd[1] - Wp[1] * dd[0])};
       double mom[3];
@@ -306,7 +314,7 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       T[2] -= dd[0] * mom[1] - dd[1] * mom[0];
     } else {
       // covered: fluid before, solid for p now
-      if (o_new[n] != p || o_old[n] != kFluid) continue;
+      if (o_new[n] != p || o_old[n] != kFluid) return;
       double mom[3] = {0, 0, 0};
       for (int k = 0; k < kQ; ++k) {
         const double g = (double)ld<STORE>(B, k, d.N, n);
@@ -319,7 +327,34 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       T[1] += dd[2] * mom[0] - dd[0] * mom[2];
       T[2] += dd[0] * mom[1] - dd[1] * mom[0];
     }
+  };
+  const BoxLin L = box_lin(b);
+  // every lane of the block runs the same number of iterations, so the
+  // wavefront-wide ballots below see all 64 lanes
+  for (uint32_t i0 = 0; i0 < L.count; i0 += kBlock) {
+    const uint32_t i = i0 + threadIdx.x;
+    bool hit = false;
+    uint32_t packed = 0;
+    if (i < L.count) {
+      int x, y, z;
+      box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
+      const float fx = min_image_f((float)x - Xf[0], (float)d.nx), fy = min_image_f((float)y - Xf[1], (float)d.ny),
+                  fz = min_image_f((float)z - Xf[2], (float)d.nz);
+      if (!(fabsf(sqrtf(fx * fx + fy * fy + fz * fz) - rf) > band)) {
+        hit = inside(x, y, z, Xo) != inside(x, y, z, Xn);
+        packed = pack_xyz(x, y, z);
+      }
+    }
+    const unsigned long long m = __ballot(hit);
+    const uint32_t nhit = (uint32_t)__popcll(m);
+    if (ncand + nhit > 64u) {  // uniform across the wavefront
+      process(ncand);
+      ncand = 0;
+    }
+    if (hit) cand[ncand + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = packed;
+    ncand += nhit;
   }
+  process(ncand);
   for (int k = 0; k < 3; ++k) {
     const double fs = block_sum<kBlock>(F[k]);
     const double ts = block_sum<kBlock>(T[k]);
