@@ -109,6 +109,13 @@ __device__ __forceinline__ uint32_t neighbour(int x, int y, int z, int k, int i,
                     d.nx, d.ny);
 }
 
+// Index offset of t steps (|t| <= 2 < n) from coordinate c along an axis of
+// n nodes and index stride `stride`, with the periodic wrap.
+__device__ __forceinline__ int step_offset(int c, int t, int n, int stride) {
+  const int v = c + t;
+  return (v < 0 ? t + n : (v >= n ? t - n : t)) * stride;
+}
+
 // Examines the buffered shell candidates and writes their links from slot
 // `written` on. Every thread must call it. Per chunk of kBlock candidates the
 // lanes first find each candidate's links (owner lookups, all issued before
@@ -126,13 +133,27 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
       int x, y, z;
       unpack_xyz(cand[k], x, y, z);
       uint32_t own[kQ], own1[kQ], own2[kQ];
-      own[0] = owner[node_index(x, y, z, d.nx, d.ny)];
+      const int n = (int)node_index(x, y, z, d.nx, d.ny);
+      // index offsets of steps -2..2 along each axis, periodic wrap included;
+      // neighbour k c_a of n is n plus one offset per axis
+      const int sy = d.nx, sz = d.nx * d.ny;
+      int ox[5], oy[5], oz[5];
 #pragma unroll
-      for (int a = 1; a < kQ; ++a) own[a] = owner[neighbour(x, y, z, 1, a, d)];
+      for (int t = -2; t <= 2; ++t) {
+        ox[t + 2] = step_offset(x, t, d.nx, 1);
+        oy[t + 2] = step_offset(y, t, d.ny, sy);
+        oz[t + 2] = step_offset(z, t, d.nz, sz);
+      }
+      auto nb = [&](int kk, int a) -> uint32_t {
+        return (uint32_t)(n + ox[kk * cx_of(a) + 2] + oy[kk * cy_of(a) + 2] + oz[kk * cz_of(a) + 2]);
+      };
+      own[0] = owner[n];
 #pragma unroll
-      for (int a = 1; a < kQ; ++a) own1[a] = owner[neighbour(x, y, z, -1, a, d)];
+      for (int a = 1; a < kQ; ++a) own[a] = owner[nb(1, a)];
 #pragma unroll
-      for (int a = 1; a < kQ; ++a) own2[a] = owner[neighbour(x, y, z, -2, a, d)];
+      for (int a = 1; a < kQ; ++a) own1[a] = owner[nb(-1, a)];
+#pragma unroll
+      for (int a = 1; a < kQ; ++a) own2[a] = owner[nb(-2, a)];
       if (own[0] == kFluid) {
 #pragma unroll
         for (int a = 1; a < kQ; ++a) {
