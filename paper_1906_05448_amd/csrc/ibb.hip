@@ -32,30 +32,44 @@ __device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint
   return Pop<STORE>::load(f + (size_t)i * N + n);
 }
 
-// Interpolated value of the entering population for one link.
+// Interpolated value of the entering population for one link, from the
+// values the scheme reads: ga0 = g_a(x_f) and, with q < 1/2, v1 = g_a(x_f - c),
+// v2 = g_a(x_f - 2c); with q >= 1/2, v1 = g_ab(x_f), v2 = g_ab(x_f - c)
+// (ab the opposite of a). The linear scheme uses v1 only, the single-node
+// scheme neither.
+__device__ __forceinline__ float bounce_from(float ga0, float v1, float v2, uint32_t scheme, float q, float delta) {
+  if (scheme == kSchemeQuadratic) {
+    if (q < 0.5f) return q * (1.0f + 2.0f * q) * ga0 + (1.0f - 4.0f * q * q) * v1 - q * (1.0f - 2.0f * q) * v2 + delta;
+    const float t = 2.0f * q - 1.0f;
+    return (ga0 + delta) / (q * (2.0f * q + 1.0f)) + t / q * v1 - t / (2.0f * q + 1.0f) * v2;
+  }
+  if (scheme == kSchemeLinear) {
+    if (q < 0.5f) return 2.0f * q * ga0 + (1.0f - 2.0f * q) * v1 + delta;
+    return (ga0 + delta) / (2.0f * q) + (2.0f * q - 1.0f) / (2.0f * q) * v1;
+  }
+  return ga0 + delta;
+}
+
+// Population array and node of the two extra values a link reads.
+__device__ __forceinline__ void bounce_sources(int a, float q, uint32_t nf, uint32_t nm1, uint32_t nm2, int& i1,
+                                               uint32_t& n1, int& i2, uint32_t& n2) {
+  const bool lo = q < 0.5f;
+  i1 = lo ? a : opp_of(a);
+  n1 = lo ? nm1 : nf;
+  i2 = i1;
+  n2 = lo ? nm2 : nm1;
+}
+
 template <int STORE>
 __device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, uint32_t N, uint32_t nf, uint32_t nm1,
                                               uint32_t nm2, int a, uint32_t scheme, float q, float delta) {
-  const int ab = opp_of(a);
+  int i1, i2;
+  uint32_t n1, n2;
+  bounce_sources(a, q, nf, nm1, nm2, i1, n1, i2, n2);
   const float ga0 = ld<STORE>(A, a, N, nf);
-  if (scheme == kSchemeQuadratic) {
-    if (q < 0.5f) {
-      const float ga1 = ld<STORE>(A, a, N, nm1), ga2 = ld<STORE>(A, a, N, nm2);
-      return q * (1.0f + 2.0f * q) * ga0 + (1.0f - 4.0f * q * q) * ga1 - q * (1.0f - 2.0f * q) * ga2 + delta;
-    }
-    const float gb0 = ld<STORE>(A, ab, N, nf), gb1 = ld<STORE>(A, ab, N, nm1);
-    const float t = 2.0f * q - 1.0f;
-    return (ga0 + delta) / (q * (2.0f * q + 1.0f)) + t / q * gb0 - t / (2.0f * q + 1.0f) * gb1;
-  }
-  if (scheme == kSchemeLinear) {
-    if (q < 0.5f) {
-      const float ga1 = ld<STORE>(A, a, N, nm1);
-      return 2.0f * q * ga0 + (1.0f - 2.0f * q) * ga1 + delta;
-    }
-    const float gb0 = ld<STORE>(A, ab, N, nf);
-    return (ga0 + delta) / (2.0f * q) + (2.0f * q - 1.0f) / (2.0f * q) * gb0;
-  }
-  return ga0 + delta;
+  const float v1 = scheme != kSchemeHalfway ? ld<STORE>(A, i1, N, n1) : 0.0f;
+  const float v2 = scheme == kSchemeQuadratic ? ld<STORE>(A, i2, N, n2) : 0.0f;
+  return bounce_from(ga0, v1, v2, scheme, q, delta);
 }
 
 // One workgroup per sphere: fill the ghost slots of its links and reduce the
@@ -73,40 +87,74 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
   const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
   const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
-    const uint32_t nf = link_node[base + k];
-    const float q = link_q[base + k];
-    const uint32_t meta = link_meta[base + k];
-    const int a = (int)(meta & 31u);
-    const uint32_t scheme = meta >> 5;
-    int x, y, z;
-    unpack_xyz(nf, x, y, z);
-    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
-    // lever arm x_w - X and wall velocity U + Omega x arm
-    const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q * cx,
-                           min_image((double)y - Xp[1], d.ny) + (double)q * cy,
-                           min_image((double)z - Xp[2], d.nz) + (double)q * cz};
-    const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
-                          Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
-    const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
-    const uint32_t n0 = node_index(x, y, z, d.nx, d.ny);
-    const uint32_t nm1 = node_index(wrap1(x - cx, d.nx), wrap1(y - cy, d.ny), wrap1(z - cz, d.nz), d.nx, d.ny);
-    const uint32_t nm2 =
-        node_index(wrap1(x - 2 * cx, d.nx), wrap1(y - 2 * cy, d.ny), wrap1(z - 2 * cz, d.nz), d.nx, d.ny);
-    const uint32_t ns = node_index(wrap1(x + cx, d.nx), wrap1(y + cy, d.ny), wrap1(z + cz, d.nz), d.nx, d.ny);
-    const float gnew = bounce_value<STORE>(A, d.N, n0, nm1, nm2, a, scheme, q, delta);
-    Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
-    const double fa = (double)ld<STORE>(A, a, d.N, n0) + (double)w_of(a);
-    const double fb = (double)gnew + (double)w_of(a);
-    const double c[3] = {(double)cx, (double)cy, (double)cz};
-    double Fl[3];
-    for (int k3 = 0; k3 < 3; ++k3) Fl[k3] = (c[k3] - uw[k3]) * fa + (c[k3] + uw[k3]) * fb;
-    F[0] += Fl[0];
-    F[1] += Fl[1];
-    F[2] += Fl[2];
-    T[0] += arm[1] * Fl[2] - arm[2] * Fl[1];
-    T[1] += arm[2] * Fl[0] - arm[0] * Fl[2];
-    T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
+  // kLinks links per thread per round: the records of a round, then all the
+  // population values its links read, are in flight together. The ghost
+  // slots written here are at solid nodes, which no link reads.
+  constexpr int kLinks = 4;
+  for (uint32_t k0 = 0; k0 < cnt; k0 += kLinks * kBlock) {
+    uint32_t nf[kLinks], meta[kLinks];
+    float q[kLinks];
+#pragma unroll
+    for (int i = 0; i < kLinks; ++i) {
+      const uint32_t k = k0 + (uint32_t)(i * kBlock) + threadIdx.x;
+      const bool live = k < cnt;
+      nf[i] = live ? link_node[base + k] : 0u;
+      q[i] = live ? link_q[base + k] : 0.0f;
+      meta[i] = live ? (uint32_t)link_meta[base + k] : 0xFFu;
+    }
+    uint32_t n0[kLinks], ns[kLinks];
+    float g0[kLinks], g1[kLinks], g2[kLinks];
+#pragma unroll
+    for (int i = 0; i < kLinks; ++i) {
+      g0[i] = g1[i] = g2[i] = 0.0f;
+      n0[i] = ns[i] = 0u;
+      if (meta[i] == 0xFFu) continue;
+      const int a = (int)(meta[i] & 31u);
+      const uint32_t scheme = meta[i] >> 5;
+      int x, y, z;
+      unpack_xyz(nf[i], x, y, z);
+      const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
+      n0[i] = node_index(x, y, z, d.nx, d.ny);
+      const uint32_t nm1 = node_index(wrap1(x - cx, d.nx), wrap1(y - cy, d.ny), wrap1(z - cz, d.nz), d.nx, d.ny);
+      const uint32_t nm2 =
+          node_index(wrap1(x - 2 * cx, d.nx), wrap1(y - 2 * cy, d.ny), wrap1(z - 2 * cz, d.nz), d.nx, d.ny);
+      ns[i] = node_index(wrap1(x + cx, d.nx), wrap1(y + cy, d.ny), wrap1(z + cz, d.nz), d.nx, d.ny);
+      int i1, i2;
+      uint32_t m1, m2;
+      bounce_sources(a, q[i], n0[i], nm1, nm2, i1, m1, i2, m2);
+      g0[i] = ld<STORE>(A, a, d.N, n0[i]);
+      if (scheme != kSchemeHalfway) g1[i] = ld<STORE>(A, i1, d.N, m1);
+      if (scheme == kSchemeQuadratic) g2[i] = ld<STORE>(A, i2, d.N, m2);
+    }
+#pragma unroll
+    for (int i = 0; i < kLinks; ++i) {
+      if (meta[i] == 0xFFu) continue;
+      const int a = (int)(meta[i] & 31u);
+      const uint32_t scheme = meta[i] >> 5;
+      int x, y, z;
+      unpack_xyz(nf[i], x, y, z);
+      const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
+      // lever arm x_w - X and wall velocity U + Omega x arm
+      const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q[i] * cx,
+                             min_image((double)y - Xp[1], d.ny) + (double)q[i] * cy,
+                             min_image((double)z - Xp[2], d.nz) + (double)q[i] * cz};
+      const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
+                            Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
+      const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
+      const float gnew = bounce_from(g0[i], g1[i], g2[i], scheme, q[i], delta);
+      Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns[i], gnew);
+      const double fa = (double)g0[i] + (double)w_of(a);
+      const double fb = (double)gnew + (double)w_of(a);
+      const double c[3] = {(double)cx, (double)cy, (double)cz};
+      double Fl[3];
+      for (int k3 = 0; k3 < 3; ++k3) Fl[k3] = (c[k3] - uw[k3]) * fa + (c[k3] + uw[k3]) * fb;
+      F[0] += Fl[0];
+      F[1] += Fl[1];
+      F[2] += Fl[2];
+      T[0] += arm[1] * Fl[2] - arm[2] * Fl[1];
+      T[1] += arm[2] * Fl[0] - arm[0] * Fl[2];
+      T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
+    }
   }
   for (int k3 = 0; k3 < 3; ++k3) {
     const double fs = block_sum<kBlock>(F[k3]);
