@@ -137,6 +137,133 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
   if (bad) atomicOr(err, kErrUnstable);
 }
 
+// FP16 storage with rows staged through LDS (nx even). A wavefront owns a
+// 128-node row segment. It reads each population's source segment as aligned
+// dwords (two nodes per lane: the access width the memory system serves
+// best; 16-bit accesses measured slower) plus the node beyond each end, into
+// its own LDS rows; each lane then takes its node's 19 shifted values from
+// LDS as halves (any 2-byte offset), in two rounds of 64 nodes, and collides
+// them exactly as the one-node kernel does. The results return through the
+// same LDS rows and leave as dwords. Round 1 (nodes 64..127) reads one slot
+// that round 0 writes: node 63's, for the directions with c_x = +1; those
+// five results wait in a small tail area until round 1 has read.
+constexpr int kSegW = 128;               // nodes per wavefront segment
+constexpr int kSegRow = (kSegW + 4) / 2; // dwords per population row: 2 halves before, 2 after
+
+__device__ __forceinline__ float half_to_g(uint16_t h) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, h)) * (1.0f / kHalfScale);
+}
+__device__ __forceinline__ uint16_t g_to_half(float g) {
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(g * kHalfScale));
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, Dims d, MrtRates r, float3 F0,
+                     IbView ib, uint32_t* __restrict__ err) {
+  __shared__ uint32_t seg_all[4][kQ][kSegRow];
+  __shared__ uint16_t tail_all[4][kQ];
+  const uint32_t b = blockIdx.x;
+  const uint32_t logical = (b & 7u) * d.per_xcd2 + (b >> 3);
+  if (logical >= d.ntiles2) return;
+  const uint32_t rest = fast_div(d.div_gx2, logical);
+  const uint32_t bx = logical - rest * d.gx2;
+  const uint32_t bz = fast_div(d.div_gy, rest);
+  const uint32_t by = rest - bz * d.gy;
+  const uint32_t lane = threadIdx.x & 63u;
+  const int wv = (int)(threadIdx.x >> 6);
+  const int y = __builtin_amdgcn_readfirstlane((int)(by * 4u) + wv);
+  const int z = (int)bz;
+  if (y >= d.ny) return;  // the whole wavefront
+  uint32_t(*seg)[kSegRow] = seg_all[wv];
+  uint16_t* tail = tail_all[wv];
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const uint32_t N = d.N;
+  const int x0 = (int)bx * kSegW;
+  const int w = min(kSegW, nx - x0);  // nodes in the segment, even
+  auto row = [&](int yy, int zz) -> uint32_t { return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx; };
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const uint32_t r00 = row(y, z), rm0 = row(ym, z), rp0 = row(yp, z);
+  const uint32_t r0m = row(y, zm), r0p = row(y, zp);
+  const uint32_t rmm = row(ym, zm), rmp = row(ym, zp), rpp = row(yp, zp), rpm = row(yp, zm);
+  // source row (y - c_iy, z - c_iz) of direction i
+  const uint32_t srow[kQ] = {r00, r00, rm0, r0m, rm0, rp0, r0m, r0p, rmm, rmp,
+                             r00, rp0, r0p, rp0, rm0, r0p, r0m, rpp, rpm};
+  // the node left of the segment and the one right of it (periodic)
+  const uint32_t xl = (uint32_t)(x0 == 0 ? nx - 1 : x0 - 1);
+  const uint32_t xr = (uint32_t)(x0 + w >= nx ? 0 : x0 + w);
+  const bool pair_live = 2 * (int)lane < w;
+
+  // stage: every load of the segment issued before the first LDS write
+  uint32_t v[kQ];
+  uint16_t e[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const _Float16* rowp = A + (size_t)i * N + srow[i];
+    v[i] = pair_live ? *(const uint32_t*)(rowp + x0 + 2 * (int)lane) : 0u;
+    // edge node: the aligned dword that holds it (a uniform address, so a
+    // scalar load), then its half
+    const uint32_t xe = cx_of(i) > 0 ? xl : xr;
+    if (cx_of(i) != 0) {
+      const uint32_t wd = ((const uint32_t*)rowp)[xe >> 1];
+      e[i] = (uint16_t)((xe & 1u) ? wd >> 16 : wd & 0xFFFFu);
+    } else {
+      e[i] = 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    uint16_t* h = (uint16_t*)seg[i];
+    seg[i][1 + lane] = v[i];  // halves 2 + 2 lane, 3 + 2 lane
+    if (lane == 0 && cx_of(i) > 0) h[1] = e[i];       // x0 - 1
+    if (lane == 0 && cx_of(i) < 0) h[2 + w] = e[i];   // x0 + w
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  bool bad = false;
+  // one round at a time (unrolled, the rounds' values would all be live)
+#pragma unroll 1
+  for (int rnd = 0; rnd < 2; ++rnd) {
+    const int j = (int)lane + 64 * rnd;
+    const bool live = j < w;
+    const uint32_t n = r00 + (uint32_t)(x0 + j);
+    float3 F = F0;
+    if (MODE == 2 && live) {
+      F = body_force_at(ib, n, F0);
+      add_ib_force(ib, n, F);
+    }
+    float g[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) g[i] = half_to_g(((const uint16_t*)seg[i])[2 + j - cx_of(i)]);
+    float rho, ux, uy, uz;
+    mrt_collide(g, F.x, F.y, F.z, r, rho, ux, uy, uz);
+    bad = bad || (live && (!(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f)));
+    // every lane has read this round's inputs (same wavefront, in order)
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      uint16_t* h = (uint16_t*)seg[i];
+      if (rnd == 0 && cx_of(i) > 0 && lane == 63u)
+        tail[i] = g_to_half(g[i]);
+      else
+        h[2 + j] = g_to_half(g[i]);
+    }
+  }
+  if (lane == 63u) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      if (cx_of(i) > 0) ((uint16_t*)seg[i])[2 + 63] = tail[i];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (pair_live) {
+    const uint32_t off = (r00 + (uint32_t)(x0 + 2 * (int)lane)) * 2u;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      __builtin_nontemporal_store(seg[i][1 + lane], (uint32_t*)((char*)(B + (size_t)i * N) + off));
+  }
+  if (bad) atomicOr(err, kErrUnstable);
+}
+
 template <int STORE>
 __global__ void __launch_bounds__(256)
 k_init_equilibrium(const float* __restrict__ u, const float* __restrict__ rho, typename Pop<STORE>::T* __restrict__ f,
@@ -197,10 +324,16 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 // them saves no cache lines and only costs divergence. Their values are never
 // read by a fluid node (those pull the ghost slots) and are refilled before
 // the node turns fluid.
+// FP16 storage with an even row length stages its rows through LDS.
+static bool use_seg_kernel(const Ctx& c) { return c.cfg.store == LBM_STORE_F16S && c.dims.nx % 2 == 0; }
+
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
-  if (c.cfg.store == LBM_STORE_F32)
+  if (use_seg_kernel(c))
+    hipLaunchKernelGGL((k_stream_collide_seg<0>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
+                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, none, c.err);
+  else if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
                        c.rates, c.body_force, none, c.err);
   else
@@ -213,7 +346,10 @@ hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
   const dim3 grid(c.dims.per_xcd * 8), block(256);
   const int b = c.ibm.cur;
   const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap, ibm_body_force_mask(c)};
-  if (c.cfg.store == LBM_STORE_F32)
+  if (use_seg_kernel(c))
+    hipLaunchKernelGGL((k_stream_collide_seg<2>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
+                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, ib, c.err);
+  else if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL((k_stream_collide<0, 2>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
                        c.rates, c.body_force, ib, c.err);
   else

@@ -58,6 +58,9 @@ struct Dims {
   uint32_t ntiles;  // gx * gy * nz
   uint32_t per_xcd; // ceil(ntiles / 8)
   FastDiv div_gx, div_gy;
+  // Tiles of 128 x 4 nodes for the FP16 kernel that stages rows in LDS.
+  uint32_t gx2, ntiles2, per_xcd2;
+  FastDiv div_gx2;
 };
 
 inline Dims make_dims(int nx, int ny, int nz) {
@@ -72,6 +75,10 @@ inline Dims make_dims(int nx, int ny, int nz) {
   d.per_xcd = (d.ntiles + 7) / 8;
   d.div_gx = make_fastdiv(d.gx);
   d.div_gy = make_fastdiv(d.gy);
+  d.gx2 = (uint32_t)(nx + 127) / 128;
+  d.ntiles2 = d.gx2 * d.gy * (uint32_t)nz;
+  d.per_xcd2 = (d.ntiles2 + 7) / 8;
+  d.div_gx2 = make_fastdiv(d.gx2);
   return d;
 }
 
