@@ -378,7 +378,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(head_name),
-                     "kernel": "k_stream_collide", "alg_bytes_per_launch": head["alg_bytes"],
+                     "kernel": "k_stream_collide_seg" if hs == "f16s" and n % 2 == 0 else "k_stream_collide",
+                     "alg_bytes_per_launch": head["alg_bytes"],
                      "avg_launch_ms": round(head["kernel_avg_ms"], 4)},
         "stream_copy": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
