@@ -15,7 +15,29 @@ def summary(db: str) -> list:
     return rows
 
 
+def _demangle_lbm(name: str) -> str:
+    """Names the profiler leaves mangled (the _Float16 kernels): namespace
+    path and integer template arguments, e.g. lbm::k_stream_collide_seg<0>."""
+    import re
+    rest = name[len("_ZN"):]
+    parts = []
+    while rest and rest[0].isdigit():
+        m = re.match(r"(\d+)", rest)
+        n = int(m.group(1))
+        ident = rest[len(m.group(1)):len(m.group(1)) + n]
+        rest = rest[len(m.group(1)) + n:]
+        if ident != "_GLOBAL__N_1":
+            parts.append(ident)
+    args = re.match(r"I((?:Li-?\d+E|Lb[01]E)+)E", rest)
+    targs = ""
+    if args:
+        targs = "<" + ", ".join(re.findall(r"L[ib](-?\d+)E", args.group(1))) + ">"
+    return "::".join(parts) + targs
+
+
 def short(name: str) -> str:
+    if name.startswith("_ZN"):
+        return _demangle_lbm(name)
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0]
 
