@@ -292,3 +292,36 @@ def test_soft_sphere_head_on_restitution_closed_form():
     v_out = P.U[1, 0] - P.U[0, 0]
     assert abs(v_out / v_in - e) < 0.01
     assert abs(t_contact / tc - 1) < 0.02
+
+
+def test_link_q_matches_bisection():
+    """q from the cancellation-free root agrees with bisection on
+    |x_f + t c - X|^2 = r^2 to 1e-12 for random links of random spheres."""
+    from oracle.lattice import C
+    rng = np.random.default_rng(17)
+    checked = 0
+    for _ in range(40):
+        X = rng.random(3) * 2.0 + 10.0
+        r = 2.0 + 4.0 * rng.random()
+        for a in range(1, 19):
+            c = np.array(C[a], float)
+            # fluid node just outside, whose neighbour along c is inside
+            for _ in range(5):
+                d = rng.normal(size=3)
+                d = d / np.linalg.norm(d) * (r + 0.3 * rng.random())
+                xf = np.round(X + d)
+                dv = xf - X
+                if np.dot(dv, dv) < r * r or np.dot(dv + c, dv + c) >= r * r:
+                    continue
+                q = float(geo.sphere_q(dv, c, r))
+                lo, hi = 0.0, 1.0
+                for _ in range(200):
+                    mid = 0.5 * (lo + hi)
+                    p = dv + mid * c
+                    if np.dot(p, p) >= r * r:
+                        lo = mid
+                    else:
+                        hi = mid
+                assert abs(q - 0.5 * (lo + hi)) < 1e-12
+                checked += 1
+    assert checked > 100
