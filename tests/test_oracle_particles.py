@@ -231,6 +231,12 @@ def test_marker_volume_matches_cell_volume(r):
         assert np.abs(d.mean(0)).max() < 2.0 / n
 
 
+def test_marker_counts_of_the_configurations():
+    # N_L = round(pi (12 r_L^2 + 1) / 3) for the radii used here: r = 8 and
+    # r = 4.5 with markers on the surface or retracted by 0.4.
+    assert [ibm.sphere_marker_count(rl) for rl in (8.0, 7.6, 4.5, 4.1)] == [805, 727, 256, 212]
+
+
 def test_forcing_layer_fraction_printed_in_paper():
     # Sec. 3.2.1 prints the share of the particle volume inside the forcing
     # layer: 0.704 (d = 12 cells) and 0.421 (d = 24). A shell as thick as
