@@ -26,6 +26,7 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kLinkBlock = 1024;  // one workgroup per sphere in the link kernel
 
 template <int STORE>
 __device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint32_t N, uint32_t n) {
@@ -75,7 +76,7 @@ __device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, u
 // One workgroup per sphere: fill the ghost slots of its links and reduce the
 // link forces and torques in FP64 in a fixed order.
 template <int STORE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kLinkBlock)
 k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, const double* __restrict__ U,
             const double* __restrict__ Om, uint32_t cap, const uint32_t* __restrict__ link_node,
             const float* __restrict__ link_q, const uint8_t* __restrict__ link_meta,
@@ -88,15 +89,17 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
   const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   // kLinks links per thread per round: the records of a round, then all the
-  // population values its links read, are in flight together. The ghost
-  // slots written here are at solid nodes, which no link reads.
-  constexpr int kLinks = 4;
-  for (uint32_t k0 = 0; k0 < cnt; k0 += kLinks * kBlock) {
+  // population values its links read, are in flight together, so a sphere's
+  // links (about 4600 at r = 8) go out in one round and the cache lines
+  // they share are fetched once. The ghost slots written here are at solid
+  // nodes, which no link reads.
+  constexpr int kLinks = 5;
+  for (uint32_t k0 = 0; k0 < cnt; k0 += kLinks * kLinkBlock) {
     uint32_t nf[kLinks], meta[kLinks];
     float q[kLinks];
 #pragma unroll
     for (int i = 0; i < kLinks; ++i) {
-      const uint32_t k = k0 + (uint32_t)(i * kBlock) + threadIdx.x;
+      const uint32_t k = k0 + (uint32_t)(i * kLinkBlock) + threadIdx.x;
       const bool live = k < cnt;
       nf[i] = live ? link_node[base + k] : 0u;
       q[i] = live ? link_q[base + k] : 0.0f;
@@ -157,8 +160,8 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
     }
   }
   for (int k3 = 0; k3 < 3; ++k3) {
-    const double fs = block_sum<kBlock>(F[k3]);
-    const double ts = block_sum<kBlock>(T[k3]);
+    const double fs = block_sum<kLinkBlock>(F[k3]);
+    const double ts = block_sum<kLinkBlock>(T[k3]);
     if (threadIdx.x == 0) {
       F_out[3 * p + k3] = fs;
       T_out[3 * p + k3] = ts;
@@ -429,11 +432,11 @@ hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double
   }
   if (c.np <= 0) return hipSuccess;
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_ibb_links<0>, dim3(c.np), dim3(kBlock), 0, c.stream, (float*)A, c.dims, X, U, Om,
+    hipLaunchKernelGGL(k_ibb_links<0>, dim3(c.np), dim3(kLinkBlock), 0, c.stream, (float*)A, c.dims, X, U, Om,
                        c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
                        c.P.T_link);
   else
-    hipLaunchKernelGGL(k_ibb_links<1>, dim3(c.np), dim3(kBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
+    hipLaunchKernelGGL(k_ibb_links<1>, dim3(c.np), dim3(kLinkBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
                        c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
                        c.P.T_link);
   return hipGetLastError();
