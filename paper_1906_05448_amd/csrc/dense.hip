@@ -33,8 +33,8 @@ __device__ __forceinline__ Tile tile_coords(const Dims& d) {
   const uint32_t bx = logical - rest * d.gx;
   const uint32_t bz = fast_div(d.div_gy, rest);
   const uint32_t by = rest - bz * d.gy;
-  t.x = (int)(bx * 64u + (threadIdx.x & 63u));
-  t.y = (int)(by * 4u + (threadIdx.x >> 6));
+  t.x = (int)(bx * 128u + (threadIdx.x & 127u));
+  t.y = (int)(by * 2u + (threadIdx.x >> 7));
   t.z = (int)bz;
   t.live = t.live && t.x < d.nx && t.y < d.ny;
   return t;
@@ -77,7 +77,7 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
   using P = Pop<STORE>;
   const Tile t = tile_coords(d);
   if (!t.live) return;
-  // One wavefront covers one 64-node row: y is uniform across it. With FP32
+  // One wavefront covers 64 nodes of one row: y is uniform across it. With FP32
   // storage the kernel keeps the row offsets in scalar registers (measured
   // 1.3% faster at 512^3); with FP16 the per-lane offsets measured 1.7%
   // faster, so that form is kept there.
@@ -168,8 +168,8 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   if (logical >= d.ntiles2) return;
   const uint32_t rest = fast_div(d.div_gx2, logical);
   const uint32_t bx = logical - rest * d.gx2;
-  const uint32_t bz = fast_div(d.div_gy, rest);
-  const uint32_t by = rest - bz * d.gy;
+  const uint32_t bz = fast_div(d.div_gy2, rest);
+  const uint32_t by = rest - bz * d.gy2;
   const uint32_t lane = threadIdx.x & 63u;
   const int wv = (int)(threadIdx.x >> 6);
   const int y = __builtin_amdgcn_readfirstlane((int)(by * 4u) + wv);
