@@ -119,11 +119,13 @@ def test_dense_full_size_sampled(store):
     assert np.sqrt(np.mean(np.square(errs))) < TOL[store]
 
 
-def test_instability_is_reported():
+@pytest.mark.parametrize("store,nx", [(0, 8), (1, 8), (1, 9)])
+def test_instability_is_reported(store, nx):
+    # both stream-collide kernels latch it: FP32 / odd-row FP16 (one node per
+    # lane) and even-row FP16 (rows staged through LDS)
     from paper_1906_05448_amd import lbm
-    shape = (8, 8, 8)
-    g = gpu_lattice(gpu_config(nx=8, ny=8, nz=8, tau=0.6))
-    u = np.zeros((3, 8, 8, 8))
+    g = gpu_lattice(gpu_config(nx=nx, ny=8, nz=8, tau=0.6, store=store))
+    u = np.zeros((3, 8, 8, nx))
     u[0] = 0.4                      # above the |u| < 0.35 guard
     g.set_fields(u)
     g.step(1)
