@@ -189,6 +189,8 @@ void ibm_support_bounds(double r, double r_d, uint32_t& forcing, uint32_t& full)
 struct Plan {
   size_t f_a, f_b, err, scratch, stats_part;
   size_t pdoubles;       // particle FP64 block
+  size_t cell_head, cell_next;
+  int cells[3];
   size_t owner[2], solid_bits, wall_bits;
   size_t link_node, link_q, link_meta, link_count;
   size_t wl_node, wl_q, wl_meta;
@@ -202,6 +204,21 @@ struct Plan {
 };
 
 constexpr int kParticleVecs = 21;  // [P][3] FP64 arrays in ParticleBufs (plus r, rho, U0)
+
+// Contact cell grid: cells at least 2 max_radius wide (plus a margin against
+// rounding of the cell index), so spheres in contact sit in the same or
+// adjacent cells. Coarsened, which keeps that property, until the grid holds
+// at most 8 cells per particle.
+void contact_cells(const lbm_config& c, size_t P, int n[3]) {
+  const double h = 2.0 * c.max_radius + 0.01;
+  const int L[3] = {c.nx, c.ny, c.nz};
+  for (int a = 0; a < 3; ++a) n[a] = std::max(1, (int)std::floor((double)L[a] / h));
+  const size_t cap = std::max<size_t>(8 * P, 4096);
+  while ((size_t)n[0] * n[1] * n[2] > cap) {
+    const int a = n[0] >= n[1] && n[0] >= n[2] ? 0 : (n[1] >= n[2] ? 1 : 2);
+    n[a] = std::max(1, n[a] / 2);
+  }
+}
 
 Plan plan(const lbm_config& c) {
   Plan p{};
@@ -220,6 +237,10 @@ Plan plan(const lbm_config& c) {
   p.stats_part = take(stats_part_bytes());
   const size_t P = has_particles(c) ? (size_t)c.max_particles : 0;
   p.pdoubles = take((size_t)(kParticleVecs * 3 + 2 + 3) * std::max<size_t>(P, 1) * sizeof(double));
+  p.cells[0] = p.cells[1] = p.cells[2] = 1;
+  if (P) contact_cells(c, P, p.cells);
+  p.cell_head = take((size_t)p.cells[0] * p.cells[1] * p.cells[2] * 4);
+  p.cell_next = take(std::max<size_t>(P, 1) * 4);
   p.wall_bits = take(words * 4);
   p.solid_bits = take(words * 4);
   if (c.bc != LBM_BC_NONE) {
@@ -518,6 +539,9 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     B.r = d;
     d += P;
     B.rho = d;
+    B.cell_head = (uint32_t*)(base + p.cell_head);
+    B.cell_next = (uint32_t*)(base + p.cell_next);
+    for (int a = 0; a < 3; ++a) B.cells[a] = p.cells[a];
   }
   c.ibb = IbbBufs{};
   c.ibb.wall_bits = (uint32_t*)(base + p.wall_bits);

@@ -155,6 +155,9 @@ struct ParticleBufs {
   double* Iu_new;
   double* IL_new;
   double* Xown[2]; // positions owner map [b] was last built for
+  uint32_t* cell_head;  // [cells] first particle of each contact cell
+  uint32_t* cell_next;  // [P] next particle in the same cell
+  int cells[3];         // contact cell grid
 };
 
 // Interpolated bounce-back geometry.

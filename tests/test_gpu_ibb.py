@@ -195,3 +195,40 @@ def test_prescribed_spheres_cross_periodic_faces(store):
     assert Xf[0, 0] > 20 and Xf[0, 2] < 5 and Xf[1, 1] < 5
     assert uncovered > 0
     g.close()
+
+
+def _crowded_sphere(centre, R, r, n, overlap):
+    """A sphere of radius R touched by n spheres of radius r, centres on a
+    Fibonacci lattice at distance R + r - overlap."""
+    k = np.arange(n) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / n)
+    theta = np.pi * (1.0 + 5.0 ** 0.5) * k
+    d = np.stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)], axis=1)
+    X = np.vstack([centre, np.asarray(centre) + (R + r - overlap) * d])
+    rad = np.concatenate([[R], np.full(n, r)])
+    return X, rad
+
+
+@pytest.mark.parametrize("side", [40, 52])
+def test_contact_forces_many_partners(side):
+    """One sphere touched by 70 others, more partners than one particle's
+    collected list holds, on contact grids of one (40^3) and two (52^3)
+    cells per axis. Contact forces follow the soft-sphere law of Sec. 3.1
+    summed in index order; pair forces cancel (Newton's third law)."""
+    c = side / 2.0
+    X, rad = _crowded_sphere((c, c, c), 12.0, 2.0, 70, 0.3)
+    dmin = min(np.linalg.norm(X[1:] - X[i], axis=1)[i:].min() for i in range(1, 70))
+    assert dmin > 2 * 2.0  # only the central sphere is in contact
+    U = np.random.default_rng(11).normal(scale=0.01, size=X.shape)
+    shape = (side, side, side)
+    o, g = _pair(shape, tau=0.6, max_np=71, max_r=12.0, coll_restitution=0.9, coll_tc_steps=8.0)
+    o.set_particles(X, U=U, r=rad)
+    g.set_particles(X, rad, u=U)
+    o.step(1)
+    g.step(1)
+    _, _, Fcg = g.forces()
+    Fco = o.state.F_c
+    assert np.abs(Fco[0]).max() > 0 and np.all(np.abs(Fco[1:]).max(axis=1) > 0)
+    assert np.abs(Fcg - Fco).max() <= 1e-12 * np.abs(Fco).max()
+    assert np.abs(Fcg.sum(axis=0)).max() <= 1e-12 * np.abs(Fcg).max()
+    g.close()
