@@ -596,6 +596,15 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     }
   }
 
+  if (cfg->bc == LBM_BC_IBB && has_particles(*cfg)) {
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) != hipSuccess ||
+        links_build_lds_total(cfg->max_radius) > (size_t)lds_max) {
+      delete h;
+      return LBM_E_SIZE;
+    }
+  }
+
   // Start at rest, density 1: shifted populations are all zero.
   hipError_t e = hipMemsetAsync(c.f_cur, 0, pop_bytes(*cfg), c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(c.err, 0, sizeof(uint32_t), c.stream);

@@ -109,57 +109,63 @@ __device__ __forceinline__ uint32_t neighbour(int x, int y, int z, int k, int i,
                     d.nx, d.ny);
 }
 
-// Index offset of t steps (|t| <= 2 < n) from coordinate c along an axis of
-// n nodes and index stride `stride`, with the periodic wrap.
-__device__ __forceinline__ int step_offset(int c, int t, int n, int stride) {
-  const int v = c + t;
-  return (v < 0 ? t + n : (v >= n ? t - n : t)) * stride;
+// Shell candidates of one row of a sphere's box. With e2 the squared
+// distance of the row (y, z) from the centre, a link's fluid end x satisfies
+// (x - X0)^2 < ro2 - e2 (it lies within r + |c| of the centre) and is not
+// inside the sphere, (x - X0)^2 >= r2 - e2. Both bounds only prune (the owner
+// map decides), so the intervals are taken slightly wide: the hole keeps a
+// margin of 1e-6 (r2 + 1) below r2, so every node it drops is inside the
+// sphere by the owner map's test as well. Returns up to two intervals
+// [a0, a1], [b0, b1] of unwrapped x within [lo, hi]; empty ones have a1 < a0.
+__device__ __forceinline__ void shell_row(double X0, double e2, double r2, double ro2, int lo, int hi, int& a0, int& a1,
+                                          int& b0, int& b1) {
+  a0 = b0 = 1;
+  a1 = b1 = 0;
+  if (!(e2 < ro2)) return;
+  const double xo = sqrt(ro2 - e2) + 1e-9;
+  const int o0 = max((int)ceil(X0 - xo), lo), o1 = min((int)floor(X0 + xo), hi);
+  a0 = o0;
+  a1 = o1;
+  const double hole = r2 - e2 - 1e-6 * (r2 + 1.0);
+  if (!(hole > 0.0)) return;
+  // dropped: |x - X0| < xi, the integers strictly between X0 - xi and X0 + xi
+  const double xi = sqrt(hole) - 1e-9;
+  const int left_hi = (int)floor(X0 - xi), right_lo = (int)ceil(X0 + xi);
+  if (left_hi + 1 > right_lo - 1) return;
+  a1 = min(left_hi, o1);
+  b0 = max(right_lo, max(o0, a1 + 1));
+  b1 = o1;
 }
 
-// Examines the buffered shell candidates and writes their links from slot
-// `written` on. Every thread must call it. Per chunk of kBlock candidates the
-// lanes first find each candidate's links (owner lookups, all issued before
-// any is used), list them in LDS in candidate-then-direction order, and then
-// evaluate q and the scheme with one link per lane, so the FP64 root is
-// computed with every lane busy and the records are written contiguously.
-__device__ void flush_candidates(const uint32_t* __restrict__ owner, const double* Xp, double r, const Dims& d,
-                                 int max_order, uint32_t p, uint32_t cap, size_t base, const uint32_t* cand,
+__device__ __forceinline__ uint32_t plane_bit(const uint32_t* plane, int i) {
+  return (plane[i >> 5] >> (i & 31)) & 1u;
+}
+
+// Examines the listed shell candidates (local coordinates in the staged box
+// sb) and writes their links from slot `written` on. Every thread must call
+// it. Per chunk of kBlock candidates the lanes find each candidate's links
+// from the LDS bit planes (fluid, owned by p), list them in LDS in
+// candidate-then-direction order, then evaluate q and the scheme with one
+// link per lane, so the FP64 root is computed with every lane busy and the
+// records are written contiguously.
+__device__ void flush_candidates(const uint32_t* fl, const uint32_t* op, const Box& sb, const double* Xp, double r,
+                                 const Dims& d, int max_order, uint32_t cap, size_t base, const uint32_t* cand,
                                  int ncand, uint16_t* lbuf, uint32_t& written, uint32_t* __restrict__ link_node,
                                  float* __restrict__ link_q, uint8_t* __restrict__ link_meta) {
+  const int sx = sb.side[0], sxy = sb.side[0] * sb.side[1];
   for (int c0 = 0; c0 < ncand; c0 += kBlock) {
     const int k = c0 + (int)threadIdx.x;
     uint32_t hits = 0, fluid1 = 0, fluid2 = 0;
     if (k < ncand) {
-      int x, y, z;
-      unpack_xyz(cand[k], x, y, z);
-      uint32_t own[kQ], own1[kQ], own2[kQ];
-      const int n = (int)node_index(x, y, z, d.nx, d.ny);
-      // index offsets of steps -2..2 along each axis, periodic wrap included;
-      // neighbour k c_a of n is n plus one offset per axis
-      const int sy = d.nx, sz = d.nx * d.ny;
-      int ox[5], oy[5], oz[5];
-#pragma unroll
-      for (int t = -2; t <= 2; ++t) {
-        ox[t + 2] = step_offset(x, t, d.nx, 1);
-        oy[t + 2] = step_offset(y, t, d.ny, sy);
-        oz[t + 2] = step_offset(z, t, d.nz, sz);
-      }
-      auto nb = [&](int kk, int a) -> uint32_t {
-        return (uint32_t)(n + ox[kk * cx_of(a) + 2] + oy[kk * cy_of(a) + 2] + oz[kk * cz_of(a) + 2]);
-      };
-      own[0] = owner[n];
-#pragma unroll
-      for (int a = 1; a < kQ; ++a) own[a] = owner[nb(1, a)];
-#pragma unroll
-      for (int a = 1; a < kQ; ++a) own1[a] = owner[nb(-1, a)];
-#pragma unroll
-      for (int a = 1; a < kQ; ++a) own2[a] = owner[nb(-2, a)];
-      if (own[0] == kFluid) {
+      const uint32_t e = cand[k];
+      const int i = (int)(e & 0xFFu) + sx * (int)((e >> 8) & 0xFFu) + sxy * (int)(e >> 16);
+      if (plane_bit(fl, i)) {
 #pragma unroll
         for (int a = 1; a < kQ; ++a) {
-          hits |= (own[a] == p ? 1u : 0u) << a;
-          fluid1 |= (own1[a] == kFluid ? 1u : 0u) << a;
-          fluid2 |= (own2[a] == kFluid ? 1u : 0u) << a;
+          const int o = cx_of(a) + sx * cy_of(a) + sxy * cz_of(a);
+          hits |= plane_bit(op, i + o) << a;
+          fluid1 |= plane_bit(fl, i - o) << a;
+          fluid2 |= plane_bit(fl, i - 2 * o) << a;
         }
       }
     }
@@ -173,10 +179,11 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < total; j += kBlock) {
       const uint32_t e = lbuf[j];
-      const uint32_t xyz = cand[c0 + (int)(e & 0xFFu)];
+      const uint32_t loc = cand[c0 + (int)(e & 0xFFu)];
       const int a = (int)((e >> 8) & 31u);
-      int x, y, z;
-      unpack_xyz(xyz, x, y, z);
+      const int x = wrap1(sb.lo[0] + (int)(loc & 0xFFu), d.nx);
+      const int y = wrap1(sb.lo[1] + (int)((loc >> 8) & 0xFFu), d.ny);
+      const int z = wrap1(sb.lo[2] + (int)(loc >> 16), d.nz);
       const double dx = min_image((double)x - Xp[0], d.nx);
       const double dy = min_image((double)y - Xp[1], d.ny);
       const double dz = min_image((double)z - Xp[2], d.nz);
@@ -184,7 +191,7 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
       const uint32_t sch = pick_scheme(q, (e >> 13) & 1u, (e >> 14) & 1u, max_order);
       const uint32_t slot = written + j;
       if (slot < cap) {
-        link_node[base + slot] = xyz;
+        link_node[base + slot] = pack_xyz(x, y, z);
         link_q[base + slot] = (float)q;
         link_meta[base + slot] = (uint8_t)(a | (sch << 5));
       }
@@ -194,57 +201,84 @@ __device__ void flush_candidates(const uint32_t* __restrict__ owner, const doubl
   }
 }
 
+// One workgroup per sphere. The owner map over the sphere's box plus two
+// nodes (every entry a candidate's 55 tests read) is staged in LDS as two
+// bit planes, built from coalesced row reads with wavefront ballots. The
+// candidates are then listed row by row from the shell intervals, a round of
+// rows at a time, and their links written in that order (deterministic).
 __global__ void __launch_bounds__(kBlock)
 k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, const double* __restrict__ rad, Dims d,
               int max_order, uint32_t cap, uint32_t* __restrict__ link_node, float* __restrict__ link_q,
               uint8_t* __restrict__ link_meta, uint32_t* __restrict__ link_count, uint32_t* __restrict__ err) {
+  extern __shared__ uint32_t planes[];  // fluid bits, then owned-by-p bits, of the staged box
   __shared__ uint32_t cand[kCand];
   __shared__ uint16_t lbuf[kBlock * (kQ - 1)];  // a chunk's links, at most every direction of every candidate
   const uint32_t p = blockIdx.x;
   const double r = rad[p];
   const double* Xp = X + 3 * p;
-  const Box b = make_box(Xp, r + 2.0);
-  const BoxLin L = box_lin(b);
   const size_t base = (size_t)p * cap;
   // The outer bound only prunes, so it carries a margin.
   const double r_out = r + 1.4142135623730951 + 1e-6;
   const double r2 = r * r, ro2 = r_out * r_out;
-  uint32_t written = 0;
-  int ncand = 0;
-  // kPer nodes per thread per iteration
-  constexpr int kPer = 4;
-  for (uint32_t i0 = 0; i0 < L.count; i0 += kPer * kBlock) {
-    uint32_t packed[kPer];
-    uint32_t mask = 0;
+  const Box cb = make_box(Xp, r_out);  // every candidate, unwrapped coordinates
+  Box sb;                               // staged: two more nodes on each side
+  for (int k = 0; k < 3; ++k) {
+    sb.lo[k] = cb.lo[k] - 2;
+    sb.side[k] = cb.side[k] + 4;
+  }
+  const BoxLin SL = box_lin(sb);
+  uint32_t* fl = planes;
+  uint32_t* op = planes + (SL.count + 63u) / 64u * 2u;
+  constexpr int kU = 8;  // owner reads in flight per thread
+  for (uint32_t i0 = 0; i0 < SL.count; i0 += kU * kBlock) {
+    uint32_t o[kU];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      int x = 0, y = 0, z = 0;
-      packed[k] = 0;
-      const uint32_t i = i0 + (uint32_t)(k * kBlock) + threadIdx.x;
-      if (i < L.count) {
-        box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-        const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
-                                min_image((double)z - Xp[2], d.nz));
-        if (d2 >= r2 && d2 < ro2) {
-          mask |= 1u << k;
-          packed[k] = pack_xyz(x, y, z);
-        }
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t i = i0 + (uint32_t)(u * kBlock) + threadIdx.x;
+      o[u] = kFluid;
+      if (i < SL.count) {
+        int x, y, z;
+        box_lin_node(sb, SL, i, d.nx, d.ny, d.nz, x, y, z);
+        o[u] = owner[node_index(x, y, z, d.nx, d.ny)];
       }
     }
-    uint32_t total;
-    uint32_t off = block_exclusive_scan<kBlock>(__popc(mask), &total);
-    if (ncand + (int)total > kCand) {  // uniform: total is block-wide
-      flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, lbuf, written, link_node, link_q, link_meta);
-      __syncthreads();
-      ncand = 0;
-    }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if ((mask >> k) & 1u) cand[ncand + off++] = packed[k];
-    ncand += (int)total;
-    __syncthreads();
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t i = i0 + (uint32_t)(u * kBlock) + threadIdx.x;
+      const uint64_t bf = __ballot(i < SL.count && o[u] == kFluid);
+      const uint64_t bp = __ballot(i < SL.count && o[u] == p);
+      if ((threadIdx.x & 63u) == 0 && i < SL.count) {  // i is a multiple of 64 here
+        fl[i >> 5] = (uint32_t)bf;
+        fl[(i >> 5) + 1] = (uint32_t)(bf >> 32);
+        op[i >> 5] = (uint32_t)bp;
+        op[(i >> 5) + 1] = (uint32_t)(bp >> 32);
+      }
+    }
   }
-  flush_candidates(owner, Xp, r, d, max_order, p, cap, base, cand, ncand, lbuf, written, link_node, link_q, link_meta);
+  __syncthreads();
+  const int rows = cb.side[1] * cb.side[2];
+  const int R = min(kBlock, kCand / cb.side[0]);  // rows per round: a round's candidates fit in cand
+  const int xlo = cb.lo[0], xhi = cb.lo[0] + cb.side[0] - 1;
+  uint32_t written = 0;
+  for (int r0 = 0; r0 < rows; r0 += R) {
+    const int row = r0 + (int)threadIdx.x;
+    int a0 = 1, a1 = 0, b0 = 1, b1 = 0, ly = 0, lz = 0;
+    if ((int)threadIdx.x < R && row < rows) {
+      ly = row % cb.side[1];
+      lz = row / cb.side[1];
+      const double dy = (double)(cb.lo[1] + ly) - Xp[1], dz = (double)(cb.lo[2] + lz) - Xp[2];
+      shell_row(Xp[0], dy * dy + dz * dz, r2, ro2, xlo, xhi, a0, a1, b0, b1);
+    }
+    const int na = a1 >= a0 ? a1 - a0 + 1 : 0, nb = b1 >= b0 ? b1 - b0 + 1 : 0;
+    uint32_t total;
+    uint32_t off = block_exclusive_scan<kBlock>((uint32_t)(na + nb), &total);
+    const uint32_t yz = ((uint32_t)(ly + 2) << 8) | ((uint32_t)(lz + 2) << 16);
+    for (int x = a0; x <= a1; ++x) cand[off++] = (uint32_t)(x - sb.lo[0]) | yz;
+    for (int x = b0; x <= b1; ++x) cand[off++] = (uint32_t)(x - sb.lo[0]) | yz;
+    __syncthreads();
+    flush_candidates(fl, op, sb, Xp, r, d, max_order, cap, base, cand, (int)total, lbuf, written, link_node, link_q,
+                     link_meta);
+  }
   if (threadIdx.x == 0) {
     if (written > cap) {
       atomicOr(err, kErrCapacity);
@@ -312,9 +346,23 @@ hipError_t launch_count_solid(const Ctx& c, const uint32_t* owner, unsigned long
   return hipGetLastError();
 }
 
+// Bit planes of the staged owner box: the candidate box of a sphere of the
+// largest radius (at most floor(2 r_out) + 3 nodes a side) plus two nodes on
+// each side.
+size_t links_build_lds_bytes(double max_radius) {
+  const size_t side = (size_t)std::floor(2.0 * (max_radius + 1.4142135623730951 + 1e-6)) + 7;
+  return 2 * ((side * side * side + 63) / 64 * 2) * sizeof(uint32_t);
+}
+
+// Dynamic plus static LDS of one link-build workgroup.
+size_t links_build_lds_total(double max_radius) {
+  return links_build_lds_bytes(max_radius) + kCand * sizeof(uint32_t) + kBlock * (kQ - 1) * sizeof(uint16_t) + 64;
+}
+
 hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double* X) {
   if (c.np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_links_build, dim3(c.np), dim3(kBlock), 0, c.stream, owner, X, c.P.r, c.dims,
+  hipLaunchKernelGGL(k_links_build, dim3(c.np), dim3(kBlock), links_build_lds_bytes(c.cfg.max_radius), c.stream,
+                     owner, X, c.P.r, c.dims,
                      c.cfg.ibb_max_order, c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta,
                      c.ibb.link_count, c.err);
   return hipGetLastError();

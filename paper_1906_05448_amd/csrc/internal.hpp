@@ -268,6 +268,8 @@ hipError_t launch_owner_fill(const Ctx& c, uint32_t* owner);
 hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold, int32_t np_old);
 hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X);
 hipError_t launch_count_solid(const Ctx& c, const uint32_t* owner, unsigned long long* out);
+size_t links_build_lds_bytes(double max_radius);  // dynamic LDS of the link build
+size_t links_build_lds_total(double max_radius);  // its dynamic plus static LDS
 hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double* X);
 hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only);
 

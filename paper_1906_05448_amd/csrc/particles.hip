@@ -175,6 +175,12 @@ k_particle_update(int np, int motion, int bc, Dims d, int3 cn, const uint32_t* _
       x1 = X[3 * i + k] + 0.5 * (U[3 * i + k] + u1);
       if (x1 >= L[k]) x1 -= L[k];
       if (x1 < 0.0) x1 += L[k];
+      // a position more than one period out (or not finite) comes only from a
+      // diverged flow: latch it and keep the geometry kernels in the lattice
+      if (!(x1 >= 0.0 && x1 < L[k])) {
+        atomicOr(err, kErrUnstable);
+        x1 = 0.0;
+      }
     }
     Xn[3 * i + k] = x1;
     Un[3 * i + k] = u1;
