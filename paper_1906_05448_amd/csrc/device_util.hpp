@@ -116,6 +116,49 @@ __device__ __forceinline__ void box_lin_node(const Box& b, const BoxLin& L, uint
   z = wrap1(b.lo[2] + (int)iz, nz);
 }
 
+// One row of a sphere: a row of nodes along x whose (y, z) lies at squared
+// distance e2 from the centre X across the row, for a sphere of squared
+// radius r2 with centre X0 along x. Nodes in [plo, phi] may be inside (none
+// outside it is); nodes strictly between clo and chi certainly are. The
+// margins (1e-6 (r2 + 1) on r2 - e2, 1e-9 on the roots) exceed any rounding
+// of the exact FP64 test d2 < r2 of a node, so that test agrees wherever
+// these bounds decide. `any` is false when no node of the row can be inside.
+struct RowSpan {
+  double plo, phi, clo, chi;
+  bool any;
+};
+
+__device__ __forceinline__ RowSpan sphere_row(double X0, double e2, double r2) {
+  RowSpan s;
+  const double m = 1e-6 * (r2 + 1.0);
+  s.any = r2 - e2 + m > 0.0;
+  const double w = s.any ? sqrt(r2 - e2 + m) + 1e-9 : 0.0;
+  s.plo = X0 - w;
+  s.phi = X0 + w;
+  const double v = r2 - e2 - m > 0.0 ? sqrt(r2 - e2 - m) - 1e-9 : 0.0;
+  s.clo = X0 - v;
+  s.chi = X0 + v;
+  return s;
+}
+
+// Integers of [ceil(o_lo), floor(o_hi)] within [lo, hi], except those
+// strictly between h_lo and h_hi, as up to two disjoint intervals [a0, a1],
+// [b0, b1]; an empty interval has its end below its start.
+__device__ __forceinline__ void row_band(double o_lo, double o_hi, double h_lo, double h_hi, int lo, int hi, int& a0,
+                                         int& a1, int& b0, int& b1) {
+  a0 = max((int)ceil(o_lo), lo);
+  a1 = min((int)floor(o_hi), hi);
+  b0 = 1;
+  b1 = 0;
+  if (a1 < a0) return;
+  const int left_hi = (int)floor(h_lo), right_lo = (int)ceil(h_hi);
+  if (left_hi + 1 > right_lo - 1) return;  // no integer strictly inside the hole
+  const int o1 = a1;
+  a1 = min(left_hi, o1);
+  b0 = max(right_lo, max(a0, a1 + 1));
+  b1 = o1;
+}
+
 // Link nodes are stored as packed coordinates x | y << 11 | z << 22.
 __device__ __forceinline__ uint32_t pack_xyz(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);

@@ -20,7 +20,8 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kCand = 2048;  // shell candidates buffered in LDS per flush
+constexpr int kCand = 2048;     // shell candidates buffered in LDS per flush
+constexpr int kRowList = 4096;  // nodes listed per round of rows in the owner passes
 
 __device__ __forceinline__ bool inside_sphere(int x, int y, int z, const double* X, double r, double Lx, double Ly,
                                               double Lz) {
@@ -37,37 +38,65 @@ __global__ void __launch_bounds__(256) k_owner_fill(uint32_t* __restrict__ owner
   owner[n] = ((wall[n >> 5] >> (n & 31u)) & 1u) ? kWall : kFluid;
 }
 
+// Calls f(n) for every node n inside the sphere (Xp, r) by the exact test.
+// A round of rows of the sphere's box lists the nodes that may be inside in
+// LDS (two square roots per row), flagging those certainly inside; the
+// others take the exact test. Every thread of the block must call it.
+template <class F>
+__device__ void for_sphere_nodes(const double* Xp, double r, const Dims& d, uint32_t* list, F&& f) {
+  const Box b = make_box(Xp, r + 1.0);
+  const double r2 = r * r;
+  const int rows = b.side[1] * b.side[2];
+  const int R = min(kBlock, kRowList / b.side[0]);  // a round's nodes fit in the list
+  const int xlo = b.lo[0], xhi = b.lo[0] + b.side[0] - 1;
+  for (int r0 = 0; r0 < rows; r0 += R) {
+    const int row = r0 + (int)threadIdx.x;
+    int a0 = 1, a1 = 0, ly = 0, lz = 0;
+    RowSpan sp{};
+    if ((int)threadIdx.x < R && row < rows) {
+      ly = row % b.side[1];
+      lz = row / b.side[1];
+      const double dy = (double)(b.lo[1] + ly) - Xp[1], dz = (double)(b.lo[2] + lz) - Xp[2];
+      sp = sphere_row(Xp[0], dy * dy + dz * dz, r2);
+      if (sp.any) {
+        a0 = max((int)ceil(sp.plo), xlo);
+        a1 = min((int)floor(sp.phi), xhi);
+      }
+    }
+    uint32_t total;
+    uint32_t off = block_exclusive_scan<kBlock>(a1 >= a0 ? (uint32_t)(a1 - a0 + 1) : 0u, &total);
+    // entry: x, y, z offsets in the box (10 bits each), certainly inside (bit 31)
+    for (int x = a0; x <= a1; ++x)
+      list[off++] = (uint32_t)(x - xlo) | ((uint32_t)ly << 10) | ((uint32_t)lz << 20) |
+                    (((double)x > sp.clo && (double)x < sp.chi) ? 0x80000000u : 0u);
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < total; j += kBlock) {
+      const uint32_t e = list[j];
+      const int x = wrap1(xlo + (int)(e & 1023u), d.nx);
+      const int y = wrap1(b.lo[1] + (int)((e >> 10) & 1023u), d.ny);
+      const int z = wrap1(b.lo[2] + (int)((e >> 20) & 1023u), d.nz);
+      if ((e >> 31) || inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) f(node_index(x, y, z, d.nx, d.ny));
+    }
+    __syncthreads();  // the list is refilled by the next round
+  }
+}
+
 // Resets the nodes inside every particle at its old position to fluid (every
 // entry a set pass wrote lies inside some sphere at the positions it used).
 __global__ void __launch_bounds__(kBlock) k_owner_clear(uint32_t* __restrict__ owner, const double* __restrict__ Xold,
                                                         const double* __restrict__ rad, Dims d) {
+  __shared__ uint32_t list[kRowList];
   const int p = blockIdx.x;
-  const double r = rad[p];
-  const double* Xp = Xold + 3 * p;
-  const Box b = make_box(Xp, r + 1.0);
-  const BoxLin L = box_lin(b);
-  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
-    int x, y, z;
-    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-    if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
-    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
+  for_sphere_nodes(Xold + 3 * p, rad[p], d, list, [&](uint32_t n) {
     if (owner[n] != kWall) owner[n] = kFluid;
-  }
+  });
 }
 
 __global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ owner, const double* __restrict__ X,
                                                       const double* __restrict__ rad, Dims d) {
-  const int p = blockIdx.x;
-  const double r = rad[p];
-  const double* Xp = X + 3 * p;
-  const Box b = make_box(Xp, r + 1.0);
-  const BoxLin L = box_lin(b);
-  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
-    int x, y, z;
-    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-    if (!inside_sphere(x, y, z, Xp, r, d.nx, d.ny, d.nz)) continue;
-    atomicMin(owner + node_index(x, y, z, d.nx, d.ny), (uint32_t)p);
-  }
+  __shared__ uint32_t list[kRowList];
+  const uint32_t p = blockIdx.x;
+  for_sphere_nodes(X + 3 * p, rad[p], d, list, [&](uint32_t n) { atomicMin(owner + n, p); });
 }
 
 // Nodes not owned by the fluid (spheres and wall), for reporting.

@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kLinkBlock = 1024;  // one workgroup per sphere in the link kernel
+constexpr int kRefillList = 4096; // nodes listed per round of rows in the refill
 
 template <int STORE>
 __device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint32_t N, uint32_t n) {
@@ -287,11 +288,11 @@ __device__ void refill_node(typename Pop<STORE>::T* B, const Dims& d, const uint
 // One workgroup per sphere: refill the nodes it uncovered and collect the
 // momentum of the nodes it covered, both into F_rc/T_rc for the next step.
 template <int STORE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 4)
 k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o_old,
                const uint32_t* __restrict__ o_new, const double* __restrict__ Xold, const double* __restrict__ Xnew,
                const double* __restrict__ Unew, const double* __restrict__ Omnew, const double* __restrict__ rad,
-               double* __restrict__ F_rc, double* __restrict__ T_rc) {
+               double* __restrict__ F_rc, double* __restrict__ T_rc, uint32_t* __restrict__ err) {
   const uint32_t p = blockIdx.x;
   const double r = rad[p];
   const double* Xn = Xnew + 3 * p;
@@ -300,9 +301,8 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   const double* Xo = Xold + 3 * p;
   // A node p uncovers lies inside p's old sphere and outside its new one; a
-  // node p covers lies inside the new sphere and outside the old one. The
-  // exact FP64 tests (the same ones that built the owner maps) prune the box
-  // before the owner maps are read.
+  // node p covers lies inside the new sphere and outside the old one, by the
+  // exact FP64 tests that built the owner maps.
   auto inside = [&](int x, int y, int z, const double* C) {
     const double dx = min_image((double)x - C[0], d.nx), dy = min_image((double)y - C[1], d.ny),
                  dz = min_image((double)z - C[2], d.nz);
@@ -312,10 +312,10 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   // inside the old sphere only, covered nodes inside the new one only. The
   // new box is placed at the old centre plus the minimum-image displacement,
   // so a sphere that crossed a periodic face still has a compact union.
+  const double Xn_near[3] = {Xo[0] + min_image(Xn[0] - Xo[0], d.nx), Xo[1] + min_image(Xn[1] - Xo[1], d.ny),
+                             Xo[2] + min_image(Xn[2] - Xo[2], d.nz)};
   Box b = make_box(Xo, r + 1.0);
   {
-    const double Xn_near[3] = {Xo[0] + min_image(Xn[0] - Xo[0], d.nx), Xo[1] + min_image(Xn[1] - Xo[1], d.ny),
-                               Xo[2] + min_image(Xn[2] - Xo[2], d.nz)};
     const Box bn = make_box(Xn_near, r + 1.0);
     for (int k = 0; k < 3; ++k) {
       const int lo = min(b.lo[k], bn.lo[k]);
@@ -324,30 +324,25 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       b.side[k] = hi - lo;
     }
   }
-  // A node can change side only within the displacement of the surface:
-  // an FP32 distance band (margin 0.01, far above FP32 error at lattice
-  // coordinates below 2048) skips the rest before the exact FP64 tests.
-  const double mv = sqrt(dist2(min_image(Xn[0] - Xo[0], d.nx), min_image(Xn[1] - Xo[1], d.ny),
-                               min_image(Xn[2] - Xo[2], d.nz)));
-  const float band = (float)mv + 0.01f, rf = (float)r;
-  const float Xf[3] = {(float)Xn[0], (float)Xn[1], (float)Xn[2]};
-  auto min_image_f = [](float v, float L) { return v > 0.5f * L ? v - L : (v < -0.5f * L ? v + L : v); };
-  // The scan only finds the nodes that changed side (arithmetic, no memory
-  // traffic) and appends them to its wavefront's LDS list in lane order; the
-  // list is processed one node per lane when it would overflow and at the
-  // end, so the owner and population loads of a node's refill are paid once
-  // per list rather than once per scan iteration that finds a node. Refills
-  // read only nodes that are fluid in both maps, never another refilled
-  // node, so the processing order does not matter.
-  __shared__ uint32_t cand_all[kBlock];
-  uint32_t* cand = cand_all + (threadIdx.x & ~63u);
+  // box offsets are packed in 10 bits; a sphere that moved that far in one
+  // step comes only from a diverged flow
+  if (b.side[0] > 1023 || b.side[1] > 1023 || b.side[2] > 1023) {
+    if (threadIdx.x == 0) atomicOr(err, kErrUnstable);
+    return;
+  }
+  // A node that changed side: uncovered (inside the old sphere) is refilled
+  // and its new momentum leaves the sphere; covered (inside the new sphere)
+  // hands its momentum to the sphere.
+  __shared__ uint32_t changed_all[kBlock];
+  uint32_t* changed = changed_all + (threadIdx.x & ~63u);
   const uint32_t lane = threadIdx.x & 63u;
-  uint32_t ncand = 0;
+  uint32_t nchanged = 0;
+  // Processes the first `count` entries of the wavefront's list, one per lane.
   auto process = [&](uint32_t count) {
     __builtin_amdgcn_wave_barrier();  // the list entries other lanes wrote
     if (lane >= count) return;
     int x, y, z;
-    unpack_xyz(cand[lane], x, y, z);
+    unpack_xyz(changed[lane], x, y, z);
     const bool in_old = inside(x, y, z, Xo);
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     const double dd[3] = {min_image((double)x - Xn[0], d.nx), min_image((double)y - Xn[1], d.ny),
@@ -379,33 +374,69 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       T[2] += dd[0] * mom[1] - dd[1] * mom[0];
     }
   };
-  const BoxLin L = box_lin(b);
-  // every lane of the block runs the same number of iterations, so the
-  // wavefront-wide ballots below see all 64 lanes
-  for (uint32_t i0 = 0; i0 < L.count; i0 += kBlock) {
-    const uint32_t i = i0 + threadIdx.x;
-    bool hit = false;
-    uint32_t packed = 0;
-    if (i < L.count) {
-      int x, y, z;
-      box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-      const float fx = min_image_f((float)x - Xf[0], (float)d.nx), fy = min_image_f((float)y - Xf[1], (float)d.ny),
-                  fz = min_image_f((float)z - Xf[2], (float)d.nz);
-      if (!(fabsf(sqrtf(fx * fx + fy * fy + fz * fz) - rf) > band)) {
+  // Each row of the union box lists only the nodes that may have changed
+  // side: those possibly inside one sphere and not certainly inside both
+  // (two square roots per sphere and row, margins beyond any rounding of the
+  // exact FP64 test); the exact tests then decide, one node per lane.
+  // Refills read only nodes that are fluid in both maps, never another
+  // refilled node, so the processing order does not matter.
+  __shared__ uint32_t list[kRefillList];
+  const double r2 = r * r;
+  const int rows = b.side[1] * b.side[2];
+  const int R = min(kBlock, kRefillList / b.side[0]);
+  const int xlo = b.lo[0], xhi = b.lo[0] + b.side[0] - 1;
+  for (int r0 = 0; r0 < rows; r0 += R) {
+    const int row = r0 + (int)threadIdx.x;
+    int a0 = 1, a1 = 0, b0 = 1, b1 = 0, ly = 0, lz = 0;
+    if ((int)threadIdx.x < R && row < rows) {
+      ly = row % b.side[1];
+      lz = row / b.side[1];
+      const double y = (double)(b.lo[1] + ly), z = (double)(b.lo[2] + lz);
+      const double eo = (y - Xo[1]) * (y - Xo[1]) + (z - Xo[2]) * (z - Xo[2]);
+      const double en = (y - Xn_near[1]) * (y - Xn_near[1]) + (z - Xn_near[2]) * (z - Xn_near[2]);
+      const RowSpan so = sphere_row(Xo[0], eo, r2), sn = sphere_row(Xn_near[0], en, r2);
+      if (so.any || sn.any) {
+        const double olo = so.any ? (sn.any ? fmin(so.plo, sn.plo) : so.plo) : sn.plo;
+        const double ohi = so.any ? (sn.any ? fmax(so.phi, sn.phi) : so.phi) : sn.phi;
+        // certainly inside both: the intersection of the two certain spans
+        const double hlo = fmax(so.clo, sn.clo), hhi = fmin(so.chi, sn.chi);
+        row_band(olo, ohi, hlo, hhi, xlo, xhi, a0, a1, b0, b1);
+      }
+    }
+    const uint32_t na = a1 >= a0 ? (uint32_t)(a1 - a0 + 1) : 0u, nb = b1 >= b0 ? (uint32_t)(b1 - b0 + 1) : 0u;
+    uint32_t total;
+    uint32_t off = block_exclusive_scan<kBlock>(na + nb, &total);
+    const uint32_t yz = ((uint32_t)ly << 10) | ((uint32_t)lz << 20);
+    for (int x = a0; x <= a1; ++x) list[off++] = (uint32_t)(x - xlo) | yz;
+    for (int x = b0; x <= b1; ++x) list[off++] = (uint32_t)(x - xlo) | yz;
+    __syncthreads();
+    // every lane runs the same number of iterations, so the wavefront-wide
+    // ballots see all 64 lanes; the changed nodes go to the wavefront's list,
+    // processed whenever it would overflow and at the end
+    for (uint32_t j0 = 0; j0 < total; j0 += kBlock) {
+      const uint32_t j = j0 + threadIdx.x;
+      bool hit = false;
+      uint32_t packed = 0;
+      if (j < total) {
+        const uint32_t e = list[j];
+        const int x = wrap1(xlo + (int)(e & 1023u), d.nx);
+        const int y = wrap1(b.lo[1] + (int)((e >> 10) & 1023u), d.ny);
+        const int z = wrap1(b.lo[2] + (int)((e >> 20) & 1023u), d.nz);
         hit = inside(x, y, z, Xo) != inside(x, y, z, Xn);
         packed = pack_xyz(x, y, z);
       }
+      const unsigned long long m = __ballot(hit);
+      const uint32_t nhit = (uint32_t)__popcll(m);
+      if (nchanged + nhit > 64u) {  // uniform across the wavefront
+        process(nchanged);
+        nchanged = 0;
+      }
+      if (hit) changed[nchanged + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = packed;
+      nchanged += nhit;
     }
-    const unsigned long long m = __ballot(hit);
-    const uint32_t nhit = (uint32_t)__popcll(m);
-    if (ncand + nhit > 64u) {  // uniform across the wavefront
-      process(ncand);
-      ncand = 0;
-    }
-    if (hit) cand[ncand + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = packed;
-    ncand += nhit;
+    __syncthreads();  // the list is refilled by the next round
   }
-  process(ncand);
+  process(nchanged);
   for (int k = 0; k < 3; ++k) {
     const double fs = block_sum<kBlock>(F[k]);
     const double ts = block_sum<kBlock>(T[k]);
@@ -447,10 +478,10 @@ hipError_t launch_cover_refill(const Ctx& c, void* B, const uint32_t* owner_old,
   if (c.np <= 0) return hipSuccess;
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL(k_cover_refill<0>, dim3(c.np), dim3(kBlock), 0, c.stream, (float*)B, c.dims, owner_old,
-                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc);
+                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc, c.err);
   else
     hipLaunchKernelGGL(k_cover_refill<1>, dim3(c.np), dim3(kBlock), 0, c.stream, (_Float16*)B, c.dims, owner_old,
-                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc);
+                       owner_new, Xold, Xnew, Unew, Omnew, c.P.r, c.P.F_rc, c.P.T_rc, c.err);
   return hipGetLastError();
 }
 
