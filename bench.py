@@ -61,9 +61,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(variant):
+def recorded_traffic(variant, n, particles):
     """HBM bytes per launch of the fused kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel source and this workload
+    (512^3, 6250 spheres), else None."""
+    if n != 512 or particles != 6250:
+        return None
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
@@ -377,7 +380,7 @@ def main():
                                "f32": "FP32 shifted populations"}[hs]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(head_name),
+                     "traffic": recorded_traffic(head_name, n, args.particles),
                      "kernel": "k_stream_collide_seg" if hs == "f16s" and n % 2 == 0 else "k_stream_collide",
                      "alg_bytes_per_launch": head["alg_bytes"],
                      "avg_launch_ms": round(head["kernel_avg_ms"], 4)},
