@@ -143,6 +143,18 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
     prof = lat.profile_read()
     lat.profile_enable(False)
     lat.sync()
+    # masked energy and dissipation spectra of the final field (every shell),
+    # a statistics call outside the stepping loop
+    spec_ms = None
+    if n & (n - 1) == 0:
+        kmax = int(np.floor(np.sqrt(3.0) * n / 2 + 0.5))
+        lat.spectrum(kmax)
+        t0.record(stream)
+        for _ in range(3):
+            lat.spectrum(kmax)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        spec_ms = t0.elapsed_time(t1) / 3
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -160,7 +172,8 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
     out = dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
                kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes, achieved_gbs=achieved,
                solid_nodes=solid, links=links,
-               kernels_ms_per_step={k: v[0] / steps for k, v in prof.items() if v[1]})
+               kernels_ms_per_step={k: v[0] / steps for k, v in prof.items() if v[1]},
+               spectrum_ms=spec_ms)
     if st is not None:
         out["stats"] = {k: st[k] for k in ("ke_masked", "eps_fluid", "eps_fluid_corrected", "n_corrected",
                                             "particle_ke")}

@@ -220,6 +220,25 @@ typedef struct {
  * zone larger than the lattice, or more interface cells than scratch). */
 int lbm_stats(lbm_ctx* ctx, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist);
 
+#define LBM_SPECTRUM_MAX_SHELL 4096
+
+/* Three-dimensional spectra of the kinetic energy and of its dissipation
+ * rate of the current field (Sec. 4.2, Figs. 11-12). With
+ * u^(k) = (1/N) sum_x u(x) exp(-2 pi i k.x / L), k in integer wavenumbers of
+ * the periodic box (k_max = n/2 along an axis of n nodes),
+ *   E[s] = 1/2 sum over round(|k|) = s of |u^(k)|^2,  D[s] = 2 nu s^2 E[s],
+ * for s = 0 .. kmax, so that the sum of E over all shells is 1/2 <|u|^2>
+ * over the N nodes (Parseval). masked != 0 replaces the velocity inside each
+ * sphere by its rigid-body motion U + Omega x (x - X) and zeroes the pipe
+ * wall, as the masked statistics do; with interpolated bounce-back the
+ * interior holds no fluid, so only the masked spectrum is meaningful there.
+ * E (host, [kmax + 1]) is required, D (host, [kmax + 1]) may be NULL;
+ * shells above kmax are not reported. FP32 transform, FP64 shell sums in a
+ * fixed order (reproducible). Uses the idle population buffer as scratch.
+ * Sync. Errors: LBM_E_ARG (E NULL, kmax outside 0 .. LBM_SPECTRUM_MAX_SHELL,
+ * a lattice side not a power of two or above 1024). */
+int lbm_spectrum(lbm_ctx* ctx, int32_t masked, int32_t kmax, double* E, double* D);
+
 /* ---- Gradient-corrector network ----------------------------------------
  * The paper finds the immersed boundary smears near-surface velocity
  * gradients, so the local dissipation next to particles differs from the

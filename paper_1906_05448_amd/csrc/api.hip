@@ -1158,6 +1158,49 @@ int lbm_corrector_labels(lbm_ctx* h, const int32_t* node_dev, int64_t n, double 
   return drain_errors(c);
 }
 
+int lbm_spectrum(lbm_ctx* h, int32_t masked, int32_t kmax, double* E, double* D) {
+  if (!h || !E || kmax < 0 || kmax > LBM_SPECTRUM_MAX_SHELL) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (!spectrum_supported(c)) return LBM_E_ARG;
+  const size_t N = c.dims.N;
+  const size_t rows = spectrum_lines(c), rowlen = spectrum_row_len(c);
+  // Idle population buffer: [Z1 | Z2], then [u | key]; the per-line shell
+  // partials overwrite u and key once the fields are packed.
+  char* base = (char*)c.f_nxt;
+  float2* Z1 = (float2*)base;
+  float2* Z2 = Z1 + N;
+  char* second = base + align_up(2 * N * sizeof(float2));
+  float* u = (float*)second;
+  uint32_t* key = (uint32_t*)(second + align_up(3 * N * sizeof(float)));
+  double* P = (double*)second;
+  int* smin = (int*)(second + align_up(rows * rowlen * sizeof(double)));
+  int* cnt = (int*)((char*)smin + align_up(rows * sizeof(int)));
+  const size_t need_a = align_up(3 * N * sizeof(float)) + align_up(N * sizeof(uint32_t));
+  const size_t need_b = align_up(rows * rowlen * sizeof(double)) + 2 * align_up(rows * sizeof(int));
+  if (align_up(2 * N * sizeof(float2)) + std::max(need_a, need_b) > pop_bytes(c.cfg)) return LBM_E_SIZE;
+  // E, D and the per-shell partials on the device in the statistics partials
+  double* Ed = c.stats_part;
+  double* Dd = Ed + (kmax + 1);
+  double* part = Dd + (kmax + 1);
+  int st = lbm_get_fields_device(h, u, nullptr);
+  if (st != LBM_OK) return st;
+  const int pc = c.pcur;
+  hipError_t e = timed(c, LBM_K_STATS, [&] {
+    hipError_t r = masked ? launch_stats_keys(c, key, 0, 1.0, c.P.X[pc]) : hipSuccess;
+    if (r == hipSuccess) r = launch_spec_pack(c, u, key, masked, Z1, Z2);
+    if (r == hipSuccess) r = launch_fft_xy(c, Z1);
+    if (r == hipSuccess) r = launch_fft_xy(c, Z2);
+    if (r == hipSuccess)
+      r = launch_spec_zbins(c, Z1, Z2, P, smin, cnt, kmax, (c.cfg.tau - 0.5) / 3.0, part, Ed, Dd);
+    return r;
+  });
+  if (e != hipSuccess) return LBM_E_HIP;
+  const size_t bytes = (size_t)(kmax + 1) * sizeof(double);
+  if (hipMemcpyAsync(E, Ed, bytes, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+  if (D && hipMemcpyAsync(D, Dd, bytes, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
+  return drain_errors(c);
+}
+
 int lbm_sync(lbm_ctx* h) {
   if (!h) return LBM_E_ARG;
   return drain_errors(h->c);

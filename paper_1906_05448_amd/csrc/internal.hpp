@@ -349,6 +349,14 @@ hipError_t launch_corrector_stats(const Ctx& c, const float* theta, const float*
                                   double* part, double* out);
 // Node keys only (see stats_device.hpp).
 hipError_t launch_stats_keys(const Ctx& c, uint32_t* key, int nbins, double width, const double* X);
+// Energy and dissipation spectra (spectrum.hip).
+bool spectrum_supported(const Ctx& c);
+size_t spectrum_row_len(const Ctx& c);  // partials per (x, y) line
+size_t spectrum_lines(const Ctx& c);
+hipError_t launch_spec_pack(const Ctx& c, const float* u, const uint32_t* key, int masked, float2* Z1, float2* Z2);
+hipError_t launch_fft_xy(const Ctx& c, float2* Z);
+hipError_t launch_spec_zbins(const Ctx& c, const float2* Z1, const float2* Z2, double* P, int* smin, int* cnt,
+                             int kmax, double nu, double* part, double* E, double* D);
 hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t* key, int nbins, double width,
                         const double* X, const double* U, const double* Om, double* part, double* out);
 

@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
         "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
+        "lbm_spectrum": (ctypes.c_int, [P, I32, I32, P, P]),
         "lbm_corrector_cells": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P,
                                                 ctypes.POINTER(I64)]),
         "lbm_corrector_labels": (ctypes.c_int, [P, P, I64, ctypes.c_double, I32, P]),
@@ -300,6 +301,15 @@ class Lattice:
         d["momentum"] = np.array(list(out.momentum))
         d["hist"] = hist
         return d
+
+    def spectrum(self, kmax: int, masked: bool = True):
+        """(k, E, D) for shells k = 0 .. kmax of the current field
+        (lbm_spectrum): energy spectrum and dissipation spectrum 2 nu k^2 E."""
+        E = np.zeros(int(kmax) + 1, np.float64)
+        D = np.zeros(int(kmax) + 1, np.float64)
+        _check(lib().lbm_spectrum(self._h, 1 if masked else 0, int(kmax), _host_ptr(E), _host_ptr(D)),
+               "lbm_spectrum")
+        return np.arange(int(kmax) + 1, dtype=np.float64), E, D
 
     # -- gradient corrector ---------------------------------------------
     def corrector_cells(self, u_rms, d_min=0.0, d_max=10.0, cap=None, features=True):
