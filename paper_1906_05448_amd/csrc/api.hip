@@ -192,7 +192,8 @@ struct Plan {
   size_t cell_head, cell_next;
   int cells[3];
   size_t owner[2], solid_bits, wall_bits;
-  size_t link_node, link_q, link_meta, link_count;
+  size_t link_node, link_q, link_meta, link_count, link_part;
+  uint32_t link_slices;
   size_t wl_node, wl_q, wl_meta;
   uint32_t link_cap, wl_count;
   // immersed boundary
@@ -254,6 +255,8 @@ Plan plan(const lbm_config& c) {
     p.link_q = take(L * 4 + 4);
     p.link_meta = take(L + 4);
     p.link_count = take(P * 4 + 4);
+    p.link_slices = std::max<uint32_t>((p.link_cap + kLinkSlice - 1) / kLinkSlice, 1);
+    p.link_part = take(P * p.link_slices * 6 * sizeof(double) + 8);
     p.wl_count = wall_link_count(c);
     p.wl_node = take((size_t)p.wl_count * 4 + 4);
     p.wl_q = take((size_t)p.wl_count * 4 + 4);
@@ -555,6 +558,8 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.ibb.link_q = (float*)(base + p.link_q);
     c.ibb.link_meta = (uint8_t*)(base + p.link_meta);
     c.ibb.link_count = (uint32_t*)(base + p.link_count);
+    c.ibb.link_part = (double*)(base + p.link_part);
+    c.ibb.link_slices = p.link_slices;
     c.ibb.wl_node = (uint32_t*)(base + p.wl_node);
     c.ibb.wl_q = (float*)(base + p.wl_q);
     c.ibb.wl_meta = (uint8_t*)(base + p.wl_meta);

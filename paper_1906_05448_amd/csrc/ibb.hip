@@ -26,7 +26,7 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kLinkBlock = 1024;  // one workgroup per sphere in the link kernel
+constexpr int kLinkBlock = kLinkSliceThreads;  // a slice of a sphere's links per workgroup
 constexpr int kRefillList = 4096; // nodes listed per round of rows in the refill
 
 template <int STORE>
@@ -74,28 +74,30 @@ __device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, u
   return bounce_from(ga0, v1, v2, scheme, q, delta);
 }
 
-// One workgroup per sphere: fill the ghost slots of its links and reduce the
-// link forces and torques in FP64 in a fixed order.
+// One workgroup per slice of kLinkSlice links of a sphere (slices of one
+// sphere run side by side on different CUs): fill the ghost slots of its
+// links and reduce the slice's link forces and torques in FP64 in a fixed
+// order into part[p][g][6]; k_link_sum adds the slices in order.
 template <int STORE>
 __global__ void __launch_bounds__(kLinkBlock)
 k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, const double* __restrict__ U,
-            const double* __restrict__ Om, uint32_t cap, const uint32_t* __restrict__ link_node,
+            const double* __restrict__ Om, uint32_t cap, uint32_t slices, const uint32_t* __restrict__ link_node,
             const float* __restrict__ link_q, const uint8_t* __restrict__ link_meta,
-            const uint32_t* __restrict__ link_count, double* __restrict__ F_out, double* __restrict__ T_out) {
-  const int p = blockIdx.x;
-  const uint32_t cnt = link_count[p];
+            const uint32_t* __restrict__ link_count, double* __restrict__ part) {
+  const int p = (int)(blockIdx.x / slices);
+  const uint32_t g = blockIdx.x % slices;
+  const uint32_t cnt = min(link_count[p], (g + 1u) * kLinkSlice);
   const size_t base = (size_t)p * cap;
   const double Xp[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
   const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
   const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  // kLinks links per thread per round: the records of a round, then all the
-  // population values its links read, are in flight together, so a sphere's
-  // links (about 4600 at r = 8) go out in one round and the cache lines
-  // they share are fetched once. The ghost slots written here are at solid
-  // nodes, which no link reads.
-  constexpr int kLinks = 5;
-  for (uint32_t k0 = 0; k0 < cnt; k0 += kLinks * kLinkBlock) {
+  // kLinks links per thread: the records of the slice, then all the
+  // population values its links read, are in flight together. The ghost
+  // slots written here are at solid nodes, which no link reads.
+  constexpr int kLinks = kLinkSlice / kLinkBlock;
+  static_assert(kLinks * kLinkBlock == kLinkSlice, "a slice is one round");
+  for (uint32_t k0 = g * kLinkSlice; k0 < cnt; k0 += kLinks * kLinkBlock) {
     uint32_t nf[kLinks], meta[kLinks];
     float q[kLinks];
 #pragma unroll
@@ -160,13 +162,29 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
       T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
     }
   }
+  double* out = part + (size_t)blockIdx.x * 6;
   for (int k3 = 0; k3 < 3; ++k3) {
     const double fs = block_sum<kLinkBlock>(F[k3]);
     const double ts = block_sum<kLinkBlock>(T[k3]);
     if (threadIdx.x == 0) {
-      F_out[3 * p + k3] = fs;
-      T_out[3 * p + k3] = ts;
+      out[k3] = fs;
+      out[3 + k3] = ts;
     }
+  }
+}
+
+// F, T of sphere p: its slice partials added in slice order.
+__global__ void __launch_bounds__(64)
+k_link_sum(int np, uint32_t slices, const double* __restrict__ part, double* __restrict__ F_out,
+           double* __restrict__ T_out) {
+  const int p = (int)(blockIdx.x * 64u + threadIdx.x);
+  if (p >= np) return;
+  double f[6] = {0, 0, 0, 0, 0, 0};
+  for (uint32_t g = 0; g < slices; ++g)
+    for (int k = 0; k < 6; ++k) f[k] += part[((size_t)p * slices + g) * 6 + k];
+  for (int k = 0; k < 3; ++k) {
+    F_out[3 * p + k] = f[k];
+    T_out[3 * p + k] = f[3 + k];
   }
 }
 
@@ -462,14 +480,19 @@ hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double
     if (e != hipSuccess) return e;
   }
   if (c.np <= 0) return hipSuccess;
+  const uint32_t slices = c.ibb.link_slices;
+  const dim3 grid((uint32_t)c.np * slices);
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_ibb_links<0>, dim3(c.np), dim3(kLinkBlock), 0, c.stream, (float*)A, c.dims, X, U, Om,
-                       c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
-                       c.P.T_link);
+    hipLaunchKernelGGL(k_ibb_links<0>, grid, dim3(kLinkBlock), 0, c.stream, (float*)A, c.dims, X, U, Om, c.link_cap,
+                       slices, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.ibb.link_part);
   else
-    hipLaunchKernelGGL(k_ibb_links<1>, dim3(c.np), dim3(kLinkBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
-                       c.link_cap, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.P.F_link,
-                       c.P.T_link);
+    hipLaunchKernelGGL(k_ibb_links<1>, grid, dim3(kLinkBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
+                       c.link_cap, slices, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count,
+                       c.ibb.link_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_link_sum, dim3(((uint32_t)c.np + 63u) / 64u), dim3(64), 0, c.stream, c.np, slices,
+                     c.ibb.link_part, c.P.F_link, c.P.T_link);
   return hipGetLastError();
 }
 

@@ -160,6 +160,11 @@ struct ParticleBufs {
   int cells[3];         // contact cell grid
 };
 
+// The link kernel works on slices of a sphere's links, one workgroup of
+// kLinkSliceThreads threads per slice.
+constexpr int kLinkSliceThreads = 256;
+constexpr uint32_t kLinkSlice = 1280;
+
 // Interpolated bounce-back geometry.
 struct IbbBufs {
   uint32_t* owner[2];    // [N] owner codes, [cur] at step n
@@ -169,6 +174,8 @@ struct IbbBufs {
   float* link_q;         // wall fraction q
   uint8_t* link_meta;    // direction | scheme << 5
   uint32_t* link_count;  // [P]
+  double* link_part;     // [P][link_slices][6] FP64 force/torque per slice of links
+  uint32_t link_slices;  // slices of kLinkSlice links per sphere
   uint32_t* wl_node;     // static wall links
   float* wl_q;
   uint8_t* wl_meta;
