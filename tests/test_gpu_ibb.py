@@ -54,6 +54,33 @@ def test_links_bit_exact_overlapping_and_wrapping_spheres():
     g.close()
 
 
+@pytest.mark.parametrize("r, shape, X", [
+    # small spheres: a few links each, rows of one or two candidates
+    (1.6, (24, 20, 22), [[0.4, 10.3, 21.7], [12.2, 9.9, 11.4], [12.9, 13.1, 11.9]]),
+    # large spheres: several rounds of rows and link chunks per sphere, a
+    # sphere wrapping two faces, two overlapping
+    (13.3, (48, 44, 40), [[3.2, 40.7, 3.0], [22.1, 20.3, 19.8], [43.5, 25.0, 23.1]]),
+    # the largest radius the immersed boundary admits, in a box just wide enough
+    (27.9, (64, 64, 64), [[31.7, 2.4, 60.9]]),
+])
+def test_links_bit_exact_small_and_large_spheres(r, shape, X):
+    """Link sets, q and schemes bit-exact against the oracle at radii that
+    take the link build's row spans and LDS planes to their extremes."""
+    X = np.asarray(X, float)
+    rr = np.full(len(X), r)
+    o, g = _pair(shape, max_np=len(X), max_r=r)
+    o.set_particles(X, r=rr)
+    g.set_particles(X, rr)
+    lo, lg = _oracle_links_sorted(o), _gpu_links_sorted(g)
+    assert len(lo) == len(lg) > 0
+    assert [t[:5] for t in lo] == [t[:5] for t in lg]
+    assert [t[6] for t in lo] == [t[6] for t in lg]
+    assert all(a[5] == b[5] for a, b in zip(lo, lg))
+    solid_o = int((o.state.owner >= 0).sum())
+    assert g.geometry_counts()[0] == solid_o
+    g.close()
+
+
 @pytest.mark.parametrize("store", [0, 1])
 def test_fixed_sphere_body_force_500_steps(store):
     """Fixed sphere r = 4.5 at the centre of a 32^3 box driven by g = 1e-6,
