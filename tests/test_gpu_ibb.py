@@ -224,6 +224,41 @@ def test_prescribed_spheres_cross_periodic_faces(store):
     g.close()
 
 
+def test_prescribed_large_sphere_fast_motion():
+    """A large sphere (r = 11.7) moving 0.12 nodes a step with spin across a
+    periodic face, next to a smaller one moving the other way: many nodes
+    change side every step, so the owner passes and the refill lists are
+    exercised at full width; solid counts exact, fields and forces at the
+    FP32 bar."""
+    shape = (40, 36, 34)
+    X = np.array([[38.9, 17.2, 16.1], [20.3, 8.9, 20.4]])
+    U = np.array([[0.12, -0.03, 0.02], [-0.05, 0.08, 0.0]])
+    W = np.array([[0.003, -0.002, 0.004], [0.0, 0.006, -0.002]])
+    r = np.array([11.7, 5.2])
+    o, g = _pair(shape, tau=0.6, store=0, max_np=2, max_r=11.7)
+    spec = synth.hit_spectrum(seed=9, u_rms=0.02, kcut=6)
+    u0 = synth.hit_field(spec, shape)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, U=U, Om=W, r=r, mode=SET_RIGID, motion="prescribed")
+    g.set_particles(X, r, u=U, omega=W, mode=2, motion=MOTION["prescribed"])
+    uncovered = 0
+    for _ in range(4):
+        o.step(5)
+        g.step(5)
+        uncovered += o.state.extra["uncovered"]
+        assert g.geometry_counts()[0] == int((o.state.owner >= 0).sum())
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        assert rel_l2(ug, uo, o.fluid_mask()) < 1e-5, o.state.step
+        Fg, _, _ = g.forces()
+        Fo, _, _ = o.forces()
+        assert rel_l2(Fg, Fo) < 1e-4
+    assert o.state.P.X[0, 0] < 10  # crossed the x face
+    assert uncovered > 200
+    g.close()
+
+
 def _crowded_sphere(centre, R, r, n, overlap):
     """A sphere of radius R touched by n spheres of radius r, centres on a
     Fibonacci lattice at distance R + r - overlap."""
