@@ -98,6 +98,9 @@ def parse():
                         "corrector in the statistics)|none, store in f16s|f32; the first is the headline")
     p.add_argument("--stats-every", type=int, default=100, help="steps between lbm_stats calls (0: none)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--pipe", action="store_true",
+                   help="time the 160x160x480 pipe (R = 74.5, linear bounce-back wall, FP32) and one snapshot of "
+                        "its component TKE budget instead of the headline workload")
     return p.parse_args()
 
 
@@ -328,6 +331,51 @@ def gpu_error_vs_oracle(sim, u0, X, steps):
     return res
 
 
+def run_pipe(torch, lbm, synth, steps, warmup):
+    """The turbulent-pipe workload: steps per second, one TKE-budget snapshot
+    (lbm_pipe_budget_add) and one statistics call, timed with HIP events on
+    the library's stream."""
+    shape, R, c = (160, 160, 480), 74.5, (79.5, 79.5)
+    tau, F = 0.52, 7e-6
+    cfg = lbm.Config(nx=shape[0], ny=shape[1], nz=shape[2], tau=tau, body_force=(0.0, 0.0, F), bc=lbm.BC_IBB,
+                     ibb_max_order=1, wall=lbm.WALL_PIPE_Z, pipe_radius=R, pipe_cx=c[0], pipe_cy=c[1],
+                     store=lbm.STORE_F32)
+    lat = lbm.Lattice(cfg)
+    u0 = synth.pipe_initial_velocity(shape, R, c, 0.05, 0.05, seed=0)
+    lat.set_fields(u0.astype(np.float32))
+    lat.step(warmup)
+    lat.sync()
+    stream = lat.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    lat.pipe_budget_reset(0.5)
+    lat.pipe_budget_add()  # warm
+    t = []
+    for what in ("budget", "stats"):
+        e0.record(stream)
+        for _ in range(3):
+            lat.pipe_budget_add() if what == "budget" else lat.stats(nbins=32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1) / 3)
+    ns, M, T = lat.pipe_budget_read()
+    lat.close()
+    N = shape[0] * shape[1] * shape[2]
+    return {"metric": "pipe step time and TKE-budget snapshot time", "unit": "ms", "n_gpus": 1,
+            "data": "synthetic",
+            "config": {"workload": "160x160x480 pipe, R=74.5 along z, linear interpolated bounce-back wall, "
+                                   "FP32 populations, tau 0.52, body force 7e-6, Poiseuille start + 5% noise",
+                       "budget_bin_width": 0.5, "budget_bins": int(M.shape[1])},
+            "steps": steps, "warmup": warmup, "ms_per_step": round(step_ms, 4),
+            "mlups": round(N / (step_ms * 1e-3) / 1e6, 1), "budget_add_ms": round(t[0], 4),
+            "stats_ms": round(t[1], 4), "budget_snapshots": int(ns)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -340,6 +388,9 @@ def main():
     from paper_1906_05448_amd import lbm
 
     torch.cuda.set_device(0)
+    if args.pipe:
+        print(json.dumps(run_pipe(torch, lbm, synth, args.steps, args.warmup)), flush=True)
+        return
     n = args.n
     bcs = {"ibb": lbm.BC_IBB, "ibm": lbm.BC_IBM, "ibmc": lbm.BC_IBM, "none": lbm.BC_NONE}
     stores = {"f32": lbm.STORE_F32, "f16s": lbm.STORE_F16S}

@@ -220,6 +220,48 @@ typedef struct {
  * zone larger than the lattice, or more interface cells than scratch). */
 int lbm_stats(lbm_ctx* ctx, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist);
 
+#define LBM_PIPE_BUDGET_MOMENTS 38
+#define LBM_PIPE_BUDGET_TERMS 13
+#define LBM_PIPE_BUDGET_MAX_BINS 1024
+
+/* Component-wise budget of the turbulent kinetic energy in the pipe, in
+ * cylindrical coordinates (Sec. 2.2, Eq. (1a)-(1c)), averaged over radial
+ * bins [k w, (k + 1) w) of the fluid nodes (r^2 < R^2) and over the snapshots
+ * added since the last reset. Needs a pipe wall (LBM_WALL_PIPE_Z).
+ *
+ * Per node, from the masked field (as lbm_stats: zero in the wall, rigid
+ * motion inside spheres) and its central-difference gradient
+ * G_ij = d_j u_i, with e_r = (x_perp - c) / r (e_x on the axis) and
+ * e_theta = e_z x e_r: u_r, u_theta, u_z; p = rho / 3; L_ab = e_a . G . e_b
+ * (the physical cylindrical components of the velocity gradient, e.g.
+ * L_r,theta = (1/r) du_r/dtheta - u_theta/r); s_ab = (L_ab + L_ba) / 2.
+ *
+ * lbm_pipe_budget_reset: clears the sums and sets the bin width w > 0
+ * (ceil(R / w) <= LBM_PIPE_BUDGET_MAX_BINS bins). Sync. Errors: LBM_E_STATE
+ * (no pipe wall), LBM_E_ARG (width).
+ * lbm_pipe_budget_add: adds the current snapshot's sums (FP64, fixed order:
+ * reproducible). Uses the idle population buffer as scratch. Sync. Errors:
+ * LBM_E_STATE (not reset), LBM_E_SIZE (scratch too small).
+ * lbm_pipe_budget_read: *nbins, *snapshots; moments (host,
+ * [LBM_PIPE_BUDGET_MOMENTS][nbins], may be NULL): the sums, in the order
+ *   count, u_r, u_t, u_z, p, s_rr, s_rt, s_rz, s_tt, s_tz, s_zz,
+ *   L_zr, L_zt, L_zz, L_rr, L_rt, L_rz, L_tt, L_tr, L_tz,
+ *   u_z u_r, u_r u_r, u_t u_r, u_z u_z, u_t u_t,
+ *   p u_r, p L_zz, p L_rr, p L_tt, u_z s_zr, u_r s_rr, u_t s_tr,
+ *   s_zr L_zr + s_zt L_zt + s_zz L_zz, s_rr L_rr + s_rt L_rt + s_rz L_rz,
+ *   s_tt L_tt + s_tr L_tr + s_tz L_tz, u_z u_z u_r, u_r u_r u_r, u_t u_t u_r
+ * (t = theta); terms (host, [LBM_PIPE_BUDGET_TERMS][nbins], may be NULL):
+ *   E_Oz, E_Tz, E_Pz, E_Vz, E_Dz, E_Tr, E_Pr, E_Vr, E_Dr,
+ *   E_Ttheta, E_Ptheta, E_Vtheta, E_Dtheta
+ * of Eq. (1) from the bin means, with a' = a - <a> (so <a'b'> = <ab> -
+ * <a><b>, <a'a'b'> = <a^2 b> - 2<a><ab> - <b><a^2> + 2<a>^2<b>), d/dr by
+ * central differences over the bin centres (k + 1/2) w (one-sided at the
+ * first and last bin), nu = (tau - 1/2) / 3; empty bins give NaN. Sync.
+ * Errors: LBM_E_STATE (not reset), LBM_E_ARG (nbins or snapshots NULL). */
+int lbm_pipe_budget_reset(lbm_ctx* ctx, double bin_width);
+int lbm_pipe_budget_add(lbm_ctx* ctx);
+int lbm_pipe_budget_read(lbm_ctx* ctx, int32_t* nbins, int64_t* snapshots, double* moments, double* terms);
+
 #define LBM_SPECTRUM_MAX_SHELL 4096
 
 /* Three-dimensional spectra of the kinetic energy and of its dissipation

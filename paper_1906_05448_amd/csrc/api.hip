@@ -192,6 +192,7 @@ struct Plan {
   size_t cell_head, cell_next;
   int cells[3];
   size_t owner[2], solid_bits, wall_bits;
+  size_t pb_acc, pb_list, pb_off;  // pipe TKE budget
   size_t link_node, link_q, link_meta, link_count, link_part;
   uint32_t link_slices;
   size_t wl_node, wl_q, wl_meta;
@@ -243,6 +244,11 @@ Plan plan(const lbm_config& c) {
   p.cell_head = take((size_t)p.cells[0] * p.cells[1] * p.cells[2] * 4);
   p.cell_next = take(std::max<size_t>(P, 1) * 4);
   p.wall_bits = take(words * 4);
+  if (c.wall == LBM_WALL_PIPE_Z) {
+    p.pb_acc = take((size_t)LBM_PIPE_BUDGET_MOMENTS * LBM_PIPE_BUDGET_MAX_BINS * sizeof(double));
+    p.pb_list = take((size_t)c.nx * (size_t)c.ny * 4);
+    p.pb_off = take((LBM_PIPE_BUDGET_MAX_BINS + 1) * 4);
+  }
   p.solid_bits = take(words * 4);
   if (c.bc != LBM_BC_NONE) {
     p.owner[0] = take(N * 4);
@@ -545,6 +551,12 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     B.cell_head = (uint32_t*)(base + p.cell_head);
     B.cell_next = (uint32_t*)(base + p.cell_next);
     for (int a = 0; a < 3; ++a) B.cells[a] = p.cells[a];
+  }
+  c.pb = Ctx::PipeBudget{};
+  if (cfg->wall == LBM_WALL_PIPE_Z) {
+    c.pb.acc = (double*)(base + p.pb_acc);
+    c.pb.list = (uint32_t*)(base + p.pb_list);
+    c.pb.off = (uint32_t*)(base + p.pb_off);
   }
   c.ibb = IbbBufs{};
   c.ibb.wall_bits = (uint32_t*)(base + p.wall_bits);
@@ -1204,6 +1216,129 @@ int lbm_spectrum(lbm_ctx* h, int32_t masked, int32_t kmax, double* E, double* D)
   if (hipMemcpyAsync(E, Ed, bytes, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
   if (D && hipMemcpyAsync(D, Dd, bytes, hipMemcpyDeviceToHost, c.stream) != hipSuccess) return LBM_E_HIP;
   return drain_errors(c);
+}
+
+int lbm_pipe_budget_reset(lbm_ctx* h, double bin_width) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (c.cfg.wall != LBM_WALL_PIPE_Z || !c.pb.acc) return LBM_E_STATE;
+  const double R = c.cfg.pipe_radius;
+  if (!(bin_width > 0.0) || !(std::ceil(R / bin_width) <= (double)LBM_PIPE_BUDGET_MAX_BINS)) return LBM_E_ARG;
+  const int nbins = std::max(1, (int)std::ceil(R / bin_width));
+  // fluid (x, y) of the cross-section by bin; r^2 and the bin exactly as
+  // the device and the wall test evaluate them
+  std::vector<std::vector<uint32_t>> by(nbins);
+  for (int y = 0; y < c.dims.ny; ++y)
+    for (int x = 0; x < c.dims.nx; ++x) {
+      const double dx = (double)x - c.cfg.pipe_cx, dy = (double)y - c.cfg.pipe_cy;
+      const double r2 = dy * dy + dx * dx;
+      if (!(r2 < R * R)) continue;
+      const int k = (int)std::floor(std::sqrt(r2) / bin_width);
+      if (k < nbins) by[k].push_back((uint32_t)x | ((uint32_t)y << 16));
+    }
+  std::vector<uint32_t> list, off(nbins + 1, 0);
+  for (int k = 0; k < nbins; ++k) {
+    off[k] = (uint32_t)list.size();
+    list.insert(list.end(), by[k].begin(), by[k].end());
+  }
+  off[nbins] = (uint32_t)list.size();
+  if (!list.empty() &&
+      hipMemcpyAsync(c.pb.list, list.data(), list.size() * 4, hipMemcpyHostToDevice, c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  if (hipMemcpyAsync(c.pb.off, off.data(), off.size() * 4, hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+      hipMemsetAsync(c.pb.acc, 0, (size_t)LBM_PIPE_BUDGET_MOMENTS * nbins * sizeof(double), c.stream) != hipSuccess ||
+      hipStreamSynchronize(c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  c.pb.nbins = nbins;
+  c.pb.width = bin_width;
+  c.pb.snapshots = 0;
+  return LBM_OK;
+}
+
+int lbm_pipe_budget_add(lbm_ctx* h) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (c.pb.nbins <= 0) return LBM_E_STATE;
+  const size_t N = c.dims.N;
+  const Scratch sc = scratch_layout(c);
+  double* part = (double*)((char*)sc.key + align_up(N * sizeof(uint32_t)));
+  const size_t used = (size_t)((char*)part - (char*)c.f_nxt);
+  if (used + pipe_budget_part_bytes(c, c.pb.nbins) > pop_bytes(c.cfg)) return LBM_E_SIZE;
+  int st = lbm_get_fields_device(h, sc.u, sc.rho);
+  if (st != LBM_OK) return st;
+  const int pc = c.pcur;
+  hipError_t e = timed(c, LBM_K_STATS, [&] {
+    hipError_t r = launch_stats_keys(c, sc.key, 0, 1.0, c.P.X[pc]);
+    if (r == hipSuccess) r = launch_pipe_budget_add(c, sc.u, sc.rho, sc.key, part);
+    return r;
+  });
+  if (e != hipSuccess) return LBM_E_HIP;
+  st = drain_errors(c);
+  if (st == LBM_OK) ++c.pb.snapshots;
+  return st;
+}
+
+int lbm_pipe_budget_read(lbm_ctx* h, int32_t* nbins, int64_t* snapshots, double* moments, double* terms) {
+  if (!h || !nbins || !snapshots) return LBM_E_ARG;
+  Ctx& c = h->c;
+  if (c.pb.nbins <= 0) return LBM_E_STATE;
+  const int K = c.pb.nbins;
+  const int NM = LBM_PIPE_BUDGET_MOMENTS;
+  std::vector<double> M((size_t)NM * K);
+  if (hipMemcpyAsync(M.data(), c.pb.acc, M.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+    return LBM_E_HIP;
+  const int st = drain_errors(c);
+  if (st != LBM_OK) return st;
+  *nbins = K;
+  *snapshots = c.pb.snapshots;
+  if (moments) std::copy(M.begin(), M.end(), moments);
+  if (!terms) return LBM_OK;
+  // bin means of the sums (moment order as documented in lbm.h)
+  enum { kCnt, kUr, kUt, kUz, kP, kSrr, kSrt, kSrz, kStt, kStz, kSzz, kLzr, kLzt, kLzz, kLrr, kLrt, kLrz, kLtt,
+         kLtr, kLtz, kUzUr, kUrUr, kUtUr, kUzUz, kUtUt, kPUr, kPLzz, kPLrr, kPLtt, kUzSzr, kUrSrr, kUtStr, kDz,
+         kDr, kDt, kUzUzUr, kUrUrUr, kUtUtUr };
+  const double w = c.pb.width, nu = (c.cfg.tau - 0.5) / 3.0;
+  auto mean = [&](int m, int k) { return M[(size_t)m * K + k] / M[(size_t)kCnt * K + k]; };
+  auto rk = [&](int k) { return ((double)k + 0.5) * w; };
+  // d f/dr at bin k over the bin centres: central, one-sided at the ends
+  auto ddr = [&](auto f, int k) {
+    if (K == 1) return std::nan("");
+    if (k == 0) return (f(1) - f(0)) / w;
+    if (k == K - 1) return (f(K - 1) - f(K - 2)) / w;
+    return (f(k + 1) - f(k - 1)) / (2.0 * w);
+  };
+  auto cov = [&](int ab, int a, int b, int k) { return mean(ab, k) - mean(a, k) * mean(b, k); };
+  auto trip = [&](int aab, int ab, int aa, int a, int b, int k) {  // <a'a'b'>
+    const double A = mean(a, k), B = mean(b, k);
+    return mean(aab, k) - 2.0 * A * mean(ab, k) - B * mean(aa, k) + 2.0 * A * A * B;
+  };
+  for (int k = 0; k < K; ++k) {
+    auto cyl_div = [&](auto f) { return ddr([&](int j) { return rk(j) * f(j); }, k) / rk(k); };
+    double* T = terms;
+    T[0 * K + k] = -cov(kUzUr, kUz, kUr, k) * ddr([&](int j) { return mean(kUz, j); }, k);
+    T[1 * K + k] = -cyl_div([&](int j) { return 0.5 * trip(kUzUzUr, kUzUr, kUzUz, kUz, kUr, j); });
+    T[2 * K + k] = cov(kPLzz, kP, kLzz, k);
+    T[3 * K + k] = 2.0 * nu * cyl_div([&](int j) { return cov(kUzSzr, kUz, kSrz, j); });
+    T[4 * K + k] = -2.0 * nu *
+                   (mean(kDz, k) - (mean(kSrz, k) * mean(kLzr, k) + mean(kStz, k) * mean(kLzt, k) +
+                                    mean(kSzz, k) * mean(kLzz, k)));
+    T[5 * K + k] = -cyl_div([&](int j) {
+      const double A = mean(kUr, j);
+      return 0.5 * (mean(kUrUrUr, j) - 3.0 * A * mean(kUrUr, j) + 2.0 * A * A * A);
+    });
+    T[6 * K + k] = -ddr([&](int j) { return cov(kPUr, kUr, kP, j); }, k) + cov(kPLrr, kP, kLrr, k);
+    T[7 * K + k] = 2.0 * nu * cyl_div([&](int j) { return cov(kUrSrr, kUr, kSrr, j); });
+    T[8 * K + k] = -2.0 * nu *
+                   (mean(kDr, k) - (mean(kSrr, k) * mean(kLrr, k) + mean(kSrt, k) * mean(kLrt, k) +
+                                    mean(kSrz, k) * mean(kLrz, k)));
+    T[9 * K + k] = -cyl_div([&](int j) { return 0.5 * trip(kUtUtUr, kUtUr, kUtUt, kUt, kUr, j); });
+    T[10 * K + k] = cov(kPLtt, kP, kLtt, k);
+    T[11 * K + k] = 2.0 * nu * cyl_div([&](int j) { return cov(kUtStr, kUt, kSrt, j); });
+    T[12 * K + k] = -2.0 * nu *
+                    (mean(kDt, k) - (mean(kStt, k) * mean(kLtt, k) + mean(kSrt, k) * mean(kLtr, k) +
+                                     mean(kStz, k) * mean(kLtz, k)));
+  }
+  return LBM_OK;
 }
 
 int lbm_sync(lbm_ctx* h) {

@@ -246,6 +246,15 @@ struct Ctx {
   // Gradient corrector attached for the statistics (lbm_corrector_set).
   const float* corr_theta;  // device FP32 network parameters, null: off
   double corr_dmin, corr_dmax, corr_urms;
+  // Pipe TKE budget accumulator (lbm_pipe_budget_*).
+  struct PipeBudget {
+    double* acc;      // [LBM_PIPE_BUDGET_MOMENTS][nbins] moment sums
+    uint32_t* list;   // fluid (x, y) of the cross-section by bin: x | y << 16
+    uint32_t* off;    // [nbins + 1] bin offsets in list
+    int nbins;        // 0 until reset
+    double width;
+    int64_t snapshots;
+  } pb;
 };
 
 // Runs a launcher, bracketed by timing events when profiling is on.
@@ -356,6 +365,9 @@ hipError_t launch_corrector_stats(const Ctx& c, const float* theta, const float*
                                   double* part, double* out);
 // Node keys only (see stats_device.hpp).
 hipError_t launch_stats_keys(const Ctx& c, uint32_t* key, int nbins, double width, const double* X);
+// Pipe TKE budget moments (budget.hip). part: nbins * nz * 38 doubles.
+size_t pipe_budget_part_bytes(const Ctx& c, int nbins);
+hipError_t launch_pipe_budget_add(const Ctx& c, const float* u, const float* rho, const uint32_t* key, double* part);
 // Energy and dissipation spectra (spectrum.hip).
 bool spectrum_supported(const Ctx& c);
 size_t spectrum_row_len(const Ctx& c);  // partials per (x, y) line

@@ -19,6 +19,7 @@ STORE_F32, STORE_F16S = 0, 1
 WALL_NONE, WALL_PIPE_Z = 0, 1
 SET_STATE, RELEASE, SET_RIGID = 0, 1, 2
 MOTION_FREE, MOTION_FIXED, MOTION_PRESCRIBED = 0, 1, 2
+PIPE_BUDGET_MOMENTS, PIPE_BUDGET_TERMS = 38, 13
 KERNEL_CLASSES = ("stream_collide", "geometry", "ibb_links", "refill", "ibm_prepass", "ibm_forcing",
                   "particle", "stats", "corrector")
 NPROF = len(KERNEL_CLASSES)
@@ -92,6 +93,9 @@ def lib() -> ctypes.CDLL:
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
         "lbm_spectrum": (ctypes.c_int, [P, I32, I32, P, P]),
+        "lbm_pipe_budget_reset": (ctypes.c_int, [P, ctypes.c_double]),
+        "lbm_pipe_budget_add": (ctypes.c_int, [P]),
+        "lbm_pipe_budget_read": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), P, P]),
         "lbm_corrector_cells": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P,
                                                 ctypes.POINTER(I64)]),
         "lbm_corrector_labels": (ctypes.c_int, [P, P, I64, ctypes.c_double, I32, P]),
@@ -310,6 +314,24 @@ class Lattice:
         _check(lib().lbm_spectrum(self._h, 1 if masked else 0, int(kmax), _host_ptr(E), _host_ptr(D)),
                "lbm_spectrum")
         return np.arange(int(kmax) + 1, dtype=np.float64), E, D
+
+    def pipe_budget_reset(self, bin_width: float) -> None:
+        _check(lib().lbm_pipe_budget_reset(self._h, float(bin_width)), "lbm_pipe_budget_reset")
+
+    def pipe_budget_add(self) -> None:
+        _check(lib().lbm_pipe_budget_add(self._h), "lbm_pipe_budget_add")
+
+    def pipe_budget_read(self):
+        """(snapshots, moments [38, nbins], terms [13, nbins]) of the pipe's
+        TKE budget accumulator (lbm_pipe_budget_read)."""
+        nb, ns = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().lbm_pipe_budget_read(self._h, ctypes.byref(nb), ctypes.byref(ns), None, None),
+               "lbm_pipe_budget_read")
+        M = np.zeros((PIPE_BUDGET_MOMENTS, nb.value), np.float64)
+        T = np.zeros((PIPE_BUDGET_TERMS, nb.value), np.float64)
+        _check(lib().lbm_pipe_budget_read(self._h, ctypes.byref(nb), ctypes.byref(ns), _host_ptr(M), _host_ptr(T)),
+               "lbm_pipe_budget_read")
+        return ns.value, M, T
 
     # -- gradient corrector ---------------------------------------------
     def corrector_cells(self, u_rms, d_min=0.0, d_max=10.0, cap=None, features=True):
