@@ -8,10 +8,11 @@
 // tensor L_ab = e_a . G . e_b and the strain s_ab = (L_ab + L_ba) / 2, with
 // e_r = (x_perp - c) / r (e_x on the axis), e_theta = e_z x e_r. The 38
 // sums of the products Eq. (1) needs (lbm.h lists them) are taken per
-// radial bin [k w, (k + 1) w): one workgroup per (bin, z plane) walks the
-// bin's (x, y) list, which the host built once, sums in FP64 and reduces in a
-// fixed order; the planes are then added in order into the accumulator. The
-// budget terms follow from the accumulated sums on the host.
+// radial bin [k w, (k + 1) w): one workgroup per (bin, chunk of kPbZ z
+// planes) walks the bin's (x, y) list, which the host built once, over its
+// planes, sums in FP64 and reduces in a fixed order; the chunks are then
+// added in order into the accumulator. The budget terms follow from the
+// accumulated sums on the host.
 #include "device_util.hpp"
 #include "internal.hpp"
 #include "stats_device.hpp"
@@ -21,21 +22,30 @@ namespace lbm {
 namespace {
 
 constexpr int kPbBlock = 256;
+constexpr int kPbZ = 4;  // z planes per workgroup
 constexpr int kPbM = LBM_PIPE_BUDGET_MOMENTS;
+
+int pb_chunks(int nz) { return (nz + kPbZ - 1) / kPbZ; }
 
 __global__ void __launch_bounds__(kPbBlock)
 k_pb_nodes(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key,
            const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om, Dims d,
            double cx, double cy, const uint32_t* __restrict__ list, const uint32_t* __restrict__ off, int nbins,
-           double* __restrict__ part) {
+           int nchunks, double* __restrict__ part) {
   const int k = (int)(blockIdx.x % (uint32_t)nbins);
-  const int z = (int)(blockIdx.x / (uint32_t)nbins);
+  const int ch = (int)(blockIdx.x / (uint32_t)nbins);
+  const int z0 = ch * kPbZ, nzc = min(kPbZ, d.nz - z0);
   const MaskedVel vel{u, key, X, U, Om, d};
   double s[kPbM];
 #pragma unroll
   for (int i = 0; i < kPbM; ++i) s[i] = 0.0;
-  for (uint32_t j = off[k] + threadIdx.x; j < off[k + 1]; j += kPbBlock) {
-    const uint32_t xy = list[j];
+  // thread t takes the (list entry, plane) pairs t, t + kPbBlock, ... of the
+  // chunk, entries fastest
+  const uint32_t cnt = off[k + 1] - off[k], total = cnt * (uint32_t)nzc;
+  for (uint32_t t = threadIdx.x; t < total; t += kPbBlock) {
+    const uint32_t zq = t / cnt;
+    const int z = z0 + (int)zq;
+    const uint32_t xy = list[off[k] + (t - zq * cnt)];
     const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
     const uint32_t n = node_index(x, y, z, d.nx, d.ny);
     const double dx = (double)x - cx, dy = (double)y - cy;
@@ -85,37 +95,38 @@ k_pb_nodes(const float* __restrict__ u, const float* __restrict__ rho, const uin
   if (threadIdx.x < kPbM) {
     double t = 0.0;
     for (int w = 0; w < kPbBlock / 64; ++w) t += ws[w][threadIdx.x];
-    part[((size_t)k * d.nz + z) * kPbM + threadIdx.x] = t;
+    part[((size_t)k * nchunks + ch) * kPbM + threadIdx.x] = t;
   }
 }
 
-// acc[m][k] += sum over z of part[k][z][m], z in order.
+// acc[m][k] += sum over the chunks of part[k][chunk][m], in order.
 __global__ void __launch_bounds__(256)
-k_pb_reduce(const double* __restrict__ part, int nbins, int nz, double* __restrict__ acc) {
+k_pb_reduce(const double* __restrict__ part, int nbins, int nchunks, double* __restrict__ acc) {
   const int i = (int)(blockIdx.x * 256u + threadIdx.x);
   if (i >= kPbM * nbins) return;
   const int m = i / nbins, k = i % nbins;
   double t = 0.0;
-  for (int z = 0; z < nz; ++z) t += part[((size_t)k * nz + z) * kPbM + m];
+  for (int ch = 0; ch < nchunks; ++ch) t += part[((size_t)k * nchunks + ch) * kPbM + m];
   acc[(size_t)m * nbins + k] += t;
 }
 
 }  // namespace
 
 size_t pipe_budget_part_bytes(const Ctx& c, int nbins) {
-  return (size_t)nbins * (size_t)c.dims.nz * kPbM * sizeof(double);
+  return (size_t)nbins * (size_t)pb_chunks(c.dims.nz) * kPbM * sizeof(double);
 }
 
 hipError_t launch_pipe_budget_add(const Ctx& c, const float* u, const float* rho, const uint32_t* key,
                                   double* part) {
   const int nbins = c.pb.nbins;
   const int pc = c.pcur;
-  hipLaunchKernelGGL(k_pb_nodes, dim3((uint32_t)nbins * (uint32_t)c.dims.nz), dim3(kPbBlock), 0, c.stream, u, rho,
-                     key, c.P.X[pc], c.P.U[pc], c.P.Om[pc], c.dims, c.cfg.pipe_cx, c.cfg.pipe_cy, c.pb.list,
-                     c.pb.off, nbins, part);
+  const int nch = pb_chunks(c.dims.nz);
+  hipLaunchKernelGGL(k_pb_nodes, dim3((uint32_t)nbins * (uint32_t)nch), dim3(kPbBlock), 0, c.stream, u, rho, key,
+                     c.P.X[pc], c.P.U[pc], c.P.Om[pc], c.dims, c.cfg.pipe_cx, c.cfg.pipe_cy, c.pb.list, c.pb.off,
+                     nbins, nch, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pb_reduce, dim3((kPbM * nbins + 255) / 256), dim3(256), 0, c.stream, part, nbins, c.dims.nz,
+  hipLaunchKernelGGL(k_pb_reduce, dim3((kPbM * nbins + 255) / 256), dim3(256), 0, c.stream, part, nbins, nch,
                      c.pb.acc);
   return hipGetLastError();
 }
