@@ -54,6 +54,13 @@ enum { LBM_BC_NONE = 0, LBM_BC_IBB = 1, LBM_BC_IBM = 2 };
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16S = 1 };
 /* Static wall: none, or a pipe with its axis along z (Sec. 2.1). */
 enum { LBM_WALL_NONE = 0, LBM_WALL_PIPE_Z = 1 };
+/* Lattice. D3Q19 MRT (Sec. 3.1) runs every configuration. D3Q27 is the
+ * turbulent-pipe solver (Sec. 2.2): one relaxation parameter for every
+ * moment (BGK) plus an optional separate relaxation time for the energy mode
+ * (the bulk-viscosity knob the paper describes), Guo forcing, FP32 storage;
+ * a periodic box (LBM_BC_NONE) or the pipe wall with linear interpolated
+ * bounce-back (LBM_BC_IBB, LBM_WALL_PIPE_Z, ibb_max_order 1); no particles. */
+enum { LBM_LATTICE_D3Q19 = 0, LBM_LATTICE_D3Q27 = 1 };
 
 typedef struct {
   int32_t nx, ny, nz;        /* lattice size, each >= 4                      */
@@ -79,11 +86,17 @@ typedef struct {
   double max_radius;         /* largest sphere radius that will be set       */
   double coll_restitution;   /* soft-sphere normal restitution (Sec. 3.1)    */
   double coll_tc_steps;      /* soft-sphere contact duration, time steps     */
+  int32_t lattice;           /* LBM_LATTICE_*                                 */
+  double tau_bulk;           /* D3Q27: relaxation time of the energy mode,
+                                > 0.5, or 0 for tau (one parameter). The
+                                mode's viscosity nu_b = (tau_bulk - 1/2)/3
+                                gives the bulk viscosity 2 rho nu_b / 3.
+                                Must be 0 with D3Q19 (s_e plays that role) */
 } lbm_config;
 
 /* Fills *cfg with defaults: 32^3, tau 0.6, the usual d'Humieres rates, no
  * force, no boundary, FP32 storage, ibm_iters 2, restitution 0.97, contact
- * time 8 steps. */
+ * time 8 steps, D3Q19. */
 void lbm_config_default(lbm_config* cfg);
 
 /* Bytes of device workspace a context with this configuration needs.

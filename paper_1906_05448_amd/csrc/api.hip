@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "d3q27.hpp"
 #include "internal.hpp"
 
 using namespace lbm;
@@ -20,9 +21,11 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 size_t n_nodes(const lbm_config& c) { return (size_t)c.nx * (size_t)c.ny * (size_t)c.nz; }
 
+int lattice_q(const lbm_config& c) { return c.lattice == LBM_LATTICE_D3Q27 ? q27::kQ : kQ; }
+
 size_t pop_bytes(const lbm_config& c) {
   const size_t elem = c.store == LBM_STORE_F32 ? 4 : 2;
-  return align_up((size_t)kQ * n_nodes(c) * elem);
+  return align_up((size_t)lattice_q(c) * n_nodes(c) * elem);
 }
 
 bool has_particles(const lbm_config& c) { return c.bc != LBM_BC_NONE && c.max_particles > 0; }
@@ -63,14 +66,15 @@ bool pipe_solid(const lbm_config& c, int x, int y) {
 // Links into the static pipe wall (exact count; the pipe is z-invariant).
 uint32_t wall_link_count(const lbm_config& c) {
   if (c.wall != LBM_WALL_PIPE_Z) return 0;
-  const int cxv[18] = {1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
-  const int cyv[18] = {0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+  const bool l27 = c.lattice == LBM_LATTICE_D3Q27;
+  const int q = l27 ? q27::kQ : kQ;
   uint64_t n = 0;
   for (int y = 0; y < c.ny; ++y)
     for (int x = 0; x < c.nx; ++x) {
       if (pipe_solid(c, x, y)) continue;
-      for (int a = 0; a < 18; ++a) {
-        const int xs = ((x + cxv[a]) % c.nx + c.nx) % c.nx, ys = ((y + cyv[a]) % c.ny + c.ny) % c.ny;
+      for (int a = 1; a < q; ++a) {
+        const int dx = l27 ? q27::cx(a) : cx_of(a), dy = l27 ? q27::cy(a) : cy_of(a);
+        const int xs = ((x + dx) % c.nx + c.nx) % c.nx, ys = ((y + dy) % c.ny + c.ny) % c.ny;
         if (pipe_solid(c, xs, ys)) ++n;
       }
     }
@@ -350,6 +354,14 @@ int check_config(const lbm_config* c) {
       return LBM_E_ARG;
   }
   if (c->ibb_max_order != 1 && c->ibb_max_order != 2) return LBM_E_ARG;
+  if (c->lattice != LBM_LATTICE_D3Q19 && c->lattice != LBM_LATTICE_D3Q27) return LBM_E_ARG;
+  if (c->lattice == LBM_LATTICE_D3Q19 && c->tau_bulk != 0.0) return LBM_E_ARG;
+  if (c->lattice == LBM_LATTICE_D3Q27) {
+    // the pipe solver: FP32, periodic box or the linear bounce-back pipe wall
+    if (c->store != LBM_STORE_F32 || c->max_particles != 0 || c->bc == LBM_BC_IBM) return LBM_E_ARG;
+    if (c->bc == LBM_BC_IBB && (c->wall != LBM_WALL_PIPE_Z || c->ibb_max_order != 1)) return LBM_E_ARG;
+    if (!(c->tau_bulk == 0.0 || (c->tau_bulk > 0.5 && isfinite(c->tau_bulk)))) return LBM_E_ARG;
+  }
   if (c->ibm_iters < 0 || c->ibm_iters > 16) return LBM_E_ARG;
   if (!(c->coll_restitution > 0.0 && c->coll_restitution <= 1.0) || !(c->coll_tc_steps > 0.0)) return LBM_E_ARG;
   return LBM_OK;
@@ -891,9 +903,10 @@ int lbm_get_links(lbm_ctx* h, int64_t cap, int32_t* node, int32_t* dir, int32_t*
       node[3 * k + 2] = z;
     }
     if (dir) {
-      dir[3 * k] = cx_of(a);
-      dir[3 * k + 1] = cy_of(a);
-      dir[3 * k + 2] = cz_of(a);
+      const bool l27 = lattice27(c);
+      dir[3 * k] = l27 ? q27::cx(a) : cx_of(a);
+      dir[3 * k + 1] = l27 ? q27::cy(a) : cy_of(a);
+      dir[3 * k + 2] = l27 ? q27::cz(a) : cz_of(a);
     }
     if (particle) particle[k] = p;
     if (q) q[k] = qv;

@@ -17,29 +17,6 @@ namespace lbm {
 
 namespace {
 
-struct Tile {
-  int x, y, z;
-  bool live;
-};
-
-__device__ __forceinline__ Tile tile_coords(const Dims& d) {
-  // Physical workgroup b runs on XCD b % 8; give each XCD a contiguous
-  // range of logical tiles.
-  const uint32_t b = blockIdx.x;
-  const uint32_t logical = (b & 7u) * d.per_xcd + (b >> 3);
-  Tile t;
-  t.live = logical < d.ntiles;
-  const uint32_t rest = fast_div(d.div_gx, logical);
-  const uint32_t bx = logical - rest * d.gx;
-  const uint32_t bz = fast_div(d.div_gy, rest);
-  const uint32_t by = rest - bz * d.gy;
-  t.x = (int)(bx * 128u + (threadIdx.x & 127u));
-  t.y = (int)(by * 2u + (threadIdx.x >> 7));
-  t.z = (int)bz;
-  t.live = t.live && t.x < d.nx && t.y < d.ny;
-  return t;
-}
-
 // Immersed-boundary force lookup: node n is in the support iff its bit is
 // set; its slot is the word rank plus the set bits below it.
 struct IbView {
@@ -305,6 +282,7 @@ k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F0, Ib
 }  // namespace
 
 hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rho, void* f) {
+  if (lattice27(c)) return launch_init_equilibrium27(c, u, rho, f);
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
   if (c.cfg.store == LBM_STORE_F32)
@@ -323,6 +301,7 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 static bool use_seg_kernel(const Ctx& c) { return c.cfg.store == LBM_STORE_F16S && c.dims.nx % 2 == 0; }
 
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
+  if (lattice27(c)) return launch_stream_collide27(c, A, B);
   const dim3 grid(c.dims.per_xcd * 8), block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
   if (use_seg_kernel(c))
@@ -354,6 +333,7 @@ hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
 }
 
 hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho) {
+  if (lattice27(c)) return launch_fields27(c, f, F, u, rho);
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};

@@ -159,6 +159,16 @@ __device__ __forceinline__ void row_band(double o_lo, double o_hi, double h_lo, 
   b1 = o1;
 }
 
+// Pipe wall: root t in [0, 1) of |dxy + t cxy|^2 = R^2 for a point inside
+// heading out.
+__device__ __forceinline__ double pipe_q(double dx, double dy, int cx, int cy, double R) {
+  const double a = (double)(cx * cx + cy * cy);
+  const double b = dx * cx + dy * cy;
+  const double cc = (dx * dx + dy * dy) - R * R;
+  const double disc = sqrt(b * b - a * cc);
+  return b >= 0.0 ? -cc / (b + disc) : (disc - b) / a;
+}
+
 // Link nodes are stored as packed coordinates x | y << 11 | z << 22.
 __device__ __forceinline__ uint32_t pack_xyz(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);

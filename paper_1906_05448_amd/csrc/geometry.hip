@@ -317,16 +317,6 @@ k_links_build(const uint32_t* __restrict__ owner, const double* __restrict__ X, 
   }
 }
 
-// Pipe wall: root t in [0, 1) of |dxy + t cxy|^2 = R^2 for a point inside
-// heading out.
-__device__ __forceinline__ double pipe_q(double dx, double dy, int cx, int cy, double R) {
-  const double a = (double)(cx * cx + cy * cy);
-  const double b = dx * cx + dy * cy;
-  const double cc = (dx * dx + dy * dy) - R * R;
-  const double disc = sqrt(b * b - a * cc);
-  return b >= 0.0 ? -cc / (b + disc) : (disc - b) / a;
-}
-
 __global__ void __launch_bounds__(256)
 k_wall_links(const uint32_t* __restrict__ owner, Dims d, double R, double pcx, double pcy, uint32_t* __restrict__ counter,
              uint32_t cap, uint32_t* __restrict__ node_out, float* __restrict__ q_out, uint8_t* __restrict__ meta_out,
@@ -398,6 +388,7 @@ hipError_t launch_links_build(const Ctx& c, const uint32_t* owner, const double*
 }
 
 hipError_t launch_wall_links(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only) {
+  if (lattice27(c)) return launch_wall_links27(c, owner, counter, count_only);
   const uint32_t N = c.dims.N;
   hipLaunchKernelGGL(k_wall_links, dim3((N + 255) / 256), dim3(256), 0, c.stream, owner, c.dims, c.cfg.pipe_radius,
                      c.cfg.pipe_cx, c.cfg.pipe_cy, counter, c.ibb.wl_count, c.ibb.wl_node, c.ibb.wl_q,

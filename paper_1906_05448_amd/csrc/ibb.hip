@@ -468,6 +468,7 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
 }  // namespace
 
 hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double* U, const double* Om) {
+  if (lattice27(c)) return launch_wall_bounce27(c, A);  // no particles on that lattice
   if (c.ibb.wl_count) {
     const dim3 g((c.ibb.wl_count + 255) / 256);
     if (c.cfg.store == LBM_STORE_F32)

@@ -86,6 +86,31 @@ inline Dims make_dims(int nx, int ny, int nz) {
   return d;
 }
 
+// Tile of the one-node stream-collide kernels (128 x 2 nodes) of workgroup
+// blockIdx.x.
+struct Tile {
+  int x, y, z;
+  bool live;
+};
+
+__device__ __forceinline__ Tile tile_coords(const Dims& d) {
+  // Physical workgroup b runs on XCD b % 8; give each XCD a contiguous
+  // range of logical tiles.
+  const uint32_t b = blockIdx.x;
+  const uint32_t logical = (b & 7u) * d.per_xcd + (b >> 3);
+  Tile t;
+  t.live = logical < d.ntiles;
+  const uint32_t rest = fast_div(d.div_gx, logical);
+  const uint32_t bx = logical - rest * d.gx;
+  const uint32_t bz = fast_div(d.div_gy, rest);
+  const uint32_t by = rest - bz * d.gy;
+  t.x = (int)(bx * 128u + (threadIdx.x & 127u));
+  t.y = (int)(by * 2u + (threadIdx.x >> 7));
+  t.z = (int)bz;
+  t.live = t.live && t.x < d.nx && t.y < d.ny;
+  return t;
+}
+
 // Bitmask words covering N nodes.
 inline uint32_t mask_words(uint32_t N) { return (N + 31u) / 32u; }
 
@@ -275,6 +300,14 @@ hipError_t timed(Ctx& c, int cls, F&& launch) {
 // Dense kernels (dense.hip).
 hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rho, void* f);
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B);
+// D3Q27 pipe solver (d3q27.hip); the D3Q19 launchers dispatch to these
+// when the configuration selects that lattice.
+hipError_t launch_stream_collide27(const Ctx& c, const void* A, void* B);
+hipError_t launch_init_equilibrium27(const Ctx& c, const float* u, const float* rho, void* f);
+hipError_t launch_fields27(const Ctx& c, const void* f, float3 F, float* u, float* rho);
+hipError_t launch_wall_links27(Ctx& c, const uint32_t* owner, uint32_t* counter, bool count_only);
+hipError_t launch_wall_bounce27(const Ctx& c, void* A);
+inline bool lattice27(const Ctx& c) { return c.cfg.lattice == LBM_LATTICE_D3Q27; }
 // u, rho from post-collision populations; F is the force of the collision
 // that produced them (zero before the first step).
 hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float* rho);

@@ -19,6 +19,7 @@ STORE_F32, STORE_F16S = 0, 1
 WALL_NONE, WALL_PIPE_Z = 0, 1
 SET_STATE, RELEASE, SET_RIGID = 0, 1, 2
 MOTION_FREE, MOTION_FIXED, MOTION_PRESCRIBED = 0, 1, 2
+LATTICE_D3Q19, LATTICE_D3Q27 = 0, 1
 PIPE_BUDGET_MOMENTS, PIPE_BUDGET_TERMS = 38, 13
 KERNEL_CLASSES = ("stream_collide", "geometry", "ibb_links", "refill", "ibm_prepass", "ibm_forcing",
                   "particle", "stats", "corrector")
@@ -45,6 +46,7 @@ class _CConfig(ctypes.Structure):
         ("pipe_radius", ctypes.c_double), ("pipe_cx", ctypes.c_double), ("pipe_cy", ctypes.c_double),
         ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double),
         ("coll_restitution", ctypes.c_double), ("coll_tc_steps", ctypes.c_double),
+        ("lattice", ctypes.c_int32), ("tau_bulk", ctypes.c_double),
     ]
 
 
@@ -149,6 +151,8 @@ class Config:
     max_radius: float = 0.0
     coll_restitution: float = 0.97
     coll_tc_steps: float = 8.0
+    lattice: int = LATTICE_D3Q19
+    tau_bulk: float = 0.0
 
     def to_c(self) -> _CConfig:
         c = _CConfig()

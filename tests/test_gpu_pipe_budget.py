@@ -19,10 +19,10 @@ pytestmark = pytest.mark.gpu
 TAU = 0.56
 
 
-def _lattice(shape, pipe, bc):
+def _lattice(shape, pipe, bc, lattice=0):
     R, cx, cy = pipe
     kw = dict(nx=shape[0], ny=shape[1], nz=shape[2], tau=TAU, body_force=(0.0, 0.0, 2e-5), bc=bc, wall=1,
-              pipe_radius=R, pipe_cx=cx, pipe_cy=cy, store=0)
+              pipe_radius=R, pipe_cx=cx, pipe_cy=cy, store=0, lattice=lattice)
     if bc == 1:
         kw["ibb_max_order"] = 1
     return gpu_lattice(gpu_config(**kw))
@@ -36,12 +36,12 @@ def _oracle_add(M, g, shape, pipe, w):
     opb.add_snapshot(M, um, rho.astype(np.float64), shape, pipe, w)
 
 
-@pytest.mark.parametrize("bc", [1, 2])
-def test_pipe_budget_matches_oracle(bc):
+@pytest.mark.parametrize("bc,lattice", [(1, lbm.LATTICE_D3Q19), (2, lbm.LATTICE_D3Q19), (1, lbm.LATTICE_D3Q27)])
+def test_pipe_budget_matches_oracle(bc, lattice):
     shape = (32, 30, 24)
     pipe = (11.3, 15.4, 14.6)
     w = 0.75
-    g = _lattice(shape, pipe, bc)
+    g = _lattice(shape, pipe, bc, lattice)
     spec = synth.hit_spectrum(seed=11, u_rms=0.01, kcut=5)
     g.set_fields(synth.hit_field(spec, shape))
     g.step(5)
