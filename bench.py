@@ -101,6 +101,8 @@ def parse():
     p.add_argument("--pipe", action="store_true",
                    help="time the 160x160x480 pipe (R = 74.5, linear bounce-back wall, FP32) and one snapshot of "
                         "its component TKE budget instead of the headline workload")
+    p.add_argument("--pipe-lattice", type=int, choices=(19, 27), default=27,
+                   help="pipe solver lattice: 27 (the paper's pipe model, one relaxation parameter) or 19 (MRT)")
     return p.parse_args()
 
 
@@ -331,15 +333,16 @@ def gpu_error_vs_oracle(sim, u0, X, steps):
     return res
 
 
-def run_pipe(torch, lbm, synth, steps, warmup):
+def run_pipe(torch, lbm, synth, steps, warmup, q=27):
     """The turbulent-pipe workload: steps per second, one TKE-budget snapshot
     (lbm_pipe_budget_add) and one statistics call, timed with HIP events on
-    the library's stream."""
+    the library's stream; the fused stream-collide kernel's HBM roofline from
+    the library's per-kernel events over a second pass."""
     shape, R, c = (160, 160, 480), 74.5, (79.5, 79.5)
     tau, F = 0.52, 7e-6
     cfg = lbm.Config(nx=shape[0], ny=shape[1], nz=shape[2], tau=tau, body_force=(0.0, 0.0, F), bc=lbm.BC_IBB,
                      ibb_max_order=1, wall=lbm.WALL_PIPE_Z, pipe_radius=R, pipe_cx=c[0], pipe_cy=c[1],
-                     store=lbm.STORE_F32)
+                     store=lbm.STORE_F32, lattice=lbm.LATTICE_D3Q27 if q == 27 else lbm.LATTICE_D3Q19)
     lat = lbm.Lattice(cfg)
     u0 = synth.pipe_initial_velocity(shape, R, c, 0.05, 0.05, seed=0)
     lat.set_fields(u0.astype(np.float32))
@@ -353,6 +356,12 @@ def run_pipe(torch, lbm, synth, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / steps
+    lat.profile_enable(True)
+    lat.step(steps)
+    prof = lat.profile_read()
+    lat.profile_enable(False)
+    lat.sync()
+    sc_ms = prof["stream_collide"][0] / prof["stream_collide"][1]
     lat.pipe_budget_reset(0.5)
     lat.pipe_budget_add()  # warm
     t = []
@@ -366,14 +375,19 @@ def run_pipe(torch, lbm, synth, steps, warmup):
     ns, M, T = lat.pipe_budget_read()
     lat.close()
     N = shape[0] * shape[1] * shape[2]
+    gbs = 2 * q * 4 * N / (sc_ms * 1e-3) / 1e9   # every population read once and written once, FP32
+    model = ("D3Q27, one relaxation parameter (BGK)" if q == 27 else "D3Q19 MRT")
     return {"metric": "pipe step time and TKE-budget snapshot time", "unit": "ms", "n_gpus": 1,
-            "data": "synthetic",
-            "config": {"workload": "160x160x480 pipe, R=74.5 along z, linear interpolated bounce-back wall, "
-                                   "FP32 populations, tau 0.52, body force 7e-6, Poiseuille start + 5% noise",
-                       "budget_bin_width": 0.5, "budget_bins": int(M.shape[1])},
+            "data": "synthetic", "dtype": "f32",
+            "config": {"workload": f"160x160x480 pipe, R=74.5 along z, {model}, linear interpolated bounce-back "
+                                   "wall, FP32 populations, tau 0.52, body force 7e-6, Poiseuille start + 5% noise",
+                       "lattice": f"D3Q{q}", "budget_bin_width": 0.5, "budget_bins": int(M.shape[1])},
             "steps": steps, "warmup": warmup, "ms_per_step": round(step_ms, 4),
             "mlups": round(N / (step_ms * 1e-3) / 1e6, 1), "budget_add_ms": round(t[0], 4),
-            "stats_ms": round(t[1], 4), "budget_snapshots": int(ns)}
+            "stats_ms": round(t[1], 4), "budget_snapshots": int(ns),
+            "roofline": {"bound": "hbm", "kernel": f"stream_collide (D3Q{q})", "achieved": round(gbs, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": None, "ms": round(sc_ms, 4)}}
 
 
 def main():
@@ -389,7 +403,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.pipe:
-        print(json.dumps(run_pipe(torch, lbm, synth, args.steps, args.warmup)), flush=True)
+        print(json.dumps(run_pipe(torch, lbm, synth, args.steps, args.warmup, args.pipe_lattice)), flush=True)
         return
     n = args.n
     bcs = {"ibb": lbm.BC_IBB, "ibm": lbm.BC_IBM, "ibmc": lbm.BC_IBM, "none": lbm.BC_NONE}
