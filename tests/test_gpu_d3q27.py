@@ -37,11 +37,11 @@ def _pair(shape, tau, tau_bulk, F, u0, r0, steps, pipe=None):
     return g, ug, rg, o
 
 
-@pytest.mark.parametrize("tau_bulk", [0.0, 1.3])
-def test_periodic_ragged_tiles(tau_bulk):
-    # 150 x 13 x 9: two 128-wide tiles with a ragged x tail, an odd y
-    # against the 2-row tiles
-    shape = (150, 13, 9)
+@pytest.mark.parametrize("tau_bulk,shape", [(0.0, (150, 13, 9)), (1.3, (150, 13, 9)), (1.3, (256, 7, 5))])
+def test_periodic_ragged_tiles(tau_bulk, shape):
+    # 150 x 13 x 9: 64 x 4 tiles (they fill a 150-node row better than
+    # 128 x 2), a ragged x tail, a ragged y tail; 256 x 7 x 5: 128 x 2 tiles
+    # with an odd y
     F = (1e-5, -2e-5, 3e-5)
     u0 = synth.random_velocity(shape, 0.05, seed=21)
     r0 = synth.random_density(shape, 0.01, seed=22)
