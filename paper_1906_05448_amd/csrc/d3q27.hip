@@ -7,8 +7,6 @@
 // kernel uses the D3Q19 kernel's 128 x 2 tiles in XCD-contiguous order, one
 // node per lane, the nine source row offsets in scalar registers and
 // non-temporal stores: 216 bytes of HBM traffic per node and step.
-#include <cmath>
-
 #include "d3q27.hpp"
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -18,41 +16,6 @@ namespace lbm {
 namespace {
 
 using namespace q27;
-
-// Tiles of TW x (256 / TW) nodes in XCD-contiguous order: 128 x 2 as the
-// D3Q19 kernel, or 64 x 4 where that leaves fewer idle lanes at the end of a
-// row (a 160-node row fills 5 of 6 wavefronts instead of 5 of 8).
-struct Tiles {
-  uint32_t gx, gy, ntiles, per_xcd;
-  FastDiv div_gx, div_gy;
-};
-
-Tiles make_tiles(const Dims& d, int tw) {
-  Tiles g;
-  g.gx = (uint32_t)(d.nx + tw - 1) / (uint32_t)tw;
-  g.gy = (uint32_t)(d.ny + 256 / tw - 1) / (uint32_t)(256 / tw);
-  g.ntiles = g.gx * g.gy * (uint32_t)d.nz;
-  g.per_xcd = (g.ntiles + 7) / 8;
-  g.div_gx = make_fastdiv(g.gx);
-  g.div_gy = make_fastdiv(g.gy);
-  return g;
-}
-
-template <int TW>
-__device__ __forceinline__ Tile tile_of(const Dims& d, const Tiles& g) {
-  const uint32_t b = blockIdx.x;
-  const uint32_t logical = (b & 7u) * g.per_xcd + (b >> 3);
-  const uint32_t rest = fast_div(g.div_gx, logical);
-  const uint32_t bx = logical - rest * g.gx;
-  const uint32_t bz = fast_div(g.div_gy, rest);
-  const uint32_t by = rest - bz * g.gy;
-  Tile t;
-  t.x = (int)(bx * (uint32_t)TW + (threadIdx.x % (uint32_t)TW));
-  t.y = (int)(by * (256u / TW) + threadIdx.x / (uint32_t)TW);
-  t.z = (int)bz;
-  t.live = logical < g.ntiles && t.x < d.nx && t.y < d.ny;
-  return t;
-}
 
 template <int TW>
 __global__ void __launch_bounds__(256)
@@ -184,10 +147,7 @@ Rates rates27(const Ctx& c) {
 }  // namespace
 
 hipError_t launch_stream_collide27(const Ctx& c, const void* A, void* B) {
-  // live share of the lanes along x for each tile width
-  const double nx = c.dims.nx;
-  const double fill128 = nx / (128.0 * std::ceil(nx / 128.0)), fill64 = nx / (64.0 * std::ceil(nx / 64.0));
-  if (fill64 > fill128) {
+  if (tile_width(c.dims.nx) == 64) {
     const Tiles tg = make_tiles(c.dims, 64);
     hipLaunchKernelGGL(k_sc27<64>, dim3(tg.per_xcd * 8), dim3(256), 0, c.stream, (const float*)A, (float*)B, c.dims,
                        tg, rates27(c), c.body_force, c.err);

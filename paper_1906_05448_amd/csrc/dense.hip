@@ -46,13 +46,14 @@ __device__ __forceinline__ void add_ib_force(const IbView& v, uint32_t n, float3
 }
 
 // MODE 0: uniform force. MODE 2: plus the immersed-boundary force at the
-// support nodes.
-template <int STORE, int MODE>
+// support nodes. TW: tile width, 128 (128 x 2 tiles) or 64 (64 x 4) where
+// that fills the rows better.
+template <int STORE, int MODE, int TW>
 __global__ void __launch_bounds__(256)
 k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STORE>::T* __restrict__ B,
-                 Dims d, MrtRates r, float3 F0, IbView ib, uint32_t* __restrict__ err) {
+                 Dims d, Tiles tg, MrtRates r, float3 F0, IbView ib, uint32_t* __restrict__ err) {
   using P = Pop<STORE>;
-  const Tile t = tile_coords(d);
+  const Tile t = tile_of<TW>(d, tg);
   if (!t.live) return;
   // One wavefront covers 64 nodes of one row: y is uniform across it. With FP32
   // storage the kernel keeps the row offsets in scalar registers (measured
@@ -300,35 +301,47 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
 // FP16 storage with an even row length stages its rows through LDS.
 static bool use_seg_kernel(const Ctx& c) { return c.cfg.store == LBM_STORE_F16S && c.dims.nx % 2 == 0; }
 
+// One-node kernel in the tile width that fills the rows best.
+template <int STORE, int MODE>
+hipError_t launch_one_node(const Ctx& c, const void* A, void* B, const IbView& ib) {
+  using T = typename Pop<STORE>::T;
+  if (tile_width(c.dims.nx) == 64) {
+    const Tiles tg = make_tiles(c.dims, 64);
+    hipLaunchKernelGGL((k_stream_collide<STORE, MODE, 64>), dim3(tg.per_xcd * 8), dim3(256), 0, c.stream,
+                       (const T*)A, (T*)B, c.dims, tg, c.rates, c.body_force, ib, c.err);
+  } else {
+    const Tiles tg = make_tiles(c.dims, 128);
+    hipLaunchKernelGGL((k_stream_collide<STORE, MODE, 128>), dim3(tg.per_xcd * 8), dim3(256), 0, c.stream,
+                       (const T*)A, (T*)B, c.dims, tg, c.rates, c.body_force, ib, c.err);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
   if (lattice27(c)) return launch_stream_collide27(c, A, B);
-  const dim3 grid(c.dims.per_xcd * 8), block(256);
+  const dim3 block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
   if (use_seg_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_seg<0>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
                        (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, none, c.err);
   else if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL((k_stream_collide<0, 0>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
-                       c.rates, c.body_force, none, c.err);
+    return launch_one_node<0, 0>(c, A, B, none);
   else
-    hipLaunchKernelGGL((k_stream_collide<1, 0>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
-                       c.dims, c.rates, c.body_force, none, c.err);
+    return launch_one_node<1, 0>(c, A, B, none);
   return hipGetLastError();
 }
 
 hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
-  const dim3 grid(c.dims.per_xcd * 8), block(256);
+  const dim3 block(256);
   const int b = c.ibm.cur;
   const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap, ibm_body_force_mask(c)};
   if (use_seg_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_seg<2>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
                        (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, ib, c.err);
   else if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL((k_stream_collide<0, 2>), grid, block, 0, c.stream, (const float*)A, (float*)B, c.dims,
-                       c.rates, c.body_force, ib, c.err);
+    return launch_one_node<0, 2>(c, A, B, ib);
   else
-    hipLaunchKernelGGL((k_stream_collide<1, 2>), grid, block, 0, c.stream, (const _Float16*)A, (_Float16*)B,
-                       c.dims, c.rates, c.body_force, ib, c.err);
+    return launch_one_node<1, 2>(c, A, B, ib);
   return hipGetLastError();
 }
 

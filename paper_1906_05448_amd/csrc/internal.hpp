@@ -23,10 +23,9 @@ constexpr uint32_t kWall = 0xFFFFFFFEu;
 // Link metadata byte: direction (bits 0..4), scheme (bits 5..6).
 enum : uint32_t { kSchemeHalfway = 0, kSchemeLinear = 1, kSchemeQuadratic = 2 };
 
-// Lattice extent plus the launch geometry of the dense kernels. Blocks are
-// 64 x 4 threads (one wavefront per 64-node x-run); the flat block id is
-// remapped so that consecutive tiles land on the same XCD (the hardware deals
-// workgroups round-robin over the 8 XCDs, each with its own L2).
+// Dense kernels remap the flat block id so that consecutive tiles land on the
+// same XCD (the hardware deals workgroups round-robin over the 8 XCDs, each
+// with its own L2).
 // Unsigned division by an invariant divisor d >= 1 with one multiply-high
 // (Granlund & Montgomery 1994, round-up method):
 //   l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
@@ -54,12 +53,6 @@ __device__ __forceinline__ uint32_t fast_div(const FastDiv& f, uint32_t n) {
 struct Dims {
   int nx, ny, nz;
   uint32_t N;       // nodes
-  // Tiles of the one-node stream-collide kernel: 128 x 2 nodes (two
-  // wavefronts side by side in x; measured 1.4% faster than 64 x 4 in FP32).
-  uint32_t gx, gy;  // tiles along x (128 wide) and y (2 tall)
-  uint32_t ntiles;  // gx * gy * nz
-  uint32_t per_xcd; // ceil(ntiles / 8)
-  FastDiv div_gx, div_gy;
   // Tiles of 128 x 4 nodes for the FP16 kernel that stages rows in LDS.
   uint32_t gx2, gy2, ntiles2, per_xcd2;
   FastDiv div_gx2, div_gy2;
@@ -71,12 +64,6 @@ inline Dims make_dims(int nx, int ny, int nz) {
   d.ny = ny;
   d.nz = nz;
   d.N = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
-  d.gx = (uint32_t)(nx + 127) / 128;
-  d.gy = (uint32_t)(ny + 1) / 2;
-  d.ntiles = d.gx * d.gy * (uint32_t)nz;
-  d.per_xcd = (d.ntiles + 7) / 8;
-  d.div_gx = make_fastdiv(d.gx);
-  d.div_gy = make_fastdiv(d.gy);
   d.gx2 = (uint32_t)(nx + 127) / 128;
   d.gy2 = (uint32_t)(ny + 3) / 4;
   d.ntiles2 = d.gx2 * d.gy2 * (uint32_t)nz;
@@ -86,29 +73,52 @@ inline Dims make_dims(int nx, int ny, int nz) {
   return d;
 }
 
-// Tile of the one-node stream-collide kernels (128 x 2 nodes) of workgroup
-// blockIdx.x.
+// Coordinates of a lane's node in its workgroup's tile.
 struct Tile {
   int x, y, z;
   bool live;
 };
 
-__device__ __forceinline__ Tile tile_coords(const Dims& d) {
-  // Physical workgroup b runs on XCD b % 8; give each XCD a contiguous
-  // range of logical tiles.
+// Tiles of TW x (256 / TW) nodes of the one-node FP32 kernels (D3Q19 and
+// D3Q27) in XCD-contiguous order: 128 x 2 (measured 1.4% faster than 64 x 4
+// where both fill the rows), or 64 x 4 where that leaves fewer idle lanes at
+// the end of a row (a 160-node row fills 5 of 6 wavefronts instead of 5 of 8).
+struct Tiles {
+  uint32_t gx, gy, ntiles, per_xcd;
+  FastDiv div_gx, div_gy;
+};
+
+inline Tiles make_tiles(const Dims& d, int tw) {
+  Tiles g;
+  g.gx = (uint32_t)(d.nx + tw - 1) / (uint32_t)tw;
+  g.gy = (uint32_t)(d.ny + 256 / tw - 1) / (uint32_t)(256 / tw);
+  g.ntiles = g.gx * g.gy * (uint32_t)d.nz;
+  g.per_xcd = (g.ntiles + 7) / 8;
+  g.div_gx = make_fastdiv(g.gx);
+  g.div_gy = make_fastdiv(g.gy);
+  return g;
+}
+
+template <int TW>
+__device__ __forceinline__ Tile tile_of(const Dims& d, const Tiles& g) {
   const uint32_t b = blockIdx.x;
-  const uint32_t logical = (b & 7u) * d.per_xcd + (b >> 3);
+  const uint32_t logical = (b & 7u) * g.per_xcd + (b >> 3);
+  const uint32_t rest = fast_div(g.div_gx, logical);
+  const uint32_t bx = logical - rest * g.gx;
+  const uint32_t bz = fast_div(g.div_gy, rest);
+  const uint32_t by = rest - bz * g.gy;
   Tile t;
-  t.live = logical < d.ntiles;
-  const uint32_t rest = fast_div(d.div_gx, logical);
-  const uint32_t bx = logical - rest * d.gx;
-  const uint32_t bz = fast_div(d.div_gy, rest);
-  const uint32_t by = rest - bz * d.gy;
-  t.x = (int)(bx * 128u + (threadIdx.x & 127u));
-  t.y = (int)(by * 2u + (threadIdx.x >> 7));
+  t.x = (int)(bx * (uint32_t)TW + (threadIdx.x % (uint32_t)TW));
+  t.y = (int)(by * (256u / TW) + threadIdx.x / (uint32_t)TW);
   t.z = (int)bz;
-  t.live = t.live && t.x < d.nx && t.y < d.ny;
+  t.live = logical < g.ntiles && t.x < d.nx && t.y < d.ny;
   return t;
+}
+
+// 64 where 64 x 4 tiles leave fewer idle lanes along x than 128 x 2.
+inline int tile_width(int nx) {
+  const int g128 = (nx + 127) / 128, g64 = (nx + 63) / 64;
+  return 128 * g128 > 64 * g64 ? 64 : 128;
 }
 
 // Bitmask words covering N nodes.
