@@ -50,15 +50,35 @@ MIN_GAP = 2.0          # centre distance >= 2r + 2 at placement
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_traffic_512cubed.md")
 TRAFFIC_SOURCES = ("paper_1906_05448_amd/csrc/dense.hip", "paper_1906_05448_amd/csrc/d3q19.hpp")
+PIPE27_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipe27_traffic_160x160x480.md")
+PIPE27_SOURCES = ("paper_1906_05448_amd/csrc/d3q27.hip", "paper_1906_05448_amd/csrc/d3q27.hpp")
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources or TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def _traffic_record(path, tag, sources, variant):
+    """traffic_bytes_per_launch of `variant` from a committed counter summary
+    whose source_sha256 `tag` line matches the current kernel sources."""
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    rec = {}
+    for ln in lines:
+        parts = ln.strip().strip("`").split()
+        if len(parts) == 3 and parts[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            rec[(parts[0], parts[1])] = parts[2]
+    if rec.get(("source_sha256", tag)) != kernel_source_hash(sources):
+        return None
+    v = rec.get(("traffic_bytes_per_launch", variant))
+    return int(v) if v is not None else None
 
 
 def recorded_traffic(variant, n, particles):
@@ -67,19 +87,7 @@ def recorded_traffic(variant, n, particles):
     (512^3, 6250 spheres), else None."""
     if n != 512 or particles != 6250:
         return None
-    try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
-    except OSError:
-        return None
-    rec = {}
-    for ln in lines:
-        parts = ln.strip().strip("`").split()
-        if len(parts) == 3 and parts[0] in ("traffic_bytes_per_launch", "source_sha256"):
-            rec[(parts[0], parts[1])] = parts[2]
-    if rec.get(("source_sha256", "dense")) != kernel_source_hash():
-        return None
-    v = rec.get(("traffic_bytes_per_launch", variant))
-    return int(v) if v is not None else None
+    return _traffic_record(TRAFFIC_FILE, "dense", TRAFFIC_SOURCES, variant)
 
 
 def log(*a):
@@ -387,7 +395,8 @@ def run_pipe(torch, lbm, synth, steps, warmup, q=27):
             "stats_ms": round(t[1], 4), "budget_snapshots": int(ns),
             "roofline": {"bound": "hbm", "kernel": f"stream_collide (D3Q{q})", "achieved": round(gbs, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "traffic": None, "ms": round(sc_ms, 4)}}
+                         "traffic": (_traffic_record(PIPE27_TRAFFIC_FILE, "d3q27", PIPE27_SOURCES, "pipe27")
+                                     if q == 27 else None), "ms": round(sc_ms, 4)}}
 
 
 def main():

@@ -120,3 +120,16 @@ def test_configuration_errors():
             gpu_lattice(gpu_config(**base, **bad))
     with pytest.raises(lbm.LbmError):  # the knob belongs to the D3Q27 solver
         gpu_lattice(gpu_config(nx=16, ny=16, nz=8, tau_bulk=1.0))
+
+
+def test_instability_is_reported():
+    g = gpu_lattice(_cfg((8, 8, 8), 0.6, 0.0, (0, 0, 0)))
+    u = np.zeros((3, 8, 8, 8))
+    u[0] = 0.4                      # above the |u| < 0.35 guard
+    g.set_fields(u)
+    g.step(1)
+    with pytest.raises(lbm.LbmError) as ei:
+        g.sync()
+    assert ei.value.status == -5
+    g.sync()                        # the latch clears once reported
+    g.close()
