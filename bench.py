@@ -115,17 +115,36 @@ def parse():
 
 
 def advance(lat, steps, every):
-    """steps time steps with lbm_stats every `every` steps; returns the last
-    statistics (or None)."""
+    """steps time steps with lbm_stats after every `every` steps, and after the
+    last step when fewer than `every` are timed, so the statistics (and the
+    corrector) always run inside the timed region; returns (the last
+    statistics or None, the number of statistics calls)."""
     s = None
-    done = 0
+    done = calls = 0
     while done < steps:
         k = steps - done if every <= 0 else min(every, steps - done)
         lat.step(k)
         done += k
-        if every > 0 and done % every == 0:
+        if every > 0 and (done % every == 0 or (done == steps and calls == 0)):
             s = lat.stats(nbins=32)
-    return s
+            calls += 1
+    return s, calls
+
+
+def step_bytes(bc, s, N, fluid, links, support):
+    """Algorithmic HBM bytes of one step (the method's traffic, not the
+    implementation's): every fluid node's 19 populations read and written
+    once; bounce-back adds the solid bitmask and 16 bytes of link data per
+    link (written by the geometry, read by the link pass); the immersed
+    boundary adds per support node the pre-pass (19 populations read, the
+    density and velocity written: 12 bytes), three forcing passes (12 bytes
+    read, 24 bytes of force read-modify-write) and the force read by the
+    collision (12 bytes)."""
+    if bc == "ibb":
+        return 38 * s * fluid + N // 8 + 16 * links
+    if bc in ("ibm", "ibmc"):
+        return 38 * s * N + support * (19 * s + 12 + 3 * 36 + 12)
+    return 38 * s * N
 
 
 def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=None):
@@ -138,6 +157,7 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
     if corr is not None:
         lat.corrector_set(corr, 0.0, 10.0, U_RMS)
     solid, links = lat.geometry_counts() if bc == lbm.BC_IBB else (0, 0)
+    support, shared = lat.ibm_support() if bc == lbm.BC_IBM else (0, 0)
     lat.step(warmup)
     lat.sync()
     stream = lat.stream
@@ -145,7 +165,7 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    st = advance(lat, steps, every)
+    st, stats_calls = advance(lat, steps, every)
     t1.record(stream)
     torch.cuda.synchronize()
     lat.sync()
@@ -184,7 +204,8 @@ def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
     out = dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
                kernel_avg_ms=k_avg, kernel_launches=k_n, alg_bytes=alg_bytes, achieved_gbs=achieved,
-               solid_nodes=solid, links=links,
+               solid_nodes=solid, links=links, support_nodes=support, shared_support_nodes=shared,
+               stats_calls_timed=stats_calls,
                kernels_ms_per_step={k: v[0] / steps for k, v in prof.items() if v[1]},
                spectrum_ms=spec_ms)
     if st is not None:
@@ -282,11 +303,31 @@ def train_corrector(torch, lbm):
     return net, info
 
 
-def cpu_baseline():
-    """The FP64 oracle, one thread, on a 64^3 box of the same recipe (12
-    released spheres of radius 8, ~10% volume fraction, bounce-back), a few
-    steps: about 10-20 s of CPU work."""
-    from threadpoolctl import threadpool_limits
+def host_description():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_sample(bc, threads, budget_s):
+    """The FP64 oracle on a 64^3 box of the production recipe (12 released
+    spheres of radius 8, ~10% volume fraction, density ratio 4) with the
+    given no-slip treatment, timed over about budget_s seconds of stepping
+    with the numerical libraries limited to `threads` threads (None: their
+    default). Returns (sim, u0, X, steps timed, seconds, threads used)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import synth
     from oracle.sim import RELEASE, Config as OConfig, Sim as OSim
@@ -294,26 +335,46 @@ def cpu_baseline():
     spec = synth.hit_spectrum(seed=0, u_rms=U_RMS)
     u0 = synth.hit_field(spec, (n, n, n))
     X = synth.random_spheres(12, (n, n, n), 2 * RADIUS + MIN_GAP, seed=0)
-    with threadpool_limits(limits=1):
-        sim = OSim(OConfig(shape=(n, n, n), tau=TAU, bc="ibb"))
+    with threadpool_limits(limits=threads):
+        used = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        sim = OSim(OConfig(shape=(n, n, n), tau=TAU, bc=bc, ibm_retraction=IBM_RD))
         sim.set_fields(u0)
         sim.set_particles(X, r=np.full(len(X), RADIUS), rho_p=np.full(len(X), RHO_P), mode=RELEASE)
         sim.step(1)
         t = time.perf_counter()
         sim.step(1)
         one = time.perf_counter() - t
-        steps = max(2, min(200, int(12.0 / max(one, 1e-3))))
+        steps = max(2, min(200, int(budget_s / max(one, 1e-3))))
         t = time.perf_counter()
         sim.step(steps)
         dt = time.perf_counter() - t
-    out = dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-               sample=f"{n}^3 box of the same recipe with 12 spheres r=8 (bounce-back, FP64), {steps} steps, "
-                      f"{dt:.1f} s, numpy single thread")
-    out["error_vs_fp64"] = gpu_error_vs_oracle(sim, u0, X, steps + 2)
+    return sim, u0, X, steps, dt, used
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample of the same recipe (a 64^3 box,
+    12 released spheres of radius 8, bounce-back), timed with the numerical
+    libraries on all usable cores and on one core: about 10 s of CPU work
+    each. The same sample with bounce-back and with the immersed boundary
+    also gives the GPU's FP32 and FP16 error against FP64."""
+    n = 64
+    host = host_description()
+    sim, u0, X, steps, dt, used = _oracle_sample("ibb", None, 10.0)
+    _, _, _, steps1, dt1, _ = _oracle_sample("ibb", 1, 10.0)
+    out = dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=used, kind="oracle",
+               sample=f"{n}^3 box of the same recipe with 12 spheres r=8 (bounce-back, FP64 numpy oracle), "
+                      f"{steps} steps in {dt:.1f} s with {used} threads",
+               single_core={"value": n ** 3 * steps1 / dt1 / 1e6, "unit": "MLUPS", "cores": 1,
+                            "sample": f"the same, {steps1} steps in {dt1:.1f} s"},
+               host=host)
+    err = {"ibb": gpu_error_vs_oracle(sim, u0, X, steps + 2, "ibb")}
+    sim_m, u0m, Xm, steps_m, _, _ = _oracle_sample("ibm", None, 6.0)
+    err["ibm"] = gpu_error_vs_oracle(sim_m, u0m, Xm, steps_m + 2, "ibm")
+    out["error_vs_fp64"] = err
     return out
 
 
-def gpu_error_vs_oracle(sim, u0, X, steps):
+def gpu_error_vs_oracle(sim, u0, X, steps, bc):
     """The same sample on the GPU in FP32 and FP16 storage: relative L2 of the
     velocity over fluid nodes and relative error of the fluid dissipation
     against the FP64 oracle state (the metric's error column)."""
@@ -327,17 +388,20 @@ def gpu_error_vs_oracle(sim, u0, X, steps):
     fluid = sim.fluid_mask()
     res = {"steps": steps}
     for name, store in (("f32", lbm.STORE_F32), ("f16s", lbm.STORE_F16S)):
-        lat = lbm.Lattice(lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store, bc=lbm.BC_IBB,
+        lat = lbm.Lattice(lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store,
+                                     bc=lbm.BC_IBB if bc == "ibb" else lbm.BC_IBM, ibm_retraction=IBM_RD,
                                      max_particles=len(X), max_radius=RADIUS))
         lat.set_fields(u0)
         lat.set_particles(X, RADIUS, rho_p=RHO_P, mode=lbm.RELEASE, motion=lbm.MOTION_FREE)
         lat.step(steps)
         ug, _ = lat.get_fields()
         sg = lat.stats(nbins=0)
+        Xg, Ug, _ = lat.get_particles()
         lat.close()
         du = (ug.astype(np.float64) - uo)[:, fluid]
         res[name] = {"u_rel_l2": float(np.linalg.norm(du) / np.linalg.norm(uo[:, fluid])),
-                     "eps_fluid_rel": float(abs(sg["eps_fluid"] - so["eps_fluid"]) / so["eps_fluid"])}
+                     "eps_fluid_rel": float(abs(sg["eps_fluid"] - so["eps_fluid"]) / so["eps_fluid"]),
+                     "particle_U_rel_l2": float(np.linalg.norm(Ug - P.U) / np.linalg.norm(P.U))}
     return res
 
 
@@ -441,6 +505,12 @@ def main():
     head_name = "-".join(variants[0])
     head = results[head_name]
     hb, hs = variants[0]
+    N = n ** 3
+    for (bc, st), name in zip(variants, [f"{b}-{s_}" for b, s_ in variants]):
+        r = results[name]
+        b = step_bytes(bc, 4 if st == "f32" else 2, N, N - r["solid_nodes"], r["links"], r["support_nodes"])
+        r["step_alg_bytes"] = b
+        r["step_roofline_frac"] = b / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     out = {
         "metric": METRIC,
         "value": round(head["mlups"], 1),
@@ -471,6 +541,12 @@ def main():
                      "kernel": "k_stream_collide_seg" if hs == "f16s" and n % 2 == 0 else "k_stream_collide",
                      "alg_bytes_per_launch": head["alg_bytes"],
                      "avg_launch_ms": round(head["kernel_avg_ms"], 4)},
+        "step_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                          "alg_bytes_per_step": head["step_alg_bytes"],
+                          "achieved": round(head["step_alg_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9, 1),
+                          "frac": round(head["step_roofline_frac"], 4),
+                          "model": "whole step: fused stream-collide over the fluid nodes plus the boundary "
+                                   "treatment's algorithmic bytes (bench.step_bytes)"},
         "stream_copy": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},

@@ -140,6 +140,35 @@ int lbm_sync(lbm_ctx* ctx);
 /* Number of completed time steps since the last lbm_set_fields(). */
 int lbm_step_count(const lbm_ctx* ctx, int64_t* step);
 
+/* ---- Checkpoint and restart ---------------------------------------------
+ * The paper starts one pipe run from the velocity field of another to save
+ * computing time (Sec. 2.2.1). A state blob holds everything later steps
+ * depend on: the populations of the current step, the step counter, the
+ * particle state in FP64 (centres, velocities, angular velocities, radii,
+ * densities, motion mode), the momentum of the nodes covered or uncovered
+ * in the previous step, the Kempe inner momentum, the forces of the last
+ * update and, with the immersed boundary, the support and spread force of
+ * the last collision (the velocity extraction of the current step reads
+ * them). The boundary geometry is rebuilt from the centres on restore, with
+ * the kernels the step uses, so a restored context continues bit for bit as
+ * the original would. Not in the blob: the pipe budget sums, an attached
+ * corrector, profiling counters, latched errors. The blob is host memory in
+ * the library's own layout (native byte order), valid only for a context
+ * with the same configuration.
+ *
+ * lbm_state_size: bytes of the current state (depends on the particle count
+ *   and, with the immersed boundary, the support size). Sync.
+ * lbm_get_state: copies the state to host (bytes >= lbm_state_size()).
+ *   Sync. Errors: LBM_E_ARG (NULL), LBM_E_SIZE (bytes too small).
+ * lbm_set_state: restores a blob of lbm_get_state() from a context with an
+ *   identical configuration (another or the same context). Sync. Errors:
+ *   LBM_E_ARG (NULL, not a state blob, another configuration, a particle
+ *   block that lbm_set_particles would reject), LBM_E_SIZE (bytes shorter
+ *   than the blob); the context is unchanged on these errors. */
+int lbm_state_size(lbm_ctx* ctx, size_t* bytes);
+int lbm_get_state(lbm_ctx* ctx, void* host, size_t bytes);
+int lbm_set_state(lbm_ctx* ctx, const void* host, size_t bytes);
+
 /* lbm_set_particles() modes. LBM_RELEASE follows Sec. 3.1: each particle
  * starts with the fluid velocity averaged over its volume (weighted by the
  * cell solid fraction) and zero angular velocity, and the populations at its
@@ -162,6 +191,9 @@ enum { LBM_MOTION_FREE = 0, LBM_MOTION_FIXED = 1, LBM_MOTION_PRESCRIBED = 2 };
  * Rebuilds the boundary geometry. Sync. Errors: LBM_E_ARG, LBM_E_SIZE. */
 int lbm_set_particles(lbm_ctx* ctx, int32_t np, const double* x, const double* u, const double* omega,
                       const double* radius, const double* rho_p, int32_t mode, int32_t motion);
+
+/* Number of particles set (lbm_set_particles, lbm_set_state). */
+int lbm_particle_count(const lbm_ctx* ctx, int32_t* np);
 
 /* Current particle state to host [np][3] arrays (any may be NULL). Sync. */
 int lbm_get_particles(lbm_ctx* ctx, double* x, double* u, double* omega);
@@ -188,6 +220,12 @@ int lbm_get_links(lbm_ctx* ctx, int64_t cap, int32_t* node, int32_t* dir, int32_
  * interpolated bounce-back) and boundary links; either pointer may be NULL.
  * Sync. */
 int lbm_geometry_counts(lbm_ctx* ctx, int64_t* solid_nodes, int64_t* links);
+
+/* Immersed boundary: nodes of the current support set (the union of the
+ * marker stencils and of the Kempe cells of every sphere, Sec. 2.1 and
+ * Sec. 3.1; with a pipe wall its marker stencils too) and the nodes that
+ * more than one sphere's support holds. Zero for other boundaries. Sync. */
+int lbm_ibm_support(lbm_ctx* ctx, int64_t* support_nodes, int64_t* shared_nodes);
 
 /* Statistics of the current snapshot (Sec. 3.2). Every sum is FP64, reduced
  * in a fixed order (bit-reproducible). Means are over all N nodes (raw and
@@ -278,7 +316,7 @@ int lbm_pipe_budget_read(lbm_ctx* ctx, int32_t* nbins, int64_t* snapshots, doubl
 #define LBM_SPECTRUM_MAX_SHELL 4096
 
 /* Three-dimensional spectra of the kinetic energy and of its dissipation
- * rate of the current field (Sec. 4.2, Figs. 11-12). With
+ * rate of the current field (Sec. 3.2.1). With
  * u^(k) = (1/N) sum_x u(x) exp(-2 pi i k.x / L), k in integer wavenumbers of
  * the periodic box (k_max = n/2 along an axis of n nodes),
  *   E[s] = 1/2 sum over round(|k|) = s of |u^(k)|^2,  D[s] = 2 nu s^2 E[s],

@@ -203,7 +203,7 @@ struct Plan {
   uint32_t link_cap, wl_count;
   // immersed boundary
   size_t ib_bits[2], ib_rank[2], ib_count, ib_fib[2], ib_shared, ib_list, ib_us, ib_bsum, ib_dirs, ib_rowbits,
-      ib_fcount, ib_fslot, ib_wmark, ib_wdF, ib_wsup;
+      ib_fcount, ib_fslot, ib_wmark, ib_wdF, ib_wsup, ib_sh_rank, ib_sh_count, ib_sh_slot, ib_sh_acc;
   uint32_t s_cap, fcap, n_markers, n_wall, wall_support;
   int side;
   size_t total;
@@ -297,6 +297,10 @@ Plan plan(const lbm_config& c) {
     }
     p.ib_count = take(2 * sizeof(uint32_t));
     p.ib_shared = take(words * 4);
+    p.ib_sh_rank = take(words * 4);
+    p.ib_sh_count = take(sizeof(uint32_t));
+    p.ib_sh_slot = take((size_t)p.s_cap * 4);
+    p.ib_sh_acc = take((size_t)3 * p.s_cap * 8);
     p.ib_list = take((size_t)p.s_cap * 4);
     p.ib_us = take((size_t)p.s_cap * 16);
     p.ib_bsum = take((words / 1024 + 2) * 4);
@@ -599,6 +603,11 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
       m.count[b] = (uint32_t*)(base + p.ib_count) + b;
     }
     m.shared = (uint32_t*)(base + p.ib_shared);
+    m.sh_rank = (uint32_t*)(base + p.ib_sh_rank);
+    m.sh_count = (uint32_t*)(base + p.ib_sh_count);
+    m.sh_slot = (uint32_t*)(base + p.ib_sh_slot);
+    m.sh_acc = (unsigned long long*)(base + p.ib_sh_acc);
+    m.sh_cap = p.s_cap;
     m.list = (uint32_t*)(base + p.ib_list);
     m.us = (float4*)(base + p.ib_us);
     m.block_sums = (uint32_t*)(base + p.ib_bsum);
@@ -673,6 +682,11 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.np = 0;
     e = zero_particle_accumulators(c);
   }
+  if (e == hipSuccess && cfg->bc == LBM_BC_IBM) {
+    // the forcing passes keep these zero between passes
+    e = hipMemsetAsync(c.ibm.sh_acc, 0, (size_t)3 * c.ibm.sh_cap * 8, c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c.ibm.sh_count, 0, sizeof(uint32_t), c.stream);
+  }
   if (e == hipSuccess && cfg->bc == LBM_BC_IBM && c.ibm.n_wall == 0) {
     // empty support until particles are set
     for (int b = 0; b < 2 && e == hipSuccess; ++b) {
@@ -728,6 +742,12 @@ int lbm_set_fields(lbm_ctx* h, const float* u, const float* rho) {
   return LBM_OK;
 }
 
+extern "C++" {
+namespace {
+hipError_t ibm_marker_setup(Ctx& c, double r);
+}  // namespace
+}  // extern "C++"
+
 int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, const double* omega,
                       const double* radius, const double* rho_p, int32_t mode, int32_t motion) {
   if (!h) return LBM_E_ARG;
@@ -764,6 +784,14 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
         W[3 * i + k] = omega[3 * i + k];
       }
     }
+  }
+  // The immersed boundary lays out one marker set for all spheres; checked
+  // before anything of the context changes, so a rejected call leaves it as
+  // it was.
+  if (cfg.bc == LBM_BC_IBM && np > 0) {
+    for (int32_t i = 1; i < np; ++i)
+      if (R[i] != R[0]) return LBM_E_ARG;
+    if (!(R[0] - cfg.ibm_retraction > 1.0)) return LBM_E_ARG;
   }
   c.np = np;
   c.motion = motion;
@@ -802,26 +830,272 @@ int lbm_set_particles(lbm_ctx* h, int32_t np, const double* x, const double* u, 
   if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[0], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
   if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[1], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
   if (e == hipSuccess && cfg.bc == LBM_BC_IBB) e = launch_links_build(c, c.ibb.owner[0], c.P.X[0]);
-  std::vector<double> dirs;
   if (e == hipSuccess && cfg.bc == LBM_BC_IBM) {
     IbmBufs& m = c.ibm;
     m.cur = m.last = 0;
     m.n_markers = 0;
-    if (np > 0) {
-      for (int32_t i = 1; i < np; ++i)
-        if (R[i] != R[0]) return LBM_E_ARG;  // one marker layout for all spheres
-      m.r_l = R[0] - cfg.ibm_retraction;
-      if (!(m.r_l > 1.0)) return LBM_E_ARG;
-      m.n_markers = marker_count(m.r_l);
-      m.dV = marker_volume(m.r_l, m.n_markers);
-      fibonacci_dirs(m.n_markers, dirs);
-      e = hipMemcpyAsync(m.dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, c.stream);
-    }
+    if (np > 0) e = ibm_marker_setup(c, R[0]);
     if (e == hipSuccess) e = launch_ibm_support_build(c, 0, c.P.X[0]);
     if (e == hipSuccess) e = ibm_inner_momentum_init(c);
   }
   if (e != hipSuccess) return LBM_E_HIP;
   return drain_errors(c);
+}
+
+extern "C++" {
+namespace {
+
+// ---- checkpoint blob ------------------------------------------------------
+// Layout (native byte order): StateHeader, the populations of the current
+// step (exactly Q N element bytes), the particle block (X, U, Omega, F_rc,
+// T_rc, F_h, T_h, F_c, I_u, I_L as [np][3] FP64, then r and rho_p as [np]),
+// then, for the immersed boundary after the first step, the support of the
+// last collision: bitmask and rank words, and the spread force of its
+// slots component by component ([3][count] FP32).
+constexpr char kStateMagic[8] = {'L', 'B', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t kStateVersion = 1;
+constexpr int kStateVec3 = 10;  // [np][3] arrays in the particle block
+
+struct StateHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  lbm_config cfg;      // field by field, padding zeroed
+  int64_t step;
+  int32_t np, motion;
+  uint64_t pop_bytes;  // Q N element bytes
+  uint64_t ibm_words;  // support bitmask words saved (0: no support section)
+  uint32_t ibm_count;  // slots of the saved support
+  uint32_t reserved;
+};
+
+lbm_config normalized(const lbm_config& a) {
+  lbm_config z;
+  memset(&z, 0, sizeof(z));
+  z.nx = a.nx; z.ny = a.ny; z.nz = a.nz;
+  z.tau = a.tau;
+  z.s_e = a.s_e; z.s_eps = a.s_eps; z.s_q = a.s_q; z.s_pi = a.s_pi; z.s_m = a.s_m;
+  for (int k = 0; k < 3; ++k) z.body_force[k] = a.body_force[k];
+  z.bc = a.bc; z.ibb_max_order = a.ibb_max_order;
+  z.ibm_retraction = a.ibm_retraction; z.ibm_iters = a.ibm_iters;
+  z.store = a.store; z.wall = a.wall;
+  z.pipe_radius = a.pipe_radius; z.pipe_cx = a.pipe_cx; z.pipe_cy = a.pipe_cy;
+  z.max_particles = a.max_particles; z.max_radius = a.max_radius;
+  z.coll_restitution = a.coll_restitution; z.coll_tc_steps = a.coll_tc_steps;
+  z.lattice = a.lattice; z.tau_bulk = a.tau_bulk;
+  return z;
+}
+
+size_t pop_exact_bytes(const lbm_config& c) {
+  return (size_t)lattice_q(c) * n_nodes(c) * (c.store == LBM_STORE_F32 ? 4 : 2);
+}
+
+size_t particle_block_bytes(int32_t np) { return (size_t)np * (3 * kStateVec3 + 2) * sizeof(double); }
+
+// The immersed boundary saves the support and spread force of the last
+// collision, which the velocity extraction of the current step reads.
+bool state_has_support(const Ctx& c) { return c.cfg.bc == LBM_BC_IBM && c.step > 0; }
+
+size_t state_bytes(const StateHeader& h) {
+  return sizeof(StateHeader) + h.pop_bytes + particle_block_bytes(h.np) + h.ibm_words * 8 +
+         (size_t)3 * h.ibm_count * 4;
+}
+
+int state_header(Ctx& c, StateHeader& h) {
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, kStateMagic, sizeof(h.magic));
+  h.version = kStateVersion;
+  h.header_bytes = (uint32_t)sizeof(StateHeader);
+  h.cfg = normalized(c.cfg);
+  h.step = c.step;
+  h.np = std::max(c.np, 0);
+  h.motion = c.motion;
+  h.pop_bytes = pop_exact_bytes(c.cfg);
+  if (state_has_support(c)) {
+    uint32_t cnt = 0;
+    if (hipMemcpyAsync(&cnt, c.ibm.count[c.ibm.last], 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+    const int st = drain_errors(c);
+    if (st != LBM_OK) return st;
+    h.ibm_words = mask_words(c.dims.N);
+    h.ibm_count = std::min(cnt, c.ibm.s_cap);
+    return LBM_OK;
+  }
+  return drain_errors(c);
+}
+
+// Particle block arrays in blob order.
+void particle_arrays(Ctx& c, double* v[kStateVec3 + 2]) {
+  const int pc = c.pcur;
+  double* a[kStateVec3 + 2] = {c.P.X[pc], c.P.U[pc], c.P.Om[pc], c.P.F_rc, c.P.T_rc, c.P.F_h,
+                               c.P.T_h,   c.P.F_c,   c.P.Iu,     c.P.IL,   c.P.r,    c.P.rho};
+  for (int k = 0; k < kStateVec3 + 2; ++k) v[k] = a[k];
+}
+
+// Marker layout of the immersed boundary for spheres of radius r.
+hipError_t ibm_marker_setup(Ctx& c, double r) {
+  IbmBufs& m = c.ibm;
+  m.r_l = r - c.cfg.ibm_retraction;
+  m.n_markers = marker_count(m.r_l);
+  m.dV = marker_volume(m.r_l, m.n_markers);
+  std::vector<double> dirs;
+  fibonacci_dirs(m.n_markers, dirs);
+  hipError_t e =
+      hipMemcpyAsync(m.dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, c.stream);
+  // the host vector must outlive the copy
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  return e;
+}
+
+}  // namespace
+}  // extern "C++"
+
+int lbm_state_size(lbm_ctx* h, size_t* bytes) {
+  if (!h || !bytes) return LBM_E_ARG;
+  StateHeader hd;
+  const int st = state_header(h->c, hd);
+  if (st != LBM_OK) return st;
+  *bytes = state_bytes(hd);
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* h, void* host, size_t bytes) {
+  if (!h || !host) return LBM_E_ARG;
+  Ctx& c = h->c;
+  StateHeader hd;
+  int st = state_header(c, hd);
+  if (st != LBM_OK) return st;
+  if (bytes < state_bytes(hd)) return LBM_E_SIZE;
+  char* out = (char*)host;
+  memcpy(out, &hd, sizeof(hd));
+  size_t off = sizeof(hd);
+  hipError_t e = hipMemcpyAsync(out + off, c.f_cur, hd.pop_bytes, hipMemcpyDeviceToHost, c.stream);
+  off += hd.pop_bytes;
+  double* v[kStateVec3 + 2];
+  particle_arrays(c, v);
+  const size_t vb = (size_t)hd.np * 3 * sizeof(double), sb = (size_t)hd.np * sizeof(double);
+  for (int k = 0; k < kStateVec3 + 2 && e == hipSuccess; ++k) {
+    const size_t b = k < kStateVec3 ? vb : sb;
+    if (b) e = hipMemcpyAsync(out + off, v[k], b, hipMemcpyDeviceToHost, c.stream);
+    off += b;
+  }
+  if (e == hipSuccess && hd.ibm_words) {
+    const IbmBufs& m = c.ibm;
+    const int b = m.last;
+    e = hipMemcpyAsync(out + off, m.bits[b], hd.ibm_words * 4, hipMemcpyDeviceToHost, c.stream);
+    off += hd.ibm_words * 4;
+    if (e == hipSuccess) e = hipMemcpyAsync(out + off, m.rank[b], hd.ibm_words * 4, hipMemcpyDeviceToHost, c.stream);
+    off += hd.ibm_words * 4;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      if (hd.ibm_count)
+        e = hipMemcpyAsync(out + off, m.fib[b] + (size_t)k * m.s_cap, (size_t)hd.ibm_count * 4,
+                           hipMemcpyDeviceToHost, c.stream);
+      off += (size_t)hd.ibm_count * 4;
+    }
+  }
+  if (e != hipSuccess) return LBM_E_HIP;
+  return drain_errors(c);
+}
+
+int lbm_set_state(lbm_ctx* h, const void* host, size_t bytes) {
+  if (!h || !host || bytes < sizeof(StateHeader)) return LBM_E_ARG;
+  Ctx& c = h->c;
+  const lbm_config& cfg = c.cfg;
+  StateHeader hd;
+  memcpy(&hd, host, sizeof(hd));
+  if (memcmp(hd.magic, kStateMagic, sizeof(hd.magic)) != 0 || hd.version != kStateVersion ||
+      hd.header_bytes != sizeof(StateHeader))
+    return LBM_E_ARG;
+  const lbm_config want = normalized(cfg);
+  if (memcmp(&hd.cfg, &want, sizeof(want)) != 0) return LBM_E_ARG;
+  if (hd.step < 0 || hd.np < 0 || hd.np > (has_particles(cfg) ? cfg.max_particles : 0)) return LBM_E_ARG;
+  if (hd.motion != LBM_MOTION_FREE && hd.motion != LBM_MOTION_FIXED && hd.motion != LBM_MOTION_PRESCRIBED)
+    return LBM_E_ARG;
+  if (hd.pop_bytes != pop_exact_bytes(cfg)) return LBM_E_ARG;
+  const bool support = cfg.bc == LBM_BC_IBM && hd.step > 0;
+  if (support ? (hd.ibm_words != mask_words(c.dims.N) || hd.ibm_count > c.ibm.s_cap)
+              : (hd.ibm_words != 0 || hd.ibm_count != 0))
+    return LBM_E_ARG;
+  if (bytes < state_bytes(hd)) return LBM_E_SIZE;
+  const char* in = (const char*)host;
+  // the particle block is checked like lbm_set_particles' arguments
+  const int32_t np = hd.np;
+  const double* pb = (const double*)(in + sizeof(hd) + hd.pop_bytes);
+  std::vector<double> blk((size_t)np * (3 * kStateVec3 + 2));
+  if (np) memcpy(blk.data(), pb, blk.size() * sizeof(double));
+  const double L[3] = {(double)cfg.nx, (double)cfg.ny, (double)cfg.nz};
+  const double* Xb = blk.data();
+  const double* Rb = blk.data() + (size_t)np * 3 * kStateVec3;
+  for (size_t i = 0; i < (size_t)np * 3 * kStateVec3; ++i)
+    if (!isfinite(blk[i])) return LBM_E_ARG;
+  for (int32_t i = 0; i < np; ++i) {
+    const double r = Rb[i], rho = Rb[np + i];
+    if (!(r > 0.0) || r > cfg.max_radius || !(rho > 0.0) || !isfinite(rho)) return LBM_E_ARG;
+    for (int k = 0; k < 3; ++k)
+      if (!(Xb[3 * i + k] >= 0.0 && Xb[3 * i + k] < L[k])) return LBM_E_ARG;
+    if (cfg.bc == LBM_BC_IBM && r != Rb[0]) return LBM_E_ARG;
+  }
+  if (cfg.bc == LBM_BC_IBM && np > 0 && !(Rb[0] - cfg.ibm_retraction > 1.0)) return LBM_E_ARG;
+
+  // Restore: populations, particle state, then the geometry of the centres
+  // (built as the step builds it) and the last collision's support.
+  c.step = hd.step;
+  c.np = np;
+  c.motion = hd.motion;
+  c.pcur = 0;
+  c.ocur = 0;
+  size_t off = sizeof(hd);
+  hipError_t e = hipMemcpyAsync(c.f_cur, in + off, hd.pop_bytes, hipMemcpyHostToDevice, c.stream);
+  off += hd.pop_bytes;
+  if (e == hipSuccess && has_particles(cfg)) e = zero_particle_accumulators(c);
+  double* v[kStateVec3 + 2];
+  particle_arrays(c, v);
+  const size_t vb = (size_t)np * 3 * sizeof(double), sb = (size_t)np * sizeof(double);
+  for (int k = 0; k < kStateVec3 + 2 && e == hipSuccess; ++k) {
+    const size_t b = k < kStateVec3 ? vb : sb;
+    if (b) e = hipMemcpyAsync(v[k], in + off, b, hipMemcpyHostToDevice, c.stream);
+    off += b;
+  }
+  if (cfg.bc != LBM_BC_NONE && cfg.wall == LBM_WALL_NONE) {
+    if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[0]);
+    if (e == hipSuccess) e = launch_owner_fill(c, c.ibb.owner[1]);
+    if (e == hipSuccess) e = launch_owner_set(c, c.ibb.owner[0], c.P.X[0]);
+    if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[0], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
+    if (e == hipSuccess && np > 0) e = hipMemcpyAsync(c.P.Xown[1], c.P.X[0], vb, hipMemcpyDeviceToDevice, c.stream);
+    if (e == hipSuccess && cfg.bc == LBM_BC_IBB) e = launch_links_build(c, c.ibb.owner[0], c.P.X[0]);
+  }
+  if (e == hipSuccess && cfg.bc == LBM_BC_IBM) {
+    IbmBufs& m = c.ibm;
+    m.cur = m.last = 0;
+    if (cfg.wall == LBM_WALL_NONE) {
+      m.n_markers = 0;
+      if (np > 0) e = ibm_marker_setup(c, Rb[0]);
+      if (e == hipSuccess) e = launch_ibm_support_build(c, 0, c.P.X[0]);
+    }
+    if (e == hipSuccess && support) {
+      const size_t wb = hd.ibm_words * 4;
+      e = hipMemcpyAsync(m.bits[1], in + off, wb, hipMemcpyHostToDevice, c.stream);
+      off += wb;
+      if (e == hipSuccess) e = hipMemcpyAsync(m.rank[1], in + off, wb, hipMemcpyHostToDevice, c.stream);
+      off += wb;
+      if (e == hipSuccess) e = hipMemcpyAsync(m.count[1], &hd.ibm_count, 4, hipMemcpyHostToDevice, c.stream);
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        if (hd.ibm_count)
+          e = hipMemcpyAsync(m.fib[1] + (size_t)k * m.s_cap, in + off, (size_t)hd.ibm_count * 4,
+                             hipMemcpyHostToDevice, c.stream);
+        off += (size_t)hd.ibm_count * 4;
+      }
+      m.last = 1;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return LBM_E_HIP;
+  return drain_errors(c);
+}
+
+int lbm_particle_count(const lbm_ctx* h, int32_t* np) {
+  if (!h || !np) return LBM_E_ARG;
+  *np = std::max(h->c.np, 0);
+  return LBM_OK;
 }
 
 int lbm_get_particles(lbm_ctx* h, double* x, double* u, double* omega) {
@@ -944,6 +1218,23 @@ int lbm_geometry_counts(lbm_ctx* h, int64_t* solid_nodes, int64_t* links) {
   return drain_errors(c);
 }
 
+int lbm_ibm_support(lbm_ctx* h, int64_t* support_nodes, int64_t* shared_nodes) {
+  if (!h) return LBM_E_ARG;
+  Ctx& c = h->c;
+  uint32_t v[2] = {0, 0};
+  if (c.cfg.bc == LBM_BC_IBM) {
+    if (hipMemcpyAsync(&v[0], c.ibm.count[c.ibm.cur], 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+    if (c.np > 0 && hipMemcpyAsync(&v[1], c.ibm.sh_count, 4, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return LBM_E_HIP;
+  }
+  const int st = drain_errors(c);
+  if (st != LBM_OK) return st;
+  if (support_nodes) *support_nodes = v[0];
+  if (shared_nodes) *shared_nodes = v[1];
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* h, int32_t nsteps) {
   if (!h || nsteps < 0) return LBM_E_ARG;
   Ctx& c = h->c;
@@ -987,6 +1278,7 @@ int lbm_get_fields(lbm_ctx* h, float* u, float* rho) {
   return drain_errors(c);
 }
 
+extern "C++" {
 namespace {
 
 // Statistics and corrector scratch in the idle population buffer (at least
@@ -1041,6 +1333,7 @@ bool corrector_fits(const Ctx& c) {
 }
 
 }  // namespace
+}  // extern "C++"
 
 int lbm_stats(lbm_ctx* h, int32_t nbins, double bin_width, lbm_stats_t* out, double* hist) {
   if (!h || !out || nbins < 0 || nbins > LBM_STATS_MAX_BINS || !(bin_width > 0.0)) return LBM_E_ARG;

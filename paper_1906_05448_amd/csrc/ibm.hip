@@ -10,10 +10,13 @@
 //             of its marker stencils) in LDS: u = u* + f_IB/(2 rho);
 //             markers interpolate U_l, dF_l = 2 (U_d - U_l) (reference
 //             density 1, half-force velocity), then spread dF_l delta dV
-//             into separate LDS accumulators with LDS float atomics; the
-//             result goes back to the slot force array with plain adds, or
-//             global atomics at nodes another sphere's support shares. All
-//             markers of a pass read the same u (one launch per pass).
+//             into LDS fixed-point sums. Nodes of this sphere alone get the
+//             sum added to their slot force in place; at nodes another
+//             sphere's support shares, the sums go to separate exact 64-bit
+//             accumulators that a fold kernel adds to the slot forces after
+//             the pass. So every marker of a pass reads the velocity of the
+//             end of the previous pass, whatever the order the workgroups
+//             run in, and the result does not depend on that order.
 //   kempe     sum alpha u and sum alpha (x - X) x u over the cells with
 //             solid fraction alpha > 0, per sphere, in FP64
 //   dense     the fused stream + collide adds f_IB at support nodes
@@ -216,8 +219,8 @@ __device__ __forceinline__ bool support_slot(const uint32_t* bits, const uint32_
 }
 
 // Per sphere: global slot of every forcing-support node, in box raster order,
-// with bit 31 set where another support shares the node (slots stay below
-// 2^31). A box row (side <= 32 nodes) touches at most two words of the
+// or, where another support shares the node, bit 31 set and the node's index
+// among the shared nodes (slots and indices stay below 2^31). A box row (side <= 32 nodes) touches at most two words of the
 // support bitmask per contiguous x segment, and there are two segments when
 // the row wraps around x. Those words, their ranks and their shared bits are
 // loaded once per row, all together, and every slot of the row is formed
@@ -227,8 +230,8 @@ constexpr uint32_t kSlotShared = 0x80000000u;
 __global__ void __launch_bounds__(kBlock)
 k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint32_t* __restrict__ bits,
             const uint32_t* __restrict__ rank, const uint32_t* __restrict__ shared,
-            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
-            uint32_t* __restrict__ fslot) {
+            const uint32_t* __restrict__ sh_rank, const uint32_t* __restrict__ rowbits,
+            const uint32_t* __restrict__ fcount, uint32_t fcap, uint32_t* __restrict__ fslot) {
   const int rows = side * side;
   const int p = blockIdx.x;
   int lo[3];
@@ -246,7 +249,7 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
       const uint32_t rowbase = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx;
       const int xa = wrap1(lo[0] + (__ffs(m) - 1), d.nx), xb = wrap1(lo[0] + (31 - __clz(m)), d.nx);
       // words of the first node of each segment and the one after it
-      uint32_t w[4], wb[4], wr[4], ws[4];
+      uint32_t w[4], wb[4], wr[4], ws[4], wq[4];
       w[0] = (rowbase + (uint32_t)xa) >> 5;
       w[2] = rowbase >> 5;  // wrapped segment starts at x = 0
       const uint32_t last1 = xa <= xb ? (rowbase + (uint32_t)xb) >> 5 : (rowbase + (uint32_t)d.nx - 1u) >> 5;
@@ -260,6 +263,7 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
         wb[k] = use ? bits[w[k]] : 0u;
         wr[k] = use ? rank[w[k]] : 0u;
         ws[k] = use ? shared[w[k]] : 0u;
+        wq[k] = use ? sh_rank[w[k]] : 0u;
       }
       while (m) {
         const int lx = __ffs(m) - 1;
@@ -270,8 +274,15 @@ k_ibm_slots(const double* __restrict__ X, int R_b, int side, Dims d, const uint3
         const uint32_t word = k == 0 ? wb[0] : (k == 1 ? wb[1] : (k == 2 ? wb[2] : wb[3]));
         const uint32_t rk = k == 0 ? wr[0] : (k == 1 ? wr[1] : (k == 2 ? wr[2] : wr[3]));
         const uint32_t sw = k == 0 ? ws[0] : (k == 1 ? ws[1] : (k == 2 ? ws[2] : ws[3]));
-        const uint32_t slot = rk + __popc(word & ((1u << (n & 31u)) - 1u));
-        if (j < cap) fslot[(size_t)p * fcap + j] = slot | (((sw >> (n & 31u)) & 1u) ? kSlotShared : 0u);
+        const uint32_t below = (1u << (n & 31u)) - 1u;
+        uint32_t entry;
+        if ((sw >> (n & 31u)) & 1u) {
+          const uint32_t sq = k == 0 ? wq[0] : (k == 1 ? wq[1] : (k == 2 ? wq[2] : wq[3]));
+          entry = kSlotShared | (sq + __popc(sw & below));
+        } else {
+          entry = rk + __popc(word & below);
+        }
+        if (j < cap) fslot[(size_t)p * fcap + j] = entry;
         ++j;
       }
     }
@@ -314,29 +325,53 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // One 1024-thread workgroup per sphere, MPT markers per thread.
 // LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 12
 // bytes holding first the staged velocities (float3 per node) and, once every
-// marker has interpolated, the spread sums of one velocity component (int64
-// per node; the three components are spread one after the other), then fcap
-// u32 (the nodes' slots with their shared flag, kept for the write-back).
-// About 72 KB for r = 8, so two spheres share a compute unit and one's
-// memory trips overlap the other's LDS work.
+// marker has interpolated, the spread sums of the three components (int32
+// per component and node), then fcap u32 (the nodes' slot-list entries, kept
+// for the write-back). About 64 KB for r = 8, so two spheres share a compute
+// unit and one's memory trips overlap the other's LDS work.
 //
-// The spread sums are 64-bit fixed point in units of 2^-50: LDS integer
-// atomics run at about the rate of plain LDS accesses, while LDS float
-// atomics measured about 25 times slower on gfx950, and integer sums are
-// exact, so a node's total does not depend on the order in which markers
-// land. |sum| < 2^13 per node and pass holds with a wide margin: the weights
-// a node receives sum to O(1) and |dF| < 1.4 below the Mach limit that the
-// collision kernel latches as unstable.
+// The spread sums are 32-bit fixed point in units of 2^-e with a scale
+// exponent e per sphere and pass, chosen from the largest |dF| of the
+// sphere's markers so that no node sum can reach 2^31: LDS integer atomics
+// run at about the rate of plain LDS accesses (float atomics measured about
+// 25 times slower on gfx950), integer sums are exact, so a node's total does
+// not depend on the order in which markers land, and the per-sphere scale
+// keeps the resolution relative to the forces of the pass (a few 1e-9 of the
+// largest |dF|) however weak or strong the flow. A node's weights from one
+// sphere's markers add up to about 1/2 (one marker per unit area of the
+// surface, the delta integrating to one over the tangent plane and to at
+// most phi(0) = 1/2 across it); kSpreadBound = 8 covers that with margin.
+// At shared nodes the sums are rescaled to the common units 2^-50 and added
+// with 64-bit atomics: exact, so the order of the spheres does not matter
+// either.
 constexpr int kPassBlock = 1024;
 constexpr int kStage = 3;  // support nodes per thread per staging round
-constexpr int kWrite = 5;  // support nodes per thread per write-back round
-constexpr double kFixScale = 0x1p50;
-constexpr double kFixUnit = 0x1p-50;
+constexpr int kWrite = 4;  // support nodes per thread per write-back round
+constexpr float kSpreadBound = 8.0f;
+constexpr int kShUnitExp = 50;  // shared accumulators: units of 2^-50
 
-__device__ __forceinline__ unsigned long long to_fix(float v) {
-  return (unsigned long long)(long long)((double)v * kFixScale);
+__device__ __forceinline__ int spread_exponent(float max_dF, float dV) {
+  const float B = max_dF * dV * kSpreadBound;
+  if (!(B > 0.0f)) return kShUnitExp;  // no force (or non-finite: the collision latches it)
+  int ex;
+  (void)frexpf(B, &ex);                // B < 2^ex
+  return min(kShUnitExp, max(0, 30 - ex));
 }
-__device__ __forceinline__ float from_fix(unsigned long long a) { return (float)((double)(long long)a * kFixUnit); }
+
+// Largest value of a non-negative float over the block (every thread gets it).
+__device__ __forceinline__ float block_max_nonneg(float v) {
+  __shared__ uint32_t part[kPassBlock / 64];
+  uint32_t b = __float_as_uint(v);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) b = max(b, (uint32_t)__shfl_xor((int)b, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = b;
+  __syncthreads();
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < kPassBlock / 64; ++w) m = max(m, part[w]);
+  __syncthreads();
+  return __uint_as_float(m);
+}
 
 template <int MPT>
 // One marker per thread: 8 waves per SIMD (<= 64 VGPRs), two workgroups per
@@ -345,14 +380,16 @@ __global__ void __launch_bounds__(kPassBlock, MPT == 1 ? 8 : 4)
 k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om,
            const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
-           const uint32_t* __restrict__ fslot, const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap, double* __restrict__ F_ib,
-           double* __restrict__ T_ib, int first) {
+           const uint32_t* __restrict__ fslot, const uint32_t* __restrict__ sh_slot, uint32_t sh_cap,
+           const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap,
+           unsigned long long* __restrict__ sh_acc, double* __restrict__ F_ib, double* __restrict__ T_ib,
+           int first) {
   extern __shared__ uint32_t lds[];
   const int rows = side * side;
   uint32_t* rb = lds;
   uint32_t* rp = rb + rows;
   float* uj = (float*)(rp + rows);
-  unsigned long long* acc = (unsigned long long*)(rp + rows);  // rows * 8 bytes in: 8-byte aligned
+  int* acc = (int*)(rp + rows);  // aliases uj once every marker has interpolated
   uint32_t* sl = (uint32_t*)(uj + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
@@ -377,8 +414,9 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   // was built; skip the sphere rather than index past the buffers.
   if (base > fcap || base != cnt) return;
   __syncthreads();
-  // Stage u = u* + f_IB / (2 rho): all loads of a round are issued before
-  // any is used, so a round costs two dependent trips to memory.
+  // Stage u = u* + f_IB / (2 rho) as the previous pass left it: all loads of
+  // a round are issued before any is used. A shared node's slot comes from
+  // the shared-node table.
   for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
     uint32_t w[kStage], s[kStage];
     float4 v[kStage];
@@ -387,7 +425,11 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     for (int i = 0; i < kStage; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
       w[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
-      s[i] = w[i] & ~kSlotShared;
+    }
+#pragma unroll
+    for (int i = 0; i < kStage; ++i) {
+      const uint32_t q = w[i] & ~kSlotShared;
+      s[i] = !(w[i] & kSlotShared) ? w[i] : (w[i] != 0xFFFFFFFFu && q < sh_cap ? sh_slot[q] : 0xFFFFFFFFu);
     }
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
@@ -412,13 +454,13 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     }
   }
   __syncthreads();
-  // interpolate and form the marker forces; every marker reads u before the
-  // accumulators replace it
+  // interpolate and form the marker forces
   const double Up[3] = {U[3 * p], U[3 * p + 1], U[3 * p + 2]};
   const double Wp[3] = {Om[3 * p], Om[3 * p + 1], Om[3 * p + 2]};
   const float dVf = (float)dV;
   double fsum[6] = {0, 0, 0, 0, 0, 0};  // force and torque on the particle
   float dF[MPT][3];
+  float dmax = 0.0f;
   Stencil st[MPT];
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
@@ -446,7 +488,10 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     const double arm[3] = {r_l * dirs[3 * l], r_l * dirs[3 * l + 1], r_l * dirs[3 * l + 2]};
     const double Ud[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
                           Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
-    for (int k = 0; k < 3; ++k) dF[m][k] = 2.0f * ((float)Ud[k] - Ul[k]);
+    for (int k = 0; k < 3; ++k) {
+      dF[m][k] = 2.0f * ((float)Ud[k] - Ul[k]);
+      dmax = fmaxf(dmax, fabsf(dF[m][k]));
+    }
     const double f[3] = {(double)dF[m][0] * dV, (double)dF[m][1] * dV, (double)dF[m][2] * dV};
     // the particle feels minus the force on the fluid
     for (int k = 0; k < 3; ++k) fsum[k] -= f[k];
@@ -463,70 +508,105 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
       T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + fsum[3 + k];
     }
   }
-  // spread dF delta dV into the fixed-point sums, one component at a time,
-  // and add each to the slot forces: plain read-modify-write where this
-  // sphere owns the node alone, global atomics where supports meet
-  for (int comp = 0; comp < 3; ++comp) {
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < cnt; j += kPassBlock) acc[j] = 0ull;
-    __syncthreads();
+  // every marker has read uj once the maximum is known (block barriers)
+  const int e = spread_exponent(block_max_nonneg(dmax), dVf);
+  for (uint32_t j = threadIdx.x; j < 3 * cnt; j += kPassBlock) acc[j] = 0;
+  __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MPT; ++m) {
-      const int l = threadIdx.x + m * kPassBlock;
-      if (l >= nmk) continue;
-      // The stencil is the same for the three components; this empty asm
-      // keeps the compiler from holding its 64 addresses and weights live
-      // across the loop (recomputing them is cheaper than spilling them).
-      asm volatile("" : "+v"(st[m].wx[0]), "+v"(st[m].wx[1]), "+v"(st[m].wx[2]), "+v"(st[m].wx[3]),
-                   "+v"(st[m].wy[0]), "+v"(st[m].wy[1]), "+v"(st[m].wy[2]), "+v"(st[m].wy[3]),
-                   "+v"(st[m].wz[0]), "+v"(st[m].wz[1]), "+v"(st[m].wz[2]), "+v"(st[m].wz[3]),
-                   "+v"(st[m].bx), "+v"(st[m].by), "+v"(st[m].bz));
-      const uint32_t below = (1u << st[m].bx) - 1u;
-      const float dFc = comp == 0 ? dF[m][0] : (comp == 1 ? dF[m][1] : dF[m][2]);
+  for (int m = 0; m < MPT; ++m) {
+    const int l = threadIdx.x + m * kPassBlock;
+    if (l >= nmk) continue;
+    const uint32_t below = (1u << st[m].bx) - 1u;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int jy = q & 3, jz = q >> 2;
-        const int row = (st[m].by + jy) + side * (st[m].bz + jz);
-        const uint32_t j0 = rp[row] + __popc(rb[row] & below);
-        const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
+    for (int q = 0; q < 16; ++q) {
+      const int jy = q & 3, jz = q >> 2;
+      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+      const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
 #pragma unroll
-        for (int jx = 0; jx < 4; ++jx) atomicAdd(&acc[j0 + jx], to_fix(dFc * (st[m].wx[jx] * wyz)));
+      for (int jx = 0; jx < 4; ++jx) {
+        const float w = st[m].wx[jx] * wyz;
+        const uint32_t j = j0 + jx;
+        atomicAdd(&acc[3 * j], __float2int_rn(ldexpf(dF[m][0] * w, e)));
+        atomicAdd(&acc[3 * j + 1], __float2int_rn(ldexpf(dF[m][1] * w, e)));
+        atomicAdd(&acc[3 * j + 2], __float2int_rn(ldexpf(dF[m][2] * w, e)));
       }
     }
-    __syncthreads();
-    float* fc = fib + (size_t)comp * s_cap;
-    for (uint32_t j0 = 0; j0 < cnt; j0 += kWrite * kPassBlock) {
-      uint32_t s[kWrite];
-      float old[kWrite];
-      bool shr[kWrite];
+  }
+  __syncthreads();
+  // Write back: nodes of this sphere alone in place (no other workgroup reads
+  // or writes them), shared nodes into the exact accumulators.
+  for (uint32_t j0 = 0; j0 < cnt; j0 += kWrite * kPassBlock) {
+    uint32_t w[kWrite];
+    float old[kWrite][3];
 #pragma unroll
-      for (int i = 0; i < kWrite; ++i) {
-        const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-        const uint32_t w = j < cnt ? sl[j] : 0xFFFFFFFFu;
-        s[i] = w & ~kSlotShared;
-        shr[i] = j < cnt && (w & kSlotShared);
-      }
+    for (int i = 0; i < kWrite; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      w[i] = j < cnt ? sl[j] : 0xFFFFFFFFu;
+    }
 #pragma unroll
-      for (int i = 0; i < kWrite; ++i)
-        if (s[i] < s_cap && !shr[i]) old[i] = fc[s[i]];
+    for (int i = 0; i < kWrite; ++i)
+      if (!(w[i] & kSlotShared) && w[i] < s_cap)
+        for (int k = 0; k < 3; ++k) old[i][k] = fib[(size_t)k * s_cap + w[i]];
 #pragma unroll
-      for (int i = 0; i < kWrite; ++i) {
-        if (s[i] >= s_cap) continue;
-        const float v = from_fix(acc[j0 + threadIdx.x + i * kPassBlock]);
-        if (shr[i])
-          atomicAdd(fc + s[i], v);
-        else
-          fc[s[i]] = old[i] + v;
+    for (int i = 0; i < kWrite; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      if (j >= cnt) continue;
+      if (!(w[i] & kSlotShared)) {
+        if (w[i] >= s_cap) continue;
+        for (int k = 0; k < 3; ++k)
+          fib[(size_t)k * s_cap + w[i]] = old[i][k] + (float)ldexp((double)acc[3 * j + k], -e);
+      } else {
+        const uint32_t q = w[i] & ~kSlotShared;
+        if (q >= sh_cap) continue;
+        for (int k = 0; k < 3; ++k) {
+          const int a = acc[3 * j + k];
+          if (a)
+            atomicAdd(sh_acc + (size_t)k * sh_cap + q,
+                      (unsigned long long)((long long)a * (1ll << (kShUnitExp - e))));
+        }
       }
     }
   }
 }
 
+// After a pass: the exact sums at shared nodes join the slot forces and the
+// accumulators return to zero.
+__global__ void __launch_bounds__(kBlock)
+k_ibm_fold(const uint32_t* __restrict__ sh_count, uint32_t sh_cap, const uint32_t* __restrict__ sh_slot,
+           unsigned long long* __restrict__ sh_acc, float* __restrict__ fib, uint32_t s_cap) {
+  const uint32_t n = min(*sh_count, sh_cap);
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint32_t s = sh_slot[i];
+    for (int k = 0; k < 3; ++k) {
+      unsigned long long* a = sh_acc + (size_t)k * sh_cap + i;
+      const long long v = (long long)*a;
+      if (!v) continue;
+      *a = 0ull;
+      if (s < s_cap) fib[(size_t)k * s_cap + s] += (float)((double)v * 0x1p-50);
+    }
+  }
+}
+
+// Shared-node table: node -> slot, in place.
+__global__ void __launch_bounds__(kBlock)
+k_ibm_shared_slots(const uint32_t* __restrict__ sh_count, uint32_t sh_cap, const uint32_t* __restrict__ bits,
+                   const uint32_t* __restrict__ rank, uint32_t* __restrict__ sh_slot) {
+  const uint32_t n = min(*sh_count, sh_cap);
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    uint32_t slot;
+    sh_slot[i] = support_slot(bits, rank, sh_slot[i], slot) ? slot : 0xFFFFFFFFu;
+  }
+}
+
 // ----------------------------------------------------------------- wall --
 // Static pipe-wall markers (rings at every integer z, desired velocity 0),
-// one thread per marker. A pass is split in two launches so every marker
+// one thread per marker. A pass is split in launches so every marker
 // interpolates the same velocity before any spread lands: interpolate and
-// store dF = 2 (0 - U_l), then spread dF delta dV with global atomics.
+// store dF = 2 (0 - U_l), spread dF delta dV into exact 64-bit fixed-point
+// sums per slot (units 2^-50; a wall carries no spheres, so the shared-node
+// accumulators are free for it), then fold the sums into the slot forces:
+// the result does not depend on the order of the atomics.
 __device__ __forceinline__ void wall_stencil(const double* __restrict__ xm, uint32_t l, int b[3], float w[3][4]) {
   for (int k = 0; k < 3; ++k) {
     const double X = xm[3 * l + k];
@@ -566,7 +646,7 @@ k_ibm_wall_interp(const double* __restrict__ xm, uint32_t nm, Dims d, const uint
 
 __global__ void __launch_bounds__(kBlock)
 k_ibm_wall_spread(const double* __restrict__ xm, uint32_t nm, float dV, Dims d, const uint32_t* __restrict__ bits,
-                  const uint32_t* __restrict__ rank, float* __restrict__ fib, uint32_t s_cap,
+                  const uint32_t* __restrict__ rank, unsigned long long* __restrict__ acc, uint32_t s_cap,
                   const float* __restrict__ dF) {
   const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
   if (l >= nm) return;
@@ -583,8 +663,25 @@ k_ibm_wall_spread(const double* __restrict__ xm, uint32_t nm, float dV, Dims d, 
         if (!support_slot(bits, rank, node_index(wrapi(b[0] + jx, d.nx), y, z, d.nx, d.ny), s) || s >= s_cap)
           continue;
         const float wt = w[0][jx] * wyz;
-        for (int k = 0; k < 3; ++k) atomicAdd(fib + (size_t)k * s_cap + s, f[k] * wt);
+        for (int k = 0; k < 3; ++k) {
+          const long long v = llrint((double)(f[k] * wt) * 0x1p50);
+          if (v) atomicAdd(acc + (size_t)k * s_cap + s, (unsigned long long)v);
+        }
       }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restrict__ acc, float* __restrict__ fib,
+                uint32_t s_cap) {
+  const uint32_t n = min(*count, s_cap);
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock)
+    for (int k = 0; k < 3; ++k) {
+      unsigned long long* a = acc + (size_t)k * s_cap + s;
+      const long long v = (long long)*a;
+      if (!v) continue;
+      *a = 0ull;
+      fib[(size_t)k * s_cap + s] += (float)((double)v * 0x1p-50);
     }
 }
 
@@ -680,8 +777,15 @@ hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
                                m.s_cap, c.err)) != hipSuccess)
     return e;
   if (c.np > 0) {
+    // shared nodes: their rank, then their slots
+    if ((e = launch_bits_compact(c.stream, m.shared, words, m.sh_rank, m.block_sums, m.sh_count, m.sh_slot,
+                                 m.sh_cap, c.err)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_ibm_shared_slots, dim3(1024), dim3(kBlock), 0, c.stream, m.sh_count, m.sh_cap,
+                       m.bits[buf], m.rank[buf], m.sh_slot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ibm_slots, dim3(c.np), dim3(kBlock), 0, c.stream, X, m.R_b, m.side, c.dims, m.bits[buf],
-                       m.rank[buf], m.shared, m.rowbits, m.fcount, m.fcap, m.fslot);
+                       m.rank[buf], m.shared, m.sh_rank, m.rowbits, m.fcount, m.fcap, m.fslot);
     e = hipGetLastError();
   }
   return e;
@@ -712,21 +816,32 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    if (c.np <= 0) {
-      // wall only
-    } else if (m.n_markers <= kPassBlock)
-      hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
-                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.us,
-                         m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
-    else
-      hipLaunchKernelGGL(k_ibm_pass<2>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs, m.n_markers, m.r_l,
-                         m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot, m.us,
-                         m.fib[m.cur], m.s_cap, c.P.F_ib, c.P.T_ib, k == 0 ? 1 : 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (c.np > 0) {
+      if (m.n_markers <= kPassBlock)
+        hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs,
+                           m.n_markers, m.r_l, m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot,
+                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib,
+                           k == 0 ? 1 : 0);
+      else
+        hipLaunchKernelGGL(k_ibm_pass<2>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs,
+                           m.n_markers, m.r_l, m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot,
+                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib,
+                           k == 0 ? 1 : 0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_ibm_fold, dim3(1024), dim3(kBlock), 0, c.stream, m.sh_count, m.sh_cap, m.sh_slot,
+                         m.sh_acc, m.fib[m.cur], m.s_cap);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipError_t e = hipSuccess;
     if (m.n_wall) {
+      // the wall accumulators are indexed by slot: the shared-node table has
+      // room for every slot (sh_cap = s_cap)
       hipLaunchKernelGGL(k_ibm_wall_spread, wgrid, dim3(kBlock), 0, c.stream, m.wmark, m.n_wall, (float)m.wdV, c.dims,
-                         m.bits[m.cur], m.rank[m.cur], m.fib[m.cur], m.s_cap, m.wdF);
+                         m.bits[m.cur], m.rank[m.cur], m.sh_acc, m.sh_cap, m.wdF);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_ibm_wall_fold, dim3(1024), dim3(kBlock), 0, c.stream, m.count[m.cur], m.sh_acc,
+                         m.fib[m.cur], m.s_cap);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

@@ -229,13 +229,22 @@ struct IbmBufs {
   uint32_t* count[2];    // [1] support size
   float* fib[2];         // [3][S_cap] spread force per slot
   uint32_t* shared;      // [mask_words] nodes in more than one sphere's support
+  // Shared nodes: their forcing contributions of a pass are summed exactly
+  // (64-bit fixed point, units 2^-50) apart from the slot forces, which the
+  // other spheres read during the same pass, and folded in after it.
+  uint32_t* sh_rank;     // [mask_words] rank of the shared bitmask words
+  uint32_t* sh_count;    // [1] shared nodes
+  uint32_t* sh_slot;     // [sh_cap] node, then slot, of each shared node
+  unsigned long long* sh_acc;  // [3][sh_cap] pass contributions, zero between passes
+  uint32_t sh_cap;
   uint32_t* list;        // [S_cap] node of each slot (current support)
   float4* us;            // [S_cap] (u*, rho) from the prepass
   uint32_t* block_sums;  // scan scratch
   double* dirs;          // [n_markers][3] unit marker directions (Fibonacci)
   uint32_t* rowbits;     // [P][rows] per-sphere forcing-support rows (box-local)
   uint32_t* fcount;      // [P] forcing-support size per sphere
-  uint32_t* fslot;       // [P][fcap] global slot of each forcing-support node
+  uint32_t* fslot;       // [P][fcap] global slot of each forcing-support node,
+                         // or kSlotShared | shared index at shared nodes
   uint32_t s_cap;        // slots reserved
   uint32_t fcap;         // forcing-support nodes reserved per sphere
   int n_markers;         // markers per sphere

@@ -1,5 +1,5 @@
 // spectrum.hip - three-dimensional spectra of the kinetic energy and of its
-// dissipation rate for one snapshot (Sec. 4.2, Figs. 11-12), with or without
+// dissipation rate for one snapshot (Sec. 3.2.1), with or without
 // the rigid-body masking of the particle interiors.
 //
 // E(k) = 1/2 sum over the shell k - 1/2 <= |k| < k + 1/2 of |u^(k)|^2, with

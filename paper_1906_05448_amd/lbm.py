@@ -89,10 +89,15 @@ def lib() -> ctypes.CDLL:
         "lbm_step_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "lbm_set_particles": (ctypes.c_int, [P, I32, P, P, P, P, P, I32, I32]),
         "lbm_get_particles": (ctypes.c_int, [P, P, P, P]),
+        "lbm_particle_count": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
+        "lbm_state_size": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "lbm_get_state": (ctypes.c_int, [P, P, SZ]),
+        "lbm_set_state": (ctypes.c_int, [P, P, SZ]),
         "lbm_forces": (ctypes.c_int, [P, P, P, P]),
         "lbm_link_count": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "lbm_get_links": (ctypes.c_int, [P, I64, P, P, P, P, P, ctypes.POINTER(I64)]),
         "lbm_geometry_counts": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "lbm_ibm_support": (ctypes.c_int, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "lbm_stats": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(_CStats), P]),
         "lbm_spectrum": (ctypes.c_int, [P, I32, I32, P, P]),
         "lbm_pipe_budget_reset": (ctypes.c_int, [P, ctypes.c_double]),
@@ -260,6 +265,26 @@ class Lattice:
                "lbm_set_particles")
         self.n_particles = n
 
+    def particle_count(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().lbm_particle_count(self._h, ctypes.byref(n)), "lbm_particle_count")
+        return n.value
+
+    # -- checkpoint -----------------------------------------------------
+    def get_state(self) -> np.ndarray:
+        """The context's state blob (lbm_get_state) as a uint8 array."""
+        n = ctypes.c_size_t()
+        _check(lib().lbm_state_size(self._h, ctypes.byref(n)), "lbm_state_size")
+        blob = np.empty(n.value, np.uint8)
+        _check(lib().lbm_get_state(self._h, _host_ptr(blob), n.value), "lbm_get_state")
+        return blob
+
+    def set_state(self, blob) -> None:
+        """Restores a blob of get_state() (lbm_set_state)."""
+        b = np.ascontiguousarray(np.asarray(blob, np.uint8))
+        _check(lib().lbm_set_state(self._h, _host_ptr(b), b.size), "lbm_set_state")
+        self.n_particles = self.particle_count()
+
     def get_particles(self):
         n = getattr(self, "n_particles", 0)
         X, U, W = (np.zeros((n, 3)) for _ in range(3))
@@ -295,6 +320,12 @@ class Lattice:
         s, l = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().lbm_geometry_counts(self._h, ctypes.byref(s), ctypes.byref(l)), "lbm_geometry_counts")
         return s.value, l.value
+
+    def ibm_support(self):
+        """(support nodes, shared nodes) of the immersed boundary."""
+        s, h = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lbm_ibm_support(self._h, ctypes.byref(s), ctypes.byref(h)), "lbm_ibm_support")
+        return s.value, h.value
 
     def stats(self, nbins: int = 32, bin_width: float = 0.25) -> dict:
         """Statistics of the current snapshot (lbm_stats): a dict with the

@@ -75,11 +75,88 @@ def test_moving_spheres_release_ibm(store):
         P = o.state.P
         assert np.abs(Xg - P.X).max() < (1e-6 if store == 0 else 2e-4)
         assert rel_l2(Ug, P.U) < (1e-4 if store == 0 else 1e-2)
+        assert rel_l2(Wg, P.Om) < (1e-3 if store == 0 else 5e-2)
+        Fg, Tg, _ = g.forces()
+        Fo, To, _ = o.forces()
+        assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
+        assert rel_l2(Tg, To) < (1e-3 if store == 0 else 5e-2)
+    assert np.abs(o.state.P.Om).max() > 1e-6  # the spheres spin up
+    g.close()
+
+
+@pytest.mark.parametrize("store,rd", [(0, 0.0), (0, 0.4), (1, 0.0), (1, 0.4)])
+def test_r8_spheres_sharing_support(store, rd):
+    """Radius 8, the production spheres: the forcing support of one sphere
+    (about 3300 nodes at r_d = 0) takes two staging rounds of the pass
+    kernel. Three released spheres, two of them 2 spacings apart so that
+    their supports share nodes, one across a periodic face; density ratio 4
+    as in the paper's particle-laden case."""
+    shape = (56, 48, 44)
+    spec = synth.hit_spectrum(seed=7, u_rms=0.03, kcut=8)
+    u0 = synth.hit_field(spec, shape)
+    X = np.array([[15.3, 20.2, 21.7], [33.4, 21.1, 22.3], [50.6, 40.9, 6.4]])
+    r = np.full(3, 8.0)
+    rho_p = np.full(3, 4.0)
+    o, g = _pair(shape, tau=0.52, store=store, rd=rd, max_np=3, max_r=8.0)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, r=r, rho_p=rho_p, mode=RELEASE)
+    g.set_particles(X, r, rho_p=rho_p, mode=1)
+    tol = 1e-5 if store == 0 else 2e-3
+    for chunk in (1, 4, 10):
+        o.step(chunk)
+        g.step(chunk)
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        assert rel_l2(ug, uo) < tol, o.state.step
+        Xg, Ug, Wg = g.get_particles()
+        P = o.state.P
+        assert np.abs(Xg - P.X).max() < (1e-6 if store == 0 else 2e-4)
+        assert rel_l2(Ug, P.U) < (1e-4 if store == 0 else 1e-2)
+        assert rel_l2(Wg, P.Om) < (1e-3 if store == 0 else 5e-2)
         Fg, Tg, _ = g.forces()
         Fo, To, _ = o.forces()
         assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
         assert rel_l2(Tg, To) < (1e-3 if store == 0 else 5e-2)
     g.close()
+
+
+def test_many_spheres_jacobi_passes_reproducible():
+    """More spheres than the device runs at once (1200 of radius 3.5 in a
+    112^3 box, supports overlapping everywhere): every marker of a forcing
+    pass reads the velocity of the end of the previous pass (Jacobi across
+    spheres, as the oracle), whichever order the workgroups run in, and the
+    shared-node sums are exact, so two runs agree bit for bit and both match
+    the FP64 oracle."""
+    shape = (112, 112, 112)
+    n, r = 1200, 3.5
+    X = synth.random_spheres(n, shape, 2 * r + 1.0, seed=21)
+    rng = np.random.default_rng(5)
+    U = rng.normal(scale=0.01, size=(n, 3))
+    W = rng.normal(scale=0.002, size=(n, 3))
+    spec = synth.hit_spectrum(seed=8, u_rms=0.03, kcut=12)
+    u0 = synth.hit_field(spec, shape)
+    runs = []
+    for _ in range(2):
+        g = gpu_lattice(gpu_config(nx=112, ny=112, nz=112, tau=0.55, bc=2, max_particles=n, max_radius=r))
+        g.set_fields(u0)
+        g.set_particles(X, np.full(n, r), u=U, omega=W, rho_p=np.full(n, 8.0))
+        g.step(3)
+        runs.append([*g.get_fields(), *g.get_particles(), *g.forces()])
+        g.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+    o = OSim(OConfig(shape=shape, tau=0.55, bc="ibm"))
+    o.set_fields(u0)
+    o.set_particles(X, U=U, Om=W, r=np.full(n, r), rho_p=np.full(n, 8.0))
+    o.step(3)
+    uo, _ = o.fields()
+    ug = runs[0][0]
+    assert rel_l2(ug, uo) < 1e-5
+    Fo, To, _ = o.forces()
+    assert rel_l2(runs[0][5], Fo) < 1e-4
+    assert rel_l2(runs[0][6], To) < 1e-3
+    assert rel_l2(runs[0][3], o.state.P.U) < 1e-4
 
 
 def test_comoving_sphere_ibm_keeps_uniform_flow():
