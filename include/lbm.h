@@ -384,6 +384,27 @@ int lbm_mlp_forward(lbm_mlp* mlp, const uint16_t* x_dev, int64_t n, float* y_dev
 int lbm_mlp_gradient(lbm_mlp* mlp, const uint16_t* x_dev, const float* t_dev, int64_t n, double* loss,
                      float* grad_host);
 
+/* The gradient of lbm_mlp_gradient without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid allocation): no network
+ * handle or workspace; the parameters (device FP32, LBM_MLP_PARAMS, e.g.
+ * lbm_mlp_device_params()), the n features x and targets t (device, as for
+ * lbm_mlp_gradient) are inputs, grad (device FP32, LBM_MLP_PARAMS) receives
+ * the gradient of the mean loss and loss_sum (device FP64, one value) the
+ * sum over the n samples and 9 outputs of (y - t)^2 (the mean loss is
+ * loss_sum / (9 n)); both equal what lbm_mlp_gradient computes for the same
+ * inputs. The per-workgroup partial sums go to a scratch array of fixed size
+ * (256 x LBM_MLP_PARAMS FP32 plus 256 FP64, 10.5 MB) that the library holds
+ * on each GPU it runs on until the process ends; every call on a GPU uses
+ * that GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. Enqueued on stream
+ * (a hipStream_t, NULL for the default stream) on the current device; async.
+ * Errors: LBM_E_ARG (a NULL pointer, n <= 0), LBM_E_SIZE (n above
+ * LBM_MLP_NOALLOC_MAX_SAMPLES), LBM_E_HIP. */
+#define LBM_MLP_NOALLOC_MAX_SAMPLES (1ll << 30)
+int lbm_mlp_gradient_noalloc(const float* theta_dev, const uint16_t* x_dev, const float* t_dev, int64_t n,
+                             float* grad_dev, double* loss_sum_dev, void* hip_stream);
+
 /* One Adam step (Kingma & Ba) with the last gradient:
  *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  *   theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -35,6 +36,38 @@ MlpPlan mlp_plan() {
   p.loss = take(sizeof(double));
   p.total = off;
   return p;
+}
+
+// ---- gradient without allocation -------------------------------------------
+// The per-workgroup partial sums of the gradient live in this file-scope
+// device array instead of a network workspace: every GPU the library runs on
+// holds one copy of it (10.5 MB) until the process ends. Host code must not
+// pass the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): its device address is looked up once per device with
+// hipGetSymbolAddress and kept in scratch_addr.
+constexpr size_t kScratchPartBytes = (size_t)lbm::kMlpGrid * lbm::kMlpParams * sizeof(float);
+constexpr size_t kScratchBytes = kScratchPartBytes + (size_t)lbm::kMlpGrid * sizeof(double);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (the current device).
+hipError_t scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -121,6 +154,19 @@ int lbm_mlp_gradient(lbm_mlp* h, const uint16_t* x, const float* t, int64_t n, d
     if (loss) *loss = l / (9.0 * (double)n);
   }
   return LBM_OK;
+}
+
+int lbm_mlp_gradient_noalloc(const float* theta, const uint16_t* x, const float* t, int64_t n, float* grad,
+                             double* loss_sum, void* stream) {
+  if (!theta || !x || !t || !grad || !loss_sum || n <= 0) return LBM_E_ARG;
+  if (n > LBM_MLP_NOALLOC_MAX_SAMPLES) return LBM_E_SIZE;
+  void* sp = nullptr;
+  if (scratch_for_current_device(&sp) != hipSuccess) return LBM_E_HIP;
+  float* part = (float*)sp;
+  double* lpart = (double*)((char*)sp + kScratchPartBytes);
+  return lbm::launch_mlp_gradient((hipStream_t)stream, theta, x, t, n, part, lpart, grad, loss_sum) == hipSuccess
+             ? LBM_OK
+             : LBM_E_HIP;
 }
 
 int lbm_mlp_adam_step(lbm_mlp* h, double lr, double beta1, double beta2, double eps) {

@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         "lbm_mlp_forward": (ctypes.c_int, [P, P, I64, P]),
         "lbm_mlp_gradient": (ctypes.c_int, [P, P, P, I64, ctypes.POINTER(ctypes.c_double), P]),
         "lbm_mlp_adam_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+        "lbm_mlp_gradient_noalloc": (ctypes.c_int, [P, P, P, I64, P, P, P]),
         "lbm_mlp_sync": (ctypes.c_int, [P]),
         "lbm_mlp_destroy": (None, [P]),
         "lbm_profile_enable": (ctypes.c_int, [P, I32]),
@@ -503,6 +504,16 @@ class Mlp:
         _check(lib().lbm_mlp_gradient(self._h, _dev(x), _dev(t), n, ctypes.byref(loss),
                                       _host_ptr(g) if want_grad else None), "lbm_mlp_gradient")
         return loss.value, g
+
+    def gradient_noalloc(self, x, t, grad, loss_sum, stream=None) -> None:
+        """lbm_mlp_gradient_noalloc at this network's parameters: the gradient
+        into grad (float32 CUDA [10249]) and the summed squared error into
+        loss_sum (float64 CUDA [1]), with no allocation by the library."""
+        n = self._rows(x)
+        st = stream if stream is not None else self.stream
+        _check(lib().lbm_mlp_gradient_noalloc(lib().lbm_mlp_device_params(self._h), _dev(x), _dev(t), n, _dev(grad),
+                                              _dev(loss_sum), ctypes.c_void_p(st.cuda_stream)),
+               "lbm_mlp_gradient_noalloc")
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
         _check(lib().lbm_mlp_adam_step(self._h, lr, beta1, beta2, eps), "lbm_mlp_adam_step")
