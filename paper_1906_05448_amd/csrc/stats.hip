@@ -13,9 +13,16 @@
 //            sphere lowers the keys of its box with atomicMin. The bin of
 //            the nearest surface is the smallest bin over surfaces, since
 //            floor is monotonic.
-//   raw      fixed grid, grid-stride: raw sums and the fluid sums
-//   masked   masked sums and the histograms; the velocity of a node inside a
-//            sphere is U + Omega x (x - X) evaluated in FP64 where needed
+//   sums     one wavefront per 64-node row segment, segments dealt out to a
+//            fixed grid: raw, masked and fluid sums and the histograms in one
+//            pass. The x neighbours come from the lanes beside (loaded only
+//            at the segment's ends), the y and z neighbours from coalesced
+//            row loads; the velocity of a node inside a sphere is
+//            U + Omega x (x - X) evaluated in FP64 where needed. Histogram
+//            bins are summed per wavefront in LDS: the binned lanes are
+//            ranked among the lanes of the same bin, and rank by rank each
+//            adds its values with a plain read-modify-write, so a bin's sum
+//            follows lane order and then segment order: reproducible.
 //   reduce   one workgroup per column adds the per-block partials in order
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -79,33 +86,171 @@ k_stats_spheres(const double* __restrict__ X, const double* __restrict__ rad, Di
   }
 }
 
+// Velocity of node (x, y, z) with key k as the masked statistics see it:
+// the lattice value v in fluid, zero in the wall, the rigid-body motion of
+// the sphere inside it (FP64).
+struct Vel3 {
+  double v[3];
+};
+
+// Rigid-body velocity of sphere p at node (x, y, z).
+__device__ __forceinline__ Vel3 rigid_at(uint32_t p, int x, int y, int z, const double* X, const double* U,
+                                      const double* Om, int nx, int ny, int nz) {
+  const double r[3] = {min_image((double)x - X[3 * p], nx), min_image((double)y - X[3 * p + 1], ny),
+                       min_image((double)z - X[3 * p + 2], nz)};
+  const double* w = Om + 3 * p;
+  Vel3 m;
+  m.v[0] = U[3 * p] + (w[1] * r[2] - w[2] * r[1]);
+  m.v[1] = U[3 * p + 1] + (w[2] * r[0] - w[0] * r[2]);
+  m.v[2] = U[3 * p + 2] + (w[0] * r[1] - w[1] * r[0]);
+  return m;
+}
+
+__device__ __forceinline__ void masked_at(uint32_t k, const float* v, int x, int y, int z, const double* X,
+                                          const double* U, const double* Om, const Dims& d, double m[3]) {
+  if (k >= kKeyFluid) {
+    m[0] = v[0];
+    m[1] = v[1];
+    m[2] = v[2];
+    return;
+  }
+  if (k == kKeyWall) {
+    m[0] = m[1] = m[2] = 0.0;
+    return;
+  }
+  const Vel3 r = rigid_at(k - 1u, x, y, z, X, U, Om, d.nx, d.ny, d.nz);
+  m[0] = r.v[0];
+  m[1] = r.v[1];
+  m[2] = r.v[2];
+}
+
+constexpr int kSegWaves = kSBlock / 64;
+
 __global__ void __launch_bounds__(kSBlock)
-k_stats_raw(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key, Dims d,
-            double nu, double* __restrict__ part, int stride) {
-  const RawVel vel{u, d.N};
-  double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // kNf .. kBulk
+k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key,
+             const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om, Dims d,
+             double nu, int nbins, double* __restrict__ part, int stride) {
+  extern __shared__ double hist_lds[];  // [wave][5][nbins]
+  const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+  double* hw = hist_lds + (size_t)wv * 5 * nbins;
+  for (int i = lane; i < 5 * nbins; i += 64) hw[i] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const uint32_t N = d.N;
+  const uint32_t segs = (uint32_t)(nx + 63) / 64u;
+  const uint32_t total = segs * (uint32_t)ny * (uint32_t)nz;
+  double s[kStatScalars] = {};
   double umax2 = 0.0;
-  for (uint32_t n = blockIdx.x * kSBlock + threadIdx.x; n < d.N; n += gridDim.x * kSBlock) {
-    const Neigh g = neighbours(n, d);
-    double v[3];
-    vel.at(n, v);
-    const double v2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-    const double ke = 0.5 * v2;
-    s[kStatKeRaw] += ke;
-    s[kStatEpsRaw] += dissipation(vel, g, nu);
-    if (key[n] >= kKeyFluid) {
-      const double r = rho[n];
-      s[kStatNf] += 1.0;
-      s[kStatMass] += r;
-      s[kStatMomX] += r * v[0];
-      s[kStatMomY] += r * v[1];
-      s[kStatMomZ] += r * v[2];
-      s[kStatKeFluid] += ke;
-      s[kStatBulk] += v[2];
-      umax2 = fmax(umax2, v2);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (uint32_t sg = blockIdx.x * kSegWaves + (uint32_t)wv; sg < total; sg += gridDim.x * kSegWaves) {
+    const uint32_t row = sg / segs;
+    const int x0 = (int)(sg - row * segs) * 64;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const int x = x0 + lane;
+    const bool live = x < nx;
+    const int xc = live ? x : nx - 1;
+    const int xl = xc == 0 ? nx - 1 : xc - 1, xr = xc == nx - 1 ? 0 : xc + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    auto at = [&](int xx, int yy, int zz) {
+      return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx + (uint32_t)xx;
+    };
+    // nodes: centre, x+, x-, y+, y-, z+, z-; the x neighbours come from the
+    // lanes beside except at the segment's ends
+    const int nxs[7] = {xc, xr, xl, xc, xc, xc, xc}, nys[7] = {y, y, y, yp, ym, y, y},
+              nzs[7] = {z, z, z, z, z, zp, zm};
+    uint32_t kk[7];
+    float vf[7][3];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      if (j == 1 || j == 2) continue;
+      const uint32_t n = at(nxs[j], nys[j], nzs[j]);
+      kk[j] = key[n];
+      for (int c = 0; c < 3; ++c) vf[j][c] = u[(size_t)c * N + n];
+    }
+    const float r0 = rho[at(xc, y, z)];
+    kk[1] = (uint32_t)__shfl_down((int)kk[0], 1, 64);
+    kk[2] = (uint32_t)__shfl_up((int)kk[0], 1, 64);
+    for (int c = 0; c < 3; ++c) {
+      vf[1][c] = __shfl_down(vf[0][c], 1, 64);
+      vf[2][c] = __shfl_up(vf[0][c], 1, 64);
+    }
+    if (lane == 63 || xc == nx - 1) {
+      const uint32_t n = at(xr, y, z);
+      kk[1] = key[n];
+      for (int c = 0; c < 3; ++c) vf[1][c] = u[(size_t)c * N + n];
+    }
+    if (lane == 0) {
+      const uint32_t n = at(xl, y, z);
+      kk[2] = key[n];
+      for (int c = 0; c < 3; ++c) vf[2][c] = u[(size_t)c * N + n];
+    }
+    // central-difference gradients in FP64, raw and (where a neighbour is
+    // masked) masked
+    bool any_masked = false;
+#pragma unroll
+    for (int j = 1; j < 7; ++j) any_masked = any_masked || kk[j] < kKeyFluid;
+    double G[3][3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * ((double)vf[1 + 2 * ax][c] - (double)vf[2 + 2 * ax][c]);
+    const double eps_raw = dissipation_of(G, nu);
+    double eps_m = eps_raw;
+    if (any_masked) {
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        double mp[3], mm[3];
+        masked_at(kk[1 + 2 * ax], vf[1 + 2 * ax], nxs[1 + 2 * ax], nys[1 + 2 * ax], nzs[1 + 2 * ax], X, U, Om, d, mp);
+        masked_at(kk[2 + 2 * ax], vf[2 + 2 * ax], nxs[2 + 2 * ax], nys[2 + 2 * ax], nzs[2 + 2 * ax], X, U, Om, d, mm);
+        for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * (mp[c] - mm[c]);
+      }
+      eps_m = dissipation_of(G, nu);
+    }
+    const double vx = vf[0][0], vy = vf[0][1], vz = vf[0][2];
+    const double ke = 0.5 * ((vx * vx + vy * vy) + vz * vz);
+    if (live) {
+      double vm[3];
+      masked_at(kk[0], vf[0], xc, y, z, X, U, Om, d, vm);
+      s[kStatKeRaw] += ke;
+      s[kStatEpsRaw] += eps_raw;
+      s[kStatKeMasked] += 0.5 * ((vm[0] * vm[0] + vm[1] * vm[1]) + vm[2] * vm[2]);
+      s[kStatEpsMasked] += eps_m;
+      if (kk[0] >= kKeyFluid) {
+        const double r = r0;
+        s[kStatNf] += 1.0;
+        s[kStatMass] += r;
+        s[kStatMomX] += r * vx;
+        s[kStatMomY] += r * vy;
+        s[kStatMomZ] += r * vz;
+        s[kStatKeFluid] += ke;
+        s[kStatBulk] += vz;
+        s[kStatEpsFluid] += eps_m;
+        umax2 = fmax(umax2, 2.0 * ke);
+      }
+    }
+    // histograms: fluid nodes within the profile range
+    const bool binned = live && kk[0] >= kKeyFluid && kk[0] != kKeyFar;
+    const uint32_t bin = kk[0] & 0x7FFFFFFFu;
+    unsigned long long todo = __ballot(binned);
+    if (todo == 0ull) continue;
+    uint32_t rank = 0, maxrank = 0;
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
+      const unsigned long long m = __ballot(binned && bin == b);
+      if (binned && bin == b) rank = (uint32_t)__popcll(m & lt);
+      maxrank = max(maxrank, (uint32_t)__popcll(m) - 1u);
+      todo &= ~m;
+    }
+    const double val[5] = {1.0, ke, eps_m, vz, vz * vz};
+    for (uint32_t t = 0; t <= maxrank; ++t) {
+      if (binned && rank == t)
+        for (int c = 0; c < 5; ++c) hw[(size_t)c * nbins + bin] += val[c];
+      __builtin_amdgcn_wave_barrier();
     }
   }
-  block_sum_first<kSBlock, 10>(s);
+  s[kStatUmax2] = 0.0;
+  block_sum_first<kSBlock, kStatScalars>(s);
   // the maximum is order-independent: a plain LDS reduction
   __shared__ double mx[kSBlock];
   mx[threadIdx.x] = umax2;
@@ -114,87 +259,15 @@ k_stats_raw(const float* __restrict__ u, const float* __restrict__ rho, const ui
     if ((int)threadIdx.x < o) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double* out = part + (size_t)blockIdx.x * stride;
-    for (int k = 0; k < 10; ++k)
-      if (k != kStatUmax2) out[k] = s[k];
-    out[kStatUmax2] = mx[0];
-  }
-}
-
-// Histograms: lane l of a wavefront owns bins l, l + 64, ...; the binned
-// nodes of an iteration are broadcast one at a time in lane order, so every
-// bin is summed in a fixed order without atomics.
-template <int SLOTS>
-__global__ void __launch_bounds__(kSBlock)
-k_stats_masked(const float* __restrict__ u, const uint32_t* __restrict__ key, const double* __restrict__ X,
-               const double* __restrict__ U, const double* __restrict__ Om, Dims d, double nu, int nbins,
-               double* __restrict__ part, int stride) {
-  const MaskedVel vel{u, key, X, U, Om, d};
-  const RawVel raw{u, d.N};
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double s[3] = {0, 0, 0};  // ke masked, eps masked, eps fluid
-  double h[SLOTS][5];
-#pragma unroll
-  for (int j = 0; j < SLOTS; ++j)
-    for (int k = 0; k < 5; ++k) h[j][k] = 0.0;
-  for (uint32_t base = blockIdx.x * kSBlock; base < d.N; base += gridDim.x * kSBlock) {
-    const uint32_t n = base + threadIdx.x;
-    bool binned = false;
-    uint32_t bin = 0;
-    double val[5] = {0, 0, 0, 0, 0};
-    if (n < d.N) {
-      const Neigh g = neighbours(n, d);
-      const uint32_t k = key[n];
-      double v[3];
-      vel.at(n, v);
-      const double ke = 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-      const double eps = dissipation(vel, g, nu);
-      s[0] += ke;
-      s[1] += eps;
-      if (k >= kKeyFluid) {
-        s[2] += eps;
-        if (k != kKeyFar) {
-          binned = true;
-          bin = k & 0x7FFFFFFFu;
-          raw.at(n, v);
-          val[0] = 1.0;
-          val[1] = ke;
-          val[2] = eps;
-          val[3] = v[2];
-          val[4] = v[2] * v[2];
-        }
-      }
-    }
-    unsigned long long m = __ballot(binned);
-    while (m) {
-      const int src = __ffsll(m) - 1;
-      m &= m - 1ull;
-      const int b = __builtin_amdgcn_readlane((int)bin, src);
-      double w[5];
-      for (int k = 0; k < 5; ++k) w[k] = readlane_d(val[k], src);
-#pragma unroll
-      for (int j = 0; j < SLOTS; ++j)
-        if ((b >> 6) == j && (b & 63) == lane)
-          for (int k = 0; k < 5; ++k) h[j][k] += w[k];
-    }
-  }
-  block_sum_first<kSBlock, 3>(s);
-  __shared__ double hs[kSBlock / 64][5][64 * SLOTS];
-#pragma unroll
-  for (int j = 0; j < SLOTS; ++j)
-    for (int k = 0; k < 5; ++k) hs[wave][k][j * 64 + lane] = h[j][k];
-  __syncthreads();
   double* out = part + (size_t)blockIdx.x * stride;
   if (threadIdx.x == 0) {
-    out[kStatKeMasked] = s[0];
-    out[kStatEpsMasked] = s[1];
-    out[kStatEpsFluid] = s[2];
+    for (int c = 0; c < kStatScalars; ++c) out[c] = s[c];
+    out[kStatUmax2] = mx[0];
   }
+  // wavefront histograms added in wavefront order
   for (int i = threadIdx.x; i < 5 * nbins; i += kSBlock) {
-    const int k = i / nbins, b = i % nbins;
     double t = 0.0;
-    for (int w = 0; w < kSBlock / 64; ++w) t += hs[w][k][b];
+    for (int w = 0; w < kSegWaves; ++w) t += hist_lds[(size_t)w * 5 * nbins + i];
     out[kStatScalars + i] = t;
   }
 }
@@ -252,17 +325,8 @@ hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t
   const int grid = (int)std::min<uint32_t>((uint32_t)kStatGrid, (d.N + kSBlock - 1) / kSBlock);
   hipError_t e = launch_stats_keys(c, key, nbins, width, X);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_stats_raw, dim3(grid), dim3(kSBlock), 0, c.stream, u, rho, key, d, nu, part, stride);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (nbins <= 64)
-    hipLaunchKernelGGL(k_stats_masked<1>, dim3(grid), dim3(kSBlock), 0, c.stream, u, key, X, U, Om, d, nu, nbins,
-                       part, stride);
-  else if (nbins <= 128)
-    hipLaunchKernelGGL(k_stats_masked<2>, dim3(grid), dim3(kSBlock), 0, c.stream, u, key, X, U, Om, d, nu, nbins,
-                       part, stride);
-  else
-    hipLaunchKernelGGL(k_stats_masked<4>, dim3(grid), dim3(kSBlock), 0, c.stream, u, key, X, U, Om, d, nu, nbins,
-                       part, stride);
+  hipLaunchKernelGGL(k_stats_sums, dim3(grid), dim3(kSBlock), (size_t)kSegWaves * 5 * std::max(nbins, 1) * sizeof(double),
+                     c.stream, u, rho, key, X, U, Om, d, nu, nbins, part, stride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stats_reduce, dim3(stride), dim3(kSBlock), 0, c.stream, part, grid, stride, out);
   return hipGetLastError();
