@@ -38,6 +38,7 @@ class PairConfig:
     d_min: float = 0.0
     d_max: float = 10.0
     store: int = lbm.STORE_F32
+    samples: int = 0            # > 0: that many cells per snapshot, drawn without replacement (seeded)
 
 
 def _motion(n, radius, u_rms, rng):
@@ -77,6 +78,13 @@ def paired_samples(cfg: PairConfig, seed: int):
         A.step(cfg.K)
         B.step(cfg.K)
         nodes, _, x = B.corrector_cells(cfg.u_rms, cfg.d_min, cfg.d_max)
+        if 0 < cfg.samples < nodes.shape[0]:
+            gen = torch.Generator(device=nodes.device)
+            gen.manual_seed(seed * 1000 + s)
+            pick = torch.randperm(nodes.shape[0], device=nodes.device, generator=gen)[:cfg.samples]
+            pick = pick.sort().values
+            nodes = nodes.index_select(0, pick).contiguous()
+            x = x.index_select(0, pick)
         xs.append(x.clone())
         target = A.corrector_labels(nodes, cfg.u_rms).clone()
         B.corrector_labels(nodes, cfg.u_rms, subtract_from=target)
