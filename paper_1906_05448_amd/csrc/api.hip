@@ -203,7 +203,7 @@ struct Plan {
   uint32_t link_cap, wl_count;
   // immersed boundary
   size_t ib_bits[2], ib_rank[2], ib_count, ib_fib[2], ib_shared, ib_list, ib_us, ib_bsum, ib_dirs, ib_rowbits,
-      ib_fcount, ib_fslot, ib_wmark, ib_wdF, ib_wsup, ib_sh_rank, ib_sh_count, ib_sh_slot, ib_sh_acc;
+      ib_fcount, ib_fslot, ib_pu, ib_pf, ib_wmark, ib_wdF, ib_wsup, ib_sh_rank, ib_sh_count, ib_sh_slot, ib_sh_acc;
   uint32_t s_cap, fcap, n_markers, n_wall, wall_support;
   int side;
   size_t total;
@@ -293,7 +293,7 @@ Plan plan(const lbm_config& c) {
     for (int b = 0; b < 2; ++b) {
       p.ib_bits[b] = take(words * 4);
       p.ib_rank[b] = take(words * 4);
-      p.ib_fib[b] = take((size_t)3 * p.s_cap * 4);
+      p.ib_fib[b] = take((size_t)p.s_cap * 16);
     }
     p.ib_count = take(2 * sizeof(uint32_t));
     p.ib_shared = take(words * 4);
@@ -308,6 +308,8 @@ Plan plan(const lbm_config& c) {
     p.ib_rowbits = take(P * rows * 4 + 4);
     p.ib_fcount = take(P * 4 + 4);
     p.ib_fslot = take(P * (size_t)p.fcap * 4 + 4);
+    p.ib_pu = take(P * (size_t)p.fcap * 16 + 16);
+    p.ib_pf = take(P * (size_t)p.fcap * 16 + 16);
     p.ib_wmark = take((size_t)p.n_wall * 3 * sizeof(double) + 8);
     p.ib_wdF = take((size_t)p.n_wall * 3 * sizeof(float) + 4);
     p.ib_wsup = take(p.n_wall ? words * 4 : 4);
@@ -599,7 +601,7 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     for (int b = 0; b < 2; ++b) {
       m.bits[b] = (uint32_t*)(base + p.ib_bits[b]);
       m.rank[b] = (uint32_t*)(base + p.ib_rank[b]);
-      m.fib[b] = (float*)(base + p.ib_fib[b]);
+      m.fib[b] = (float4*)(base + p.ib_fib[b]);
       m.count[b] = (uint32_t*)(base + p.ib_count) + b;
     }
     m.shared = (uint32_t*)(base + p.ib_shared);
@@ -615,6 +617,8 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     m.rowbits = (uint32_t*)(base + p.ib_rowbits);
     m.fcount = (uint32_t*)(base + p.ib_fcount);
     m.fslot = (uint32_t*)(base + p.ib_fslot);
+    m.pu = (float4*)(base + p.ib_pu);
+    m.pf = (float4*)(base + p.ib_pf);
     m.s_cap = p.s_cap;
     m.fcap = p.fcap;
     m.side = p.side;
@@ -853,7 +857,7 @@ namespace {
 // last collision: bitmask and rank words, and the spread force of its
 // slots component by component ([3][count] FP32).
 constexpr char kStateMagic[8] = {'L', 'B', 'M', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 constexpr int kStateVec3 = 10;  // [np][3] arrays in the particle block
 
 struct StateHeader {
@@ -897,7 +901,7 @@ bool state_has_support(const Ctx& c) { return c.cfg.bc == LBM_BC_IBM && c.step >
 
 size_t state_bytes(const StateHeader& h) {
   return sizeof(StateHeader) + h.pop_bytes + particle_block_bytes(h.np) + h.ibm_words * 8 +
-         (size_t)3 * h.ibm_count * 4;
+         (size_t)h.ibm_count * sizeof(float4);
 }
 
 int state_header(Ctx& c, StateHeader& h) {
@@ -985,12 +989,10 @@ int lbm_get_state(lbm_ctx* h, void* host, size_t bytes) {
     off += hd.ibm_words * 4;
     if (e == hipSuccess) e = hipMemcpyAsync(out + off, m.rank[b], hd.ibm_words * 4, hipMemcpyDeviceToHost, c.stream);
     off += hd.ibm_words * 4;
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-      if (hd.ibm_count)
-        e = hipMemcpyAsync(out + off, m.fib[b] + (size_t)k * m.s_cap, (size_t)hd.ibm_count * 4,
-                           hipMemcpyDeviceToHost, c.stream);
-      off += (size_t)hd.ibm_count * 4;
-    }
+    if (e == hipSuccess && hd.ibm_count)
+      e = hipMemcpyAsync(out + off, m.fib[b], (size_t)hd.ibm_count * sizeof(float4), hipMemcpyDeviceToHost,
+                         c.stream);
+    off += (size_t)hd.ibm_count * sizeof(float4);
   }
   if (e != hipSuccess) return LBM_E_HIP;
   return drain_errors(c);
@@ -1078,12 +1080,10 @@ int lbm_set_state(lbm_ctx* h, const void* host, size_t bytes) {
       if (e == hipSuccess) e = hipMemcpyAsync(m.rank[1], in + off, wb, hipMemcpyHostToDevice, c.stream);
       off += wb;
       if (e == hipSuccess) e = hipMemcpyAsync(m.count[1], &hd.ibm_count, 4, hipMemcpyHostToDevice, c.stream);
-      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-        if (hd.ibm_count)
-          e = hipMemcpyAsync(m.fib[1] + (size_t)k * m.s_cap, in + off, (size_t)hd.ibm_count * 4,
-                             hipMemcpyHostToDevice, c.stream);
-        off += (size_t)hd.ibm_count * 4;
-      }
+      if (e == hipSuccess && hd.ibm_count)
+        e = hipMemcpyAsync(m.fib[1], in + off, (size_t)hd.ibm_count * sizeof(float4), hipMemcpyHostToDevice,
+                           c.stream);
+      off += (size_t)hd.ibm_count * sizeof(float4);
       m.last = 1;
     }
   }

@@ -22,7 +22,7 @@ namespace {
 struct IbView {
   const uint32_t* bits;
   const uint32_t* rank;
-  const float* fib;  // [3][s_cap]
+  const float4* fib;  // [s_cap] (x, y, z, unused)
   uint32_t s_cap;
   const uint32_t* nobody;  // nodes without body force (outside a pipe), or null
 };
@@ -39,9 +39,10 @@ __device__ __forceinline__ void add_ib_force(const IbView& v, uint32_t n, float3
   if ((w >> b) & 1u) {
     const uint32_t s = v.rank[n >> 5] + __popc(w & ((1u << b) - 1u));
     if (s >= v.s_cap) return;  // capacity overflow is latched by the build
-    F.x += v.fib[s];
-    F.y += v.fib[(size_t)v.s_cap + s];
-    F.z += v.fib[2 * (size_t)v.s_cap + s];
+    const float4 f = v.fib[s];
+    F.x += f.x;
+    F.y += f.y;
+    F.z += f.z;
   }
 }
 

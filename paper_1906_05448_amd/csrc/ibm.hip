@@ -295,7 +295,7 @@ template <int STORE>
 __global__ void __launch_bounds__(256)
 k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, const uint32_t* __restrict__ nobody,
               const uint32_t* __restrict__ list, const uint32_t* __restrict__ count, uint32_t s_cap,
-              float4* __restrict__ us, float* __restrict__ fib) {
+              float4* __restrict__ us, float4* __restrict__ fib) {
   const uint32_t s = blockIdx.x * 256u + threadIdx.x;
   if (s >= *count || s >= s_cap) return;
   const uint32_t n = list[s];
@@ -316,9 +316,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
   }
   const float rho = 1.0f + drho;
   us[s] = make_float4((jx + 0.5f * F.x) / rho, (jy + 0.5f * F.y) / rho, (jz + 0.5f * F.z) / rho, rho);
-  fib[s] = 0.0f;
-  fib[(size_t)s_cap + s] = 0.0f;
-  fib[2 * (size_t)s_cap + s] = 0.0f;
+  fib[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // --------------------------------------------------------------- passes --
@@ -381,9 +379,9 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
            const double* __restrict__ dirs, int nmk, double r_l, double dV, int R_b, int side, Dims d,
            const uint32_t* __restrict__ rowbits, const uint32_t* __restrict__ fcount, uint32_t fcap,
            const uint32_t* __restrict__ fslot, const uint32_t* __restrict__ sh_slot, uint32_t sh_cap,
-           const float4* __restrict__ us, float* __restrict__ fib, uint32_t s_cap,
+           const float4* __restrict__ us, float4* __restrict__ fib, uint32_t s_cap,
            unsigned long long* __restrict__ sh_acc, double* __restrict__ F_ib, double* __restrict__ T_ib,
-           int first) {
+           float4* __restrict__ pu, float4* __restrict__ pf, int first, int last) {
   extern __shared__ uint32_t lds[];
   const int rows = side * side;
   uint32_t* rb = lds;
@@ -416,11 +414,15 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   __syncthreads();
   // Stage u = u* + f_IB / (2 rho) as the previous pass left it: all loads of
   // a round are issued before any is used. A shared node's slot comes from
-  // the shared-node table.
+  // the shared-node table. The spread force is zero before the first pass
+  // (the pre-pass cleared it). With the per-sphere copies (pu, pf non-null)
+  // the first pass gathers (u*, rho) once and keeps it in fslot order; later
+  // passes read the unshared nodes from the copies.
+  float4* const pu_p = pu ? pu + (size_t)p * fcap : nullptr;
+  float4* const pf_p = pf ? pf + (size_t)p * fcap : nullptr;
   for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
     uint32_t w[kStage], s[kStage];
-    float4 v[kStage];
-    float f[kStage][3];
+    float4 v[kStage], f[kStage];
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
@@ -433,9 +435,15 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     }
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
-      if (s[i] < s_cap) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      f[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (s[i] >= s_cap) continue;
+      if (pu_p && !first && !(w[i] & kSlotShared)) {
+        v[i] = pu_p[j];
+        f[i] = pf_p[j];
+      } else {
         v[i] = us[s[i]];
-        for (int k = 0; k < 3; ++k) f[i][k] = fib[(size_t)k * s_cap + s[i]];
+        if (!first) f[i] = fib[s[i]];
       }
     }
 #pragma unroll
@@ -447,10 +455,11 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
         uj[3 * j] = uj[3 * j + 1] = uj[3 * j + 2] = 0.0f;
         continue;
       }
+      if (pu_p && first && !(w[i] & kSlotShared)) pu_p[j] = v[i];
       const float h = 0.5f / v[i].w;
-      uj[3 * j] = v[i].x + f[i][0] * h;
-      uj[3 * j + 1] = v[i].y + f[i][1] * h;
-      uj[3 * j + 2] = v[i].z + f[i][2] * h;
+      uj[3 * j] = v[i].x + f[i].x * h;
+      uj[3 * j + 1] = v[i].y + f[i].y * h;
+      uj[3 * j + 2] = v[i].z + f[i].z * h;
     }
   }
   __syncthreads();
@@ -535,27 +544,35 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   }
   __syncthreads();
   // Write back: nodes of this sphere alone in place (no other workgroup reads
-  // or writes them), shared nodes into the exact accumulators.
+  // or writes them; into the per-sphere copy until the last pass), shared
+  // nodes into the exact accumulators.
   for (uint32_t j0 = 0; j0 < cnt; j0 += kWrite * kPassBlock) {
     uint32_t w[kWrite];
-    float old[kWrite][3];
+    float4 old[kWrite];
 #pragma unroll
     for (int i = 0; i < kWrite; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
       w[i] = j < cnt ? sl[j] : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int i = 0; i < kWrite; ++i)
-      if (!(w[i] & kSlotShared) && w[i] < s_cap)
-        for (int k = 0; k < 3; ++k) old[i][k] = fib[(size_t)k * s_cap + w[i]];
+    for (int i = 0; i < kWrite; ++i) {
+      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+      old[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (!first && !(w[i] & kSlotShared) && w[i] < s_cap) old[i] = pf_p ? pf_p[j] : fib[w[i]];
+    }
 #pragma unroll
     for (int i = 0; i < kWrite; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
       if (j >= cnt) continue;
       if (!(w[i] & kSlotShared)) {
         if (w[i] >= s_cap) continue;
-        for (int k = 0; k < 3; ++k)
-          fib[(size_t)k * s_cap + w[i]] = old[i][k] + (float)ldexp((double)acc[3 * j + k], -e);
+        const float4 fn = make_float4(old[i].x + (float)ldexp((double)acc[3 * j], -e),
+                                      old[i].y + (float)ldexp((double)acc[3 * j + 1], -e),
+                                      old[i].z + (float)ldexp((double)acc[3 * j + 2], -e), 0.0f);
+        if (pf_p && !last)
+          pf_p[j] = fn;
+        else
+          fib[w[i]] = fn;
       } else {
         const uint32_t q = w[i] & ~kSlotShared;
         if (q >= sh_cap) continue;
@@ -574,16 +591,20 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
 // accumulators return to zero.
 __global__ void __launch_bounds__(kBlock)
 k_ibm_fold(const uint32_t* __restrict__ sh_count, uint32_t sh_cap, const uint32_t* __restrict__ sh_slot,
-           unsigned long long* __restrict__ sh_acc, float* __restrict__ fib, uint32_t s_cap) {
+           unsigned long long* __restrict__ sh_acc, float4* __restrict__ fib, uint32_t s_cap) {
   const uint32_t n = min(*sh_count, sh_cap);
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const uint32_t s = sh_slot[i];
+    float add[3];
     for (int k = 0; k < 3; ++k) {
       unsigned long long* a = sh_acc + (size_t)k * sh_cap + i;
       const long long v = (long long)*a;
-      if (!v) continue;
-      *a = 0ull;
-      if (s < s_cap) fib[(size_t)k * s_cap + s] += (float)((double)v * 0x1p-50);
+      add[k] = (float)((double)v * 0x1p-50);
+      if (v) *a = 0ull;
+    }
+    if (s < s_cap && (add[0] != 0.0f || add[1] != 0.0f || add[2] != 0.0f)) {
+      const float4 o = fib[s];
+      fib[s] = make_float4(o.x + add[0], o.y + add[1], o.z + add[2], 0.0f);
     }
   }
 }
@@ -617,7 +638,7 @@ __device__ __forceinline__ void wall_stencil(const double* __restrict__ xm, uint
 
 __global__ void __launch_bounds__(kBlock)
 k_ibm_wall_interp(const double* __restrict__ xm, uint32_t nm, Dims d, const uint32_t* __restrict__ bits,
-                  const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float* __restrict__ fib,
+                  const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float4* __restrict__ fib,
                   uint32_t s_cap, float* __restrict__ dF) {
   const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
   if (l >= nm) return;
@@ -634,11 +655,12 @@ k_ibm_wall_interp(const double* __restrict__ xm, uint32_t nm, Dims d, const uint
         if (!support_slot(bits, rank, node_index(wrapi(b[0] + jx, d.nx), y, z, d.nx, d.ny), s) || s >= s_cap)
           continue;
         const float4 v = us[s];
+        const float4 f = fib[s];
         const float h = 0.5f / v.w;
         const float wt = w[0][jx] * wyz;
-        U[0] += wt * (v.x + fib[s] * h);
-        U[1] += wt * (v.y + fib[(size_t)s_cap + s] * h);
-        U[2] += wt * (v.z + fib[2 * (size_t)s_cap + s] * h);
+        U[0] += wt * (v.x + f.x * h);
+        U[1] += wt * (v.y + f.y * h);
+        U[2] += wt * (v.z + f.z * h);
       }
     }
   for (int k = 0; k < 3; ++k) dF[3 * (size_t)l + k] = -2.0f * U[k];
@@ -672,17 +694,22 @@ k_ibm_wall_spread(const double* __restrict__ xm, uint32_t nm, float dV, Dims d, 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restrict__ acc, float* __restrict__ fib,
+k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restrict__ acc, float4* __restrict__ fib,
                 uint32_t s_cap) {
   const uint32_t n = min(*count, s_cap);
-  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock)
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+    float add[3];
     for (int k = 0; k < 3; ++k) {
       unsigned long long* a = acc + (size_t)k * s_cap + s;
       const long long v = (long long)*a;
-      if (!v) continue;
-      *a = 0ull;
-      fib[(size_t)k * s_cap + s] += (float)((double)v * 0x1p-50);
+      add[k] = (float)((double)v * 0x1p-50);
+      if (v) *a = 0ull;
     }
+    if (add[0] != 0.0f || add[1] != 0.0f || add[2] != 0.0f) {
+      const float4 o = fib[s];
+      fib[s] = make_float4(o.x + add[0], o.y + add[1], o.z + add[2], 0.0f);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- kempe --
@@ -691,7 +718,7 @@ k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restri
 template <bool DENSE>
 __global__ void __launch_bounds__(kBlock)
 k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, const uint32_t* __restrict__ bits,
-        const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float* __restrict__ fib,
+        const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float4* __restrict__ fib,
         uint32_t s_cap, const float* __restrict__ ufield, double* __restrict__ Iu, double* __restrict__ IL) {
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
@@ -716,10 +743,11 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
       uint32_t slot;
       if (!support_slot(bits, rank, n, slot) || slot >= s_cap) continue;
       const float4 v = us[slot];
+      const float4 f = fib[slot];
       const float h = 0.5f / v.w;
-      u[0] = (double)(v.x + fib[slot] * h);
-      u[1] = (double)(v.y + fib[(size_t)s_cap + slot] * h);
-      u[2] = (double)(v.z + fib[2 * (size_t)s_cap + slot] * h);
+      u[0] = (double)(v.x + f.x * h);
+      u[1] = (double)(v.y + f.y * h);
+      u[2] = (double)(v.z + f.z * h);
     }
     s[0] += a * u[0];
     s[1] += a * u[1];
@@ -809,6 +837,10 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
   const size_t lds = pass_lds_bytes(c);
   const int passes = 1 + c.cfg.ibm_iters;
   const dim3 wgrid((m.n_wall + kBlock - 1) / kBlock);
+  // Per-sphere copies between passes, unless a wall's markers also act on
+  // the slot forces between the sphere passes.
+  float4* const pu = m.n_wall ? nullptr : m.pu;
+  float4* const pf = m.n_wall ? nullptr : m.pf;
   for (int k = 0; k < passes; ++k) {
     if (m.n_wall) {
       hipLaunchKernelGGL(k_ibm_wall_interp, wgrid, dim3(kBlock), 0, c.stream, m.wmark, m.n_wall, c.dims,
@@ -820,13 +852,13 @@ hipError_t launch_ibm_forcing_pass(const Ctx& c, const double* X, const double* 
       if (m.n_markers <= kPassBlock)
         hipLaunchKernelGGL(k_ibm_pass<1>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs,
                            m.n_markers, m.r_l, m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot,
-                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib,
-                           k == 0 ? 1 : 0);
+                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib, pu, pf,
+                           k == 0 ? 1 : 0, k == passes - 1 ? 1 : 0);
       else
         hipLaunchKernelGGL(k_ibm_pass<2>, dim3(c.np), dim3(kPassBlock), lds, c.stream, X, U, Om, m.dirs,
                            m.n_markers, m.r_l, m.dV, m.R_b, m.side, c.dims, m.rowbits, m.fcount, m.fcap, m.fslot,
-                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib,
-                           k == 0 ? 1 : 0);
+                           m.sh_slot, m.sh_cap, m.us, m.fib[m.cur], m.s_cap, m.sh_acc, c.P.F_ib, c.P.T_ib, pu, pf,
+                           k == 0 ? 1 : 0, k == passes - 1 ? 1 : 0);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_ibm_fold, dim3(1024), dim3(kBlock), 0, c.stream, m.sh_count, m.sh_cap, m.sh_slot,

@@ -227,7 +227,7 @@ struct IbmBufs {
   uint32_t* bits[2];     // [mask_words]
   uint32_t* rank[2];     // [mask_words]
   uint32_t* count[2];    // [1] support size
-  float* fib[2];         // [3][S_cap] spread force per slot
+  float4* fib[2];        // [S_cap] spread force per slot (x, y, z; w unused)
   uint32_t* shared;      // [mask_words] nodes in more than one sphere's support
   // Shared nodes: their forcing contributions of a pass are summed exactly
   // (64-bit fixed point, units 2^-50) apart from the slot forces, which the
@@ -245,6 +245,11 @@ struct IbmBufs {
   uint32_t* fcount;      // [P] forcing-support size per sphere
   uint32_t* fslot;       // [P][fcap] global slot of each forcing-support node,
                          // or kSlotShared | shared index at shared nodes
+  // Per-sphere copies, in fslot order, of (u*, rho) and of the spread force
+  // at the sphere's unshared forcing nodes between the passes of one step:
+  // read contiguously instead of gathered through the slot list.
+  float4* pu;            // [P][fcap]
+  float4* pf;            // [P][fcap]
   uint32_t s_cap;        // slots reserved
   uint32_t fcap;         // forcing-support nodes reserved per sphere
   int n_markers;         // markers per sphere
