@@ -180,7 +180,7 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const _Float16* rowp = A + (size_t)i * N + srow[i];
-    v[i] = pair_live ? *(const uint32_t*)(rowp + x0 + 2 * (int)lane) : 0u;
+    v[i] = pair_live ? __builtin_nontemporal_load((const uint32_t*)(rowp + x0 + 2 * (int)lane)) : 0u;
     // edge node: a vector load at a uniform address (scalar loads of the
     // same nodes measured 7.5% extra HBM reads: their lines are not served
     // from the copy the neighbouring segment's vector loads bring into L2)

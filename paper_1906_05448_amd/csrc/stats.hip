@@ -3,8 +3,9 @@
 // the rigid-body motion inside particles (zero in the pipe wall), and over
 // fluid nodes; mass and momentum of the fluid; local profiles binned by the
 // distance to the nearest surface (Sec. 3.2.1). Per-node arithmetic is FP64 on
-// the FP32 velocity field and every sum is reduced in a fixed order, so the
-// result does not change from run to run.
+// the FP32 velocity field and every sum is reduced in a fixed order (fixed
+// by the lattice and the device's size), so the result does not change from
+// run to run.
 //
 // Passes (u and rho extracted beforehand into idle population memory):
 //   key      per node: 0 pipe wall, p + 1 inside sphere p (lowest index),
@@ -13,16 +14,17 @@
 //            sphere lowers the keys of its box with atomicMin. The bin of
 //            the nearest surface is the smallest bin over surfaces, since
 //            floor is monotonic.
-//   sums     one wavefront per 64-node row segment, segments dealt out to a
-//            fixed grid: raw, masked and fluid sums and the histograms in one
-//            pass. The x neighbours come from the lanes beside (loaded only
-//            at the segment's ends), the y and z neighbours from coalesced
-//            row loads; the velocity of a node inside a sphere is
-//            U + Omega x (x - X) evaluated in FP64 where needed. Histogram
+//   sums     one wavefront walks a 64-node row segment along z (runs of z
+//            dealt out to a grid the device holds at once): raw, masked and
+//            fluid sums and the histograms in one pass. The rows at z - 1
+//            and z stay in registers, the x neighbours come from the lanes
+//            beside (loaded only at the segment's ends), the y neighbours
+//            from coalesced row loads; the velocity of a node inside a sphere
+//            is U + Omega x (x - X) evaluated in FP64 where needed. Histogram
 //            bins are summed per wavefront in LDS: the binned lanes are
 //            ranked among the lanes of the same bin, and rank by rank each
 //            adds its values with a plain read-modify-write, so a bin's sum
-//            follows lane order and then segment order: reproducible.
+//            follows lane order and then the wavefront's order of nodes.
 //   reduce   one workgroup per column adds the per-block partials in order
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -126,10 +128,58 @@ __device__ __forceinline__ void masked_at(uint32_t k, const float* v, int x, int
 
 constexpr int kSegWaves = kSBlock / 64;
 
+// Velocity and key of one node.
+struct Node {
+  float u[3];
+  uint32_t k;
+};
+
+__device__ __forceinline__ Node load_node(const float* __restrict__ u, const uint32_t* __restrict__ key, uint32_t N,
+                                          uint32_t n) {
+  Node v;
+  v.u[0] = u[n];
+  v.u[1] = u[(size_t)N + n];
+  v.u[2] = u[2 * (size_t)N + n];
+  v.k = key[n];
+  return v;
+}
+
+__device__ __forceinline__ Node shfl_node(const Node& v, int src) {
+  Node o;
+  for (int c = 0; c < 3; ++c) o.u[c] = __shfl(v.u[c], src, 64);
+  o.k = (uint32_t)__shfl((int)v.k, src, 64);
+  return o;
+}
+
+// Work of the sums pass: (64-node row segment, y) columns, each cut into
+// z runs so that there are about eight runs per wavefront (the runs are
+// dealt out in a fixed order; eight or more keep the last round short).
+struct ZPlan {
+  uint32_t segs, cols, nzc, zlen, items;
+};
+
+__host__ __device__ inline ZPlan zplan(int nx, int ny, int nz, uint32_t waves) {
+  ZPlan z;
+  z.segs = (uint32_t)(nx + 63) / 64u;
+  z.cols = z.segs * (uint32_t)ny;
+  uint32_t k = (8u * waves + z.cols - 1) / z.cols;
+  k = k < 1u ? 1u : (k > (uint32_t)nz ? (uint32_t)nz : k);
+  z.zlen = ((uint32_t)nz + k - 1) / k;
+  z.nzc = ((uint32_t)nz + z.zlen - 1) / z.zlen;
+  z.items = z.cols * z.nzc;
+  return z;
+}
+
+// One wavefront walks a 64-node row segment along z: the rows at z - 1 and
+// z stay in registers from the previous steps, so each step loads the row
+// at z + 1, the rows at y - 1 and y + 1 (which the wavefronts of the
+// neighbouring columns, on the same XCD, load as well) and the density; the
+// x neighbours come from the lanes beside, the nodes beyond the segment's
+// ends from two lanes' extra loads.
 __global__ void __launch_bounds__(kSBlock)
 k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key,
              const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om, Dims d,
-             double nu, int nbins, double* __restrict__ part, int stride) {
+             double nu, int nbins, double* __restrict__ part, int stride, ZPlan zp, uint32_t per_xcd) {
   extern __shared__ double hist_lds[];  // [wave][5][nbins]
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
   double* hw = hist_lds + (size_t)wv * 5 * nbins;
@@ -137,116 +187,112 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
   __builtin_amdgcn_wave_barrier();
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
-  const uint32_t segs = (uint32_t)(nx + 63) / 64u;
-  const uint32_t total = segs * (uint32_t)ny * (uint32_t)nz;
+  // XCD-major block order: the blocks of one XCD take consecutive columns
+  const uint32_t logical = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+  const uint32_t waves = gridDim.x * kSegWaves;
   double s[kStatScalars] = {};
   double umax2 = 0.0;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (uint32_t sg = blockIdx.x * kSegWaves + (uint32_t)wv; sg < total; sg += gridDim.x * kSegWaves) {
-    const uint32_t row = sg / segs;
-    const int x0 = (int)(sg - row * segs) * 64;
-    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+  for (uint32_t it = logical * kSegWaves + (uint32_t)wv; it < zp.items; it += waves) {
+    const uint32_t zc = it / zp.cols, col = it - zc * zp.cols;
+    const uint32_t yy = col / zp.segs;
+    const int x0 = (int)(col - yy * zp.segs) * 64, y = (int)yy;
+    const int z0 = (int)(zc * zp.zlen), z1 = min(nz, z0 + (int)zp.zlen);
     const int x = x0 + lane;
     const bool live = x < nx;
     const int xc = live ? x : nx - 1;
     const int xl = xc == 0 ? nx - 1 : xc - 1, xr = xc == nx - 1 ? 0 : xc + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-    auto at = [&](int xx, int yy, int zz) {
-      return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx + (uint32_t)xx;
+    const bool need_l = lane == 0, need_r = lane == 63 || xc == nx - 1;
+    auto at = [&](int xx, int yv, int zz) {
+      return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yv) * (uint32_t)nx + (uint32_t)xx;
     };
-    // nodes: centre, x+, x-, y+, y-, z+, z-; the x neighbours come from the
-    // lanes beside except at the segment's ends
-    const int nxs[7] = {xc, xr, xl, xc, xc, xc, xc}, nys[7] = {y, y, y, yp, ym, y, y},
-              nzs[7] = {z, z, z, z, z, zp, zm};
-    uint32_t kk[7];
-    float vf[7][3];
+    Node zm = load_node(u, key, N, at(xc, y, z0 == 0 ? nz - 1 : z0 - 1));
+    Node c0 = load_node(u, key, N, at(xc, y, z0));
+    for (int z = z0; z < z1; ++z) {
+      const int zpl = z == nz - 1 ? 0 : z + 1, zmi = z == 0 ? nz - 1 : z - 1;
+      // every load of the step before any use
+      const Node cz = load_node(u, key, N, at(xc, y, zpl));
+      const Node ymn = load_node(u, key, N, at(xc, ym, z));
+      const Node ypn = load_node(u, key, N, at(xc, yp, z));
+      const float r0 = rho[at(xc, y, z)];
+      Node hl, hr;
+      if (need_l) hl = load_node(u, key, N, at(xl, y, z));
+      if (need_r) hr = load_node(u, key, N, at(xr, y, z));
+      Node xpn = shfl_node(c0, min(lane + 1, 63));
+      Node xmn = shfl_node(c0, max(lane - 1, 0));
+      if (need_r) xpn = hr;
+      if (need_l) xmn = hl;
+      // neighbours: x+, x-, y+, y-, z+, z-
+      const Node* nb[6] = {&xpn, &xmn, &ypn, &ymn, &cz, &zm};
+      // central-difference gradients in FP64, raw and (where a neighbour is
+      // masked) masked
+      bool any_masked = false;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      if (j == 1 || j == 2) continue;
-      const uint32_t n = at(nxs[j], nys[j], nzs[j]);
-      kk[j] = key[n];
-      for (int c = 0; c < 3; ++c) vf[j][c] = u[(size_t)c * N + n];
-    }
-    const float r0 = rho[at(xc, y, z)];
-    kk[1] = (uint32_t)__shfl_down((int)kk[0], 1, 64);
-    kk[2] = (uint32_t)__shfl_up((int)kk[0], 1, 64);
-    for (int c = 0; c < 3; ++c) {
-      vf[1][c] = __shfl_down(vf[0][c], 1, 64);
-      vf[2][c] = __shfl_up(vf[0][c], 1, 64);
-    }
-    if (lane == 63 || xc == nx - 1) {
-      const uint32_t n = at(xr, y, z);
-      kk[1] = key[n];
-      for (int c = 0; c < 3; ++c) vf[1][c] = u[(size_t)c * N + n];
-    }
-    if (lane == 0) {
-      const uint32_t n = at(xl, y, z);
-      kk[2] = key[n];
-      for (int c = 0; c < 3; ++c) vf[2][c] = u[(size_t)c * N + n];
-    }
-    // central-difference gradients in FP64, raw and (where a neighbour is
-    // masked) masked
-    bool any_masked = false;
+      for (int j = 0; j < 6; ++j) any_masked = any_masked || nb[j]->k < kKeyFluid;
+      double G[3][3];
 #pragma unroll
-    for (int j = 1; j < 7; ++j) any_masked = any_masked || kk[j] < kKeyFluid;
-    double G[3][3];
+      for (int ax = 0; ax < 3; ++ax)
+        for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * ((double)nb[2 * ax]->u[c] - (double)nb[2 * ax + 1]->u[c]);
+      const double eps_raw = dissipation_of(G, nu);
+      double eps_m = eps_raw;
+      if (any_masked) {
+        const int nxs[6] = {xr, xl, xc, xc, xc, xc}, nys[6] = {y, y, yp, ym, y, y}, nzs[6] = {z, z, z, z, zpl, zmi};
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax)
-      for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * ((double)vf[1 + 2 * ax][c] - (double)vf[2 + 2 * ax][c]);
-    const double eps_raw = dissipation_of(G, nu);
-    double eps_m = eps_raw;
-    if (any_masked) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        double mp[3], mm[3];
-        masked_at(kk[1 + 2 * ax], vf[1 + 2 * ax], nxs[1 + 2 * ax], nys[1 + 2 * ax], nzs[1 + 2 * ax], X, U, Om, d, mp);
-        masked_at(kk[2 + 2 * ax], vf[2 + 2 * ax], nxs[2 + 2 * ax], nys[2 + 2 * ax], nzs[2 + 2 * ax], X, U, Om, d, mm);
-        for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * (mp[c] - mm[c]);
+        for (int ax = 0; ax < 3; ++ax) {
+          double mp[3], mm[3];
+          const int a = 2 * ax, b = 2 * ax + 1;
+          masked_at(nb[a]->k, nb[a]->u, nxs[a], nys[a], nzs[a], X, U, Om, d, mp);
+          masked_at(nb[b]->k, nb[b]->u, nxs[b], nys[b], nzs[b], X, U, Om, d, mm);
+          for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * (mp[c] - mm[c]);
+        }
+        eps_m = dissipation_of(G, nu);
       }
-      eps_m = dissipation_of(G, nu);
-    }
-    const double vx = vf[0][0], vy = vf[0][1], vz = vf[0][2];
-    const double ke = 0.5 * ((vx * vx + vy * vy) + vz * vz);
-    if (live) {
-      double vm[3];
-      masked_at(kk[0], vf[0], xc, y, z, X, U, Om, d, vm);
-      s[kStatKeRaw] += ke;
-      s[kStatEpsRaw] += eps_raw;
-      s[kStatKeMasked] += 0.5 * ((vm[0] * vm[0] + vm[1] * vm[1]) + vm[2] * vm[2]);
-      s[kStatEpsMasked] += eps_m;
-      if (kk[0] >= kKeyFluid) {
-        const double r = r0;
-        s[kStatNf] += 1.0;
-        s[kStatMass] += r;
-        s[kStatMomX] += r * vx;
-        s[kStatMomY] += r * vy;
-        s[kStatMomZ] += r * vz;
-        s[kStatKeFluid] += ke;
-        s[kStatBulk] += vz;
-        s[kStatEpsFluid] += eps_m;
-        umax2 = fmax(umax2, 2.0 * ke);
+      const double vx = c0.u[0], vy = c0.u[1], vz = c0.u[2];
+      const double ke = 0.5 * ((vx * vx + vy * vy) + vz * vz);
+      const uint32_t k0 = c0.k;
+      if (live) {
+        double vm[3];
+        masked_at(k0, c0.u, xc, y, z, X, U, Om, d, vm);
+        s[kStatKeRaw] += ke;
+        s[kStatEpsRaw] += eps_raw;
+        s[kStatKeMasked] += 0.5 * ((vm[0] * vm[0] + vm[1] * vm[1]) + vm[2] * vm[2]);
+        s[kStatEpsMasked] += eps_m;
+        if (k0 >= kKeyFluid) {
+          const double rr = r0;
+          s[kStatNf] += 1.0;
+          s[kStatMass] += rr;
+          s[kStatMomX] += rr * vx;
+          s[kStatMomY] += rr * vy;
+          s[kStatMomZ] += rr * vz;
+          s[kStatKeFluid] += ke;
+          s[kStatBulk] += vz;
+          s[kStatEpsFluid] += eps_m;
+          umax2 = fmax(umax2, 2.0 * ke);
+        }
       }
-    }
-    // histograms: fluid nodes within the profile range
-    const bool binned = live && kk[0] >= kKeyFluid && kk[0] != kKeyFar;
-    const uint32_t bin = kk[0] & 0x7FFFFFFFu;
-    unsigned long long todo = __ballot(binned);
-    if (todo == 0ull) continue;
-    uint32_t rank = 0, maxrank = 0;
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
-      const unsigned long long m = __ballot(binned && bin == b);
-      if (binned && bin == b) rank = (uint32_t)__popcll(m & lt);
-      maxrank = max(maxrank, (uint32_t)__popcll(m) - 1u);
-      todo &= ~m;
-    }
-    const double val[5] = {1.0, ke, eps_m, vz, vz * vz};
-    for (uint32_t t = 0; t <= maxrank; ++t) {
-      if (binned && rank == t)
-        for (int c = 0; c < 5; ++c) hw[(size_t)c * nbins + bin] += val[c];
-      __builtin_amdgcn_wave_barrier();
+      zm = c0;
+      c0 = cz;
+      // histograms: fluid nodes within the profile range
+      const bool binned = live && k0 >= kKeyFluid && k0 != kKeyFar;
+      const uint32_t bin = k0 & 0x7FFFFFFFu;
+      unsigned long long todo = __ballot(binned);
+      if (todo == 0ull) continue;
+      uint32_t rank = 0, maxrank = 0;
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
+        const unsigned long long m = __ballot(binned && bin == bb);
+        if (binned && bin == bb) rank = (uint32_t)__popcll(m & lt);
+        maxrank = max(maxrank, (uint32_t)__popcll(m) - 1u);
+        todo &= ~m;
+      }
+      const double val[5] = {1.0, ke, eps_m, vz, vz * vz};
+      for (uint32_t t = 0; t <= maxrank; ++t) {
+        if (binned && rank == t)
+          for (int c = 0; c < 5; ++c) hw[(size_t)c * nbins + bin] += val[c];
+        __builtin_amdgcn_wave_barrier();
+      }
     }
   }
   s[kStatUmax2] = 0.0;
@@ -322,11 +368,24 @@ hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t
   const Dims& d = c.dims;
   const double nu = (c.cfg.tau - 0.5) / 3.0;
   const int stride = kStatScalars + 5 * nbins;
-  const int grid = (int)std::min<uint32_t>((uint32_t)kStatGrid, (d.N + kSBlock - 1) / kSBlock);
-  hipError_t e = launch_stats_keys(c, key, nbins, width, X);
+  // The work is dealt out statically, so the grid is what the device holds
+  // at once (whole XCD groups, at most kStatGrid blocks): no block waits for
+  // another to finish. The sums then depend on the device's size but not on
+  // the run.
+  const size_t lds = (size_t)kSegWaves * 5 * std::max(nbins, 1) * sizeof(double);
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stats_sums, kSBlock, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_stats_sums, dim3(grid), dim3(kSBlock), (size_t)kSegWaves * 5 * std::max(nbins, 1) * sizeof(double),
-                     c.stream, u, rho, key, X, U, Om, d, nu, nbins, part, stride);
+  const uint32_t hold = std::max<uint32_t>(8u, (uint32_t)std::max(cus, 1) * (uint32_t)std::max(per_cu, 1));
+  const uint32_t per_xcd = std::min<uint32_t>((uint32_t)kStatGrid, hold) / 8u;
+  const int grid = (int)(8u * per_xcd);
+  const ZPlan zp = zplan(d.nx, d.ny, d.nz, (uint32_t)grid * kSegWaves);
+  e = launch_stats_keys(c, key, nbins, width, X);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_sums, dim3(grid), dim3(kSBlock), lds, c.stream, u, rho, key, X, U, Om, d, nu, nbins, part,
+                     stride, zp, per_xcd);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_stats_reduce, dim3(stride), dim3(kSBlock), 0, c.stream, part, grid, stride, out);
   return hipGetLastError();
