@@ -261,7 +261,7 @@ def train_corrector(torch, lbm):
     # network kernels alone: gradient (forward + backward) and forward of one
     # large batch, timed on the stream with no host work in between
     xb, tb = x[:batch].contiguous(), t[:batch].contiguous()
-    xf = x.repeat(8, 1).contiguous()
+    xf = x.repeat(64, 1).contiguous()
     e0.record(stream)
     for _ in range(50):
         if lbm.lib().lbm_mlp_gradient(net._h, lbm._dev(xb), lbm._dev(tb), batch, None, None) != 0:

@@ -32,9 +32,12 @@ struct TrainLds {
   float bred[kMBlock / 64][2 * kMlpHid + kMlpOutPad];
 };
 
+constexpr int kFwdTiles = 2;    // 16-sample tiles per wavefront in the forward kernel
+constexpr int kFBlock = 768;    // forward workgroup: 12 wavefronts share one copy of the weights
+
 struct FwdLds {
   MlpWeights w;
-  __bf16 h1[kMBlock / 64][16][kMlpHid], h2[kMBlock / 64][16][kMlpHid];
+  __bf16 h[kFBlock / 64][kFwdTiles][16][kMlpHid];
 };
 
 __device__ __forceinline__ void load_tile(const __bf16* __restrict__ X, int64_t n, int64_t cell, bf16x8 (&a)[3]) {
@@ -50,23 +53,28 @@ __device__ __forceinline__ void load_tile(const __bf16* __restrict__ X, int64_t 
   }
 }
 
-__global__ void __launch_bounds__(kMBlock)
+__global__ void __launch_bounds__(kFBlock)
 k_mlp_forward(const float* __restrict__ theta, const __bf16* __restrict__ X, int64_t n, float* __restrict__ Y) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   FwdLds& s = *(FwdLds*)lds_raw;
-  mlp_load_weights<kMBlock>(theta, s.w);
+  mlp_load_weights<kFBlock>(theta, s.w);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, grp = lane >> 4;
-  for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < n; c0 += (int64_t)gridDim.x * kChunk) {
-    const int64_t base = c0 + wave * 16;
-    bf16x8 a[3];
-    load_tile(X, n, base + col, a);
-    const f32x4 y = mlp_forward_tile(a, s.w, &s.h1[wave][0][0], &s.h2[wave][0][0], nullptr, nullptr);
+  constexpr int64_t kFwdChunk = (kFBlock / 64) * kFwdTiles * 16;
+  for (int64_t c0 = (int64_t)blockIdx.x * kFwdChunk; c0 < n; c0 += (int64_t)gridDim.x * kFwdChunk) {
+    const int64_t base = c0 + wave * kFwdTiles * 16;
+    bf16x8 a[kFwdTiles][3];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t cell = base + grp * 4 + e;
-      if (cell < n) Y[cell * kMlpOutPad + col] = y[e];
-    }
+    for (int t = 0; t < kFwdTiles; ++t) load_tile(X, n, base + t * 16 + col, a[t]);
+    f32x4 y[kFwdTiles];
+    mlp_forward_tiles<kFwdTiles>(a, s.w, &s.h[wave][0][0][0], y);
+#pragma unroll
+    for (int t = 0; t < kFwdTiles; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t cell = base + t * 16 + grp * 4 + e;
+        if (cell < n) Y[cell * kMlpOutPad + col] = y[t][e];
+      }
   }
 }
 
@@ -273,9 +281,9 @@ size_t mlp_forward_lds_bytes() { return sizeof(FwdLds); }
 
 hipError_t launch_mlp_forward(hipStream_t st, const float* theta, const uint16_t* X, int64_t n, float* Y) {
   if (n <= 0) return hipSuccess;
-  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  const int64_t chunks = (n + (kFBlock / 64) * kFwdTiles * 16 - 1) / ((kFBlock / 64) * kFwdTiles * 16);
   const int grid = (int)std::min<int64_t>(chunks, 2048);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kMBlock), sizeof(FwdLds), st, theta, (const __bf16*)X, n, Y);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kFBlock), sizeof(FwdLds), st, theta, (const __bf16*)X, n, Y);
   return hipGetLastError();
 }
 

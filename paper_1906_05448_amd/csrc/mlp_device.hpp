@@ -32,11 +32,17 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f3
 
 __device__ __forceinline__ bf16x8 lds8(const __bf16* p) { return *(const bf16x8*)p; }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// The activations end up in BF16 (8 significant bits), so the logistic
+// function takes the hardware exponential and reciprocal (about 1 ulp of
+// FP32 each) instead of an IEEE division: the transcendental unit, not the
+// matrix cores, bounds the forward pass.
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 
 // d/dz silu(z) = s + z s (1 - s), s = sigmoid(z)
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s + z * s * (1.0f - s);
 }
 
@@ -122,6 +128,91 @@ __device__ __forceinline__ f32x4 mlp_forward_tile(const bf16x8 (&a1)[3], const M
 #pragma unroll
   for (int e = 0; e < 4; ++e) y[e] += w.b3[col];
   return y;
+}
+
+// Inference on T 16-sample tiles at once by one wavefront: each weight
+// operand is read from LDS once for the T tiles, and the T independent
+// product chains hide one another's matrix-core and LDS latency. h: this
+// wave's [T][16][64] BF16 LDS rows, holding the first hidden layer and then,
+// once every lane has read it, the second. y receives y + b3 per tile in the
+// C layout of mlp_forward_tile.
+template <int T>
+__device__ __forceinline__ void mlp_forward_tiles(const bf16x8 (&a1)[T][3], const MlpWeights& w, __bf16* h,
+                                                  f32x4 (&y)[T]) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  constexpr int kTile = 16 * kMlpHid;
+  // layer 1
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    f32x4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      const bf16x8 b = lds8(&w.W1[n * 16 + col][ks * 32 + grp * 8]);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma(a1[t][ks], b, acc[t]);
+    }
+    const int j = n * 16 + col;
+    const float bj = w.b1[j];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h[t * kTile + (grp * 4 + e) * kMlpHid + j] = (__bf16)silu(acc[t][e] + bj);
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes done
+  __builtin_amdgcn_wave_barrier();
+  // layer 2: every A operand read before the outputs overwrite h
+  bf16x8 a2[T][2];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) a2[t][ks] = lds8(&h[t * kTile + col * kMlpHid + ks * 32 + grp * 8]);
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    f32x4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const bf16x8 b = lds8(&w.W2[n * 16 + col][ks * 32 + grp * 8]);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma(a2[t][ks], b, acc[t]);
+    }
+    const int j = n * 16 + col;
+    const float bj = w.b2[j];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h[t * kTile + (grp * 4 + e) * kMlpHid + j] = (__bf16)silu(acc[t][e] + bj);
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+  // layer 3
+  bf16x8 a3[T][2];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) a3[t][ks] = lds8(&h[t * kTile + col * kMlpHid + ks * 32 + grp * 8]);
+#pragma unroll
+  for (int t = 0; t < T; ++t) y[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const bf16x8 b = lds8(&w.W3[col][ks * 32 + grp * 8]);
+#pragma unroll
+    for (int t = 0; t < T; ++t) y[t] = mfma(a3[t][ks], b, y[t]);
+  }
+  const float b3 = w.b3[col];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[t][e] += b3;
+  // h is read again by the next call's first writes: keep this call's reads
+  // ahead of them
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace lbm
