@@ -275,6 +275,18 @@ def train_corrector(torch, lbm):
     e1.record(stream)
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 10
+    # the gradient on a large batch (about 1 M samples): the kernels' own
+    # throughput, which a 4 096-sample training batch does not fill
+    big = min(1 << 20, xf.shape[0])
+    xg = xf[:big].contiguous()
+    tg = t.repeat((big + t.shape[0] - 1) // t.shape[0], 1)[:big].contiguous()
+    e0.record(stream)
+    for _ in range(10):
+        if lbm.lib().lbm_mlp_gradient(net._h, lbm._dev(xg), lbm._dev(tg), big, None, None) != 0:
+            raise RuntimeError("lbm_mlp_gradient failed")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    grad_big_ms = e0.elapsed_time(e1) / 10
     xe, te, tbe = corrector.paired_samples(cfg, 7)
     y = net.forward(xe)
     nu = (cfg.tau - 0.5) / 3
@@ -287,16 +299,21 @@ def train_corrector(torch, lbm):
     e_ref, e_ibm, e_cor = eps(te + tbe), eps(tbe), eps(tbe + y)
     err_plain = float(torch.linalg.norm(e_ibm - e_ref) / torch.linalg.norm(e_ref))
     err_corr = float(torch.linalg.norm(e_cor - e_ref) / torch.linalg.norm(e_ref))
-    # matrix-core work actually issued per sample (padded shapes 96-64-64-16):
-    # forward 2 (96*64 + 64*64 + 64*16) flop, gradient about 3x that
+    # matrix-core work issued per sample (padded shapes 96-64-64-16): forward
+    # 2 (96*64 + 64*64 + 64*16) flop; the gradient adds the weight gradients
+    # (the same products) and the back-propagation through W3 (out padded to
+    # 32) and W2: 2 (32*64 + 64*64) more (the MFMA op counters give both)
     fwd_flop = 2 * (96 * 64 + 64 * 64 + 64 * 16)
+    grad_flop = 2 * fwd_flop + 2 * (32 * 64 + 64 * 64)
     peak = 2.5e15
     info = dict(train_samples=int(x.shape[0]), steps=steps, batch=batch,
                 train_samples_per_s=round(steps * batch / (train_ms * 1e-3), 1),
                 loss_first=round(float(losses[:10].mean()), 5), loss_last=round(float(losses[-100:].mean()), 5),
                 heldout_eps_rel_l2_plain_ibm=round(err_plain, 4), heldout_eps_rel_l2_corrected=round(err_corr, 4),
                 gradient_kernel_ms_batch4096=round(grad_ms, 4),
-                gradient_mfma_util=round(3 * fwd_flop * batch / (grad_ms * 1e-3) / peak, 5),
+                gradient_mfma_util=round(grad_flop * batch / (grad_ms * 1e-3) / peak, 5),
+                gradient_kernel_ms_large=round(grad_big_ms, 4), gradient_large_batch=int(big),
+                gradient_large_mfma_util=round(grad_flop * big / (grad_big_ms * 1e-3) / peak, 5),
                 forward_ms=round(fwd_ms, 4), forward_samples=int(xf.shape[0]),
                 forward_mfma_util=round(fwd_flop * xf.shape[0] / (fwd_ms * 1e-3) / peak, 5))
     log(f"bench: corrector {info}")

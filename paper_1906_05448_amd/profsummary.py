@@ -1,8 +1,14 @@
-"""Summarise a rocprofv3 results database (kernel trace) as a text table.
+"""Summarise rocprofv3 results databases as text tables.
 
     python -m paper_1906_05448_amd.profsummary <run_results.db> [title]
+    python -m paper_1906_05448_amd.profsummary --pmc <fetch_results.db> <write_results.db> [title]
 
-Prints one row per kernel: calls, total (ms) and average (us) duration, share.
+The first form (kernel trace) prints one row per kernel: calls, total (ms)
+and average (us) duration, share. The second (one FETCH_SIZE run, one
+WRITE_SIZE run of the same program) prints per kernel and grid the median
+KiB per dispatch of each counter and the bytes after scaling each counter by
+what it reads for the runtime's device-to-device copy kernel in the same run
+(a copy of known size: bench.py copies 2 GiB).
 """
 import sqlite3
 import sys
@@ -52,5 +58,52 @@ def main(argv):
         print(f"| `{short(name)}` | {calls} | {total / 1e3:.2f} | {avg:.1f} | {pct:.2f} |")
 
 
+def _pmc(db: str, counter: str) -> dict:
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, grid_size, value from counters_collection where counter_name = ?",
+                       (counter,)).fetchall()
+    con.close()
+    out = {}
+    for name, grid, v in rows:
+        out.setdefault((short(name), grid), []).append(v)
+    return out
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+COPY_BYTES = 2 * 1024 ** 3  # bench.py's calibration copy, read and written
+
+
+def pmc_main(argv):
+    fetch, write = _pmc(argv[2], "FETCH_SIZE"), _pmc(argv[3], "WRITE_SIZE")
+    title = argv[4] if len(argv) > 4 else argv[2]
+    copy_key = [k for k in fetch if "copyBuffer" in k[0]]
+    scale_f = scale_w = 1.0
+    if copy_key:
+        k = max(copy_key, key=lambda t: _median(fetch[t]))
+        scale_f = COPY_BYTES / (_median(fetch[k]) * 1024)
+        if k in write:
+            scale_w = COPY_BYTES / (_median(write[k]) * 1024)
+    print(f"# {title}\n")
+    print(f"Counter scale from the 2 GiB copy: FETCH_SIZE x {scale_f:.4f}, WRITE_SIZE x {scale_w:.4f}.\n")
+    print("| kernel | grid | dispatches | FETCH KiB | WRITE KiB | read GB | write GB |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    keys = sorted(fetch, key=lambda t: -_median(fetch[t]) - _median(write.get(t, [0])))
+    for k in keys:
+        if "copyBuffer" in k[0] or "fillBuffer" in k[0]:
+            continue
+        f = _median(fetch[k])
+        w = _median(write.get(k, [0]))
+        print(f"| `{k[0]}` | {k[1]} | {len(fetch[k])} | {f:.0f} | {w:.0f} | {f * 1024 * scale_f / 1e9:.3f} | "
+              f"{w * 1024 * scale_w / 1e9:.3f} |")
+
+
 if __name__ == "__main__":
-    main(sys.argv)
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc":
+        pmc_main(sys.argv)
+    else:
+        main(sys.argv)
