@@ -56,6 +56,10 @@ struct Dims {
   // Tiles of 128 x 4 nodes for the FP16 kernel that stages rows in LDS.
   uint32_t gx2, gy2, ntiles2, per_xcd2;
   FastDiv div_gx2, div_gy2;
+  // Row tiles of 512 x 1 nodes (nx a multiple of 512) for the same kernel
+  // with the segment edges passed between wavefronts.
+  uint32_t gxr, ntilesr, per_xcdr;
+  FastDiv div_gxr, div_ny;
 };
 
 inline Dims make_dims(int nx, int ny, int nz) {
@@ -70,6 +74,11 @@ inline Dims make_dims(int nx, int ny, int nz) {
   d.per_xcd2 = (d.ntiles2 + 7) / 8;
   d.div_gx2 = make_fastdiv(d.gx2);
   d.div_gy2 = make_fastdiv(d.gy2);
+  d.gxr = (uint32_t)(nx + 511) / 512;
+  d.ntilesr = d.gxr * (uint32_t)ny * (uint32_t)nz;
+  d.per_xcdr = (d.ntilesr + 7) / 8;
+  d.div_gxr = make_fastdiv(d.gxr);
+  d.div_ny = make_fastdiv((uint32_t)ny);
   return d;
 }
 
