@@ -46,16 +46,33 @@ k_corr_zone(const double* __restrict__ X, const double* __restrict__ rad, Dims d
   const double* Xp = X + 3 * p;
   const double re = excl_radius(rad[p], rd);
   const Box b = make_box(Xp, re);
-  const uint32_t total = b.count();
-  for (uint32_t i = threadIdx.x; i < total; i += kCBlock) {
-    int x, y, z;
-    box_node(b, i, d.nx, d.ny, d.nz, x, y, z);
-    if (sphere_d2(Xp, x, y, z, d) < re * re) {
+  // one thread per (row, run of 32 x positions): the nodes of a run that fall
+  // into one bitmask word are marked with one atomic
+  const int runs = (b.side[0] + 31) / 32;
+  const int items = runs * b.side[1] * b.side[2];
+  for (int it = threadIdx.x; it < items; it += kCBlock) {
+    const int rowi = it / runs, run = it - rowi * runs;
+    const int y = wrapi(b.lo[1] + rowi % b.side[1], d.ny), z = wrapi(b.lo[2] + rowi / b.side[1], d.nz);
+    const int i0 = run * 32, i1 = min(b.side[0], i0 + 32);
+    uint32_t word = 0xFFFFFFFFu, bits = 0u;
+    auto flush = [&]() {
+      if (bits) {
+        const uint32_t old = atomicOr(once + word, bits);
+        if (old & bits) atomicOr(twice + word, old & bits);
+      }
+    };
+    for (int ix = i0; ix < i1; ++ix) {
+      const int x = wrapi(b.lo[0] + ix, d.nx);
+      if (!(sphere_d2(Xp, x, y, z, d) < re * re)) continue;
       const uint32_t n = node_index(x, y, z, d.nx, d.ny);
-      const uint32_t bit = 1u << (n & 31u);
-      const uint32_t old = atomicOr(once + (n >> 5), bit);
-      if (old & bit) atomicOr(twice + (n >> 5), bit);
+      if ((n >> 5) != word) {
+        flush();
+        word = n >> 5;
+        bits = 0u;
+      }
+      bits |= 1u << (n & 31u);
     }
+    flush();
   }
 }
 
@@ -131,6 +148,22 @@ __device__ __forceinline__ float cell_feature(int f, const Cell& c, const float*
   return 0.0f;
 }
 
+// Feature f < 81 from its velocity value (feature_from), the others as
+// cell_feature gives them.
+__device__ __forceinline__ float cell_feature_from(int f, const Cell& c, float uval, const Dims& d, double u_rms) {
+  if (f < 81) {
+    const int o = f / 3, k = f - 3 * o;
+    const int xn = wrap1(c.x + o % 3 - 1, d.nx), yn = wrap1(c.y + (o / 3) % 3 - 1, d.ny),
+              zn = wrap1(c.z + o / 9 - 1, d.nz);
+    const double r0 = min_image((double)xn - c.X[0], d.nx), r1 = min_image((double)yn - c.X[1], d.ny),
+                 r2 = min_image((double)zn - c.X[2], d.nz);
+    const double rig = k == 0 ? c.U[0] + (c.W[1] * r2 - c.W[2] * r1)
+                              : (k == 1 ? c.U[1] + (c.W[2] * r0 - c.W[0] * r2) : c.U[2] + (c.W[0] * r1 - c.W[1] * r0));
+    return (float)(((double)uval - rig) / u_rms);
+  }
+  return cell_feature(f, c, nullptr, d, u_rms);
+}
+
 // Thread per (cell, group of 8 features): one 16-byte store.
 __global__ void __launch_bounds__(kCBlock)
 k_corr_features(const uint32_t* __restrict__ list, const uint32_t* __restrict__ plist, const uint32_t* __restrict__ count,
@@ -204,8 +237,27 @@ k_corr_stats(const float* __restrict__ theta, const uint32_t* __restrict__ list,
     __bf16* xrow = &s.xs[wave][col][0];
     if (valid) {
       const Cell c = make_cell(list[ci], plist[ci], X, U, Om, rad, d);
-#pragma unroll 1
-      for (int t = 0; t < 24; ++t) xrow[grp * 24 + t] = (__bf16)cell_feature(grp * 24 + t, c, u, d, u_rms);
+      // lane group g takes the stencil offsets g, g + 4, ...: every velocity
+      // load of the lane issued before the first is used
+      float raw[7][3];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const int o = grp + 4 * j;
+        raw[j][0] = raw[j][1] = raw[j][2] = 0.0f;
+        if (o < 27) {
+          const uint32_t nn = node_index(wrap1(c.x + o % 3 - 1, d.nx), wrap1(c.y + (o / 3) % 3 - 1, d.ny),
+                                         wrap1(c.z + o / 9 - 1, d.nz), d.nx, d.ny);
+          for (int k = 0; k < 3; ++k) raw[j][k] = u[(size_t)k * d.N + nn];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const int o = grp + 4 * j;
+        if (o < 27)
+          for (int k = 0; k < 3; ++k) xrow[3 * o + k] = (__bf16)cell_feature_from(3 * o + k, c, raw[j][k], d, u_rms);
+      }
+      if (grp == 3)
+        for (int f = 81; f < kMlpInPad; ++f) xrow[f] = (__bf16)cell_feature(f, c, nullptr, d, u_rms);
     } else {
 #pragma unroll 1
       for (int t = 0; t < 24; ++t) xrow[grp * 24 + t] = (__bf16)0.0f;

@@ -2,13 +2,15 @@
 
     python -m paper_1906_05448_amd.profsummary <run_results.db> [title]
     python -m paper_1906_05448_amd.profsummary --pmc <fetch_results.db> <write_results.db> [title]
+    python -m paper_1906_05448_amd.profsummary --counters <results.db> [title]
 
 The first form (kernel trace) prints one row per kernel: calls, total (ms)
 and average (us) duration, share. The second (one FETCH_SIZE run, one
 WRITE_SIZE run of the same program) prints per kernel and grid the median
 KiB per dispatch of each counter and the bytes after scaling each counter by
 what it reads for the runtime's device-to-device copy kernel in the same run
-(a copy of known size: bench.py copies 2 GiB).
+(a copy of known size: bench.py copies 2 GiB). The third prints, per kernel
+and grid, the median per dispatch of every counter the run collected.
 """
 import sqlite3
 import sys
@@ -102,8 +104,32 @@ def pmc_main(argv):
               f"{w * 1024 * scale_w / 1e9:.3f} |")
 
 
+def counters_main(argv):
+    con = sqlite3.connect(argv[2])
+    rows = con.execute("select kernel_name, grid_size, counter_name, dispatch_id, sum(value) from counters_collection "
+                       "group by kernel_name, grid_size, counter_name, dispatch_id").fetchall()
+    con.close()
+    title = argv[3] if len(argv) > 3 else argv[2]
+    vals, names = {}, []
+    for name, grid, cn, _, v in rows:
+        vals.setdefault((short(name), grid), {}).setdefault(cn, []).append(v)
+        if cn not in names:
+            names.append(cn)
+    names.sort()
+    print(f"# {title}\n")
+    print("Median per dispatch.\n")
+    print("| kernel | grid | dispatches | " + " | ".join(names) + " |")
+    print("|---|---:|---:|" + "---:|" * len(names))
+    for (k, g), cs in sorted(vals.items()):
+        n = max(len(v) for v in cs.values())
+        cells = [f"{_median(cs[c]):.0f}" if c in cs else "" for c in names]
+        print(f"| `{k}` | {g} | {n} | " + " | ".join(cells) + " |")
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc":
         pmc_main(sys.argv)
+    elif len(sys.argv) > 1 and sys.argv[1] == "--counters":
+        counters_main(sys.argv)
     else:
         main(sys.argv)
