@@ -131,7 +131,7 @@ def advance(lat, steps, every):
     return s, calls
 
 
-def step_bytes(bc, s, N, fluid, links, support):
+def step_bytes(bc, s, N, fluid, links, support, stats_per_step=0.0):
     """Algorithmic HBM bytes of one step (the method's traffic, not the
     implementation's): every fluid node's 19 populations read and written
     once; bounce-back adds the solid bitmask and 16 bytes of link data per
@@ -139,12 +139,16 @@ def step_bytes(bc, s, N, fluid, links, support):
     boundary adds per support node the pre-pass (19 populations read, the
     density and velocity written: 12 bytes), three forcing passes (12 bytes
     read, 24 bytes of force read-modify-write) and the force read by the
-    collision (12 bytes)."""
+    collision (12 bytes). Statistics calls inside the timed steps add, per
+    call and node, the velocity extraction (19 populations read, velocity
+    and density written: 16 bytes), the key written (4 bytes) and the sums'
+    reads of velocity, density and key (20 bytes), spread over the steps."""
+    stats = int(stats_per_step * (38 * s + 40) * N)
     if bc == "ibb":
-        return 38 * s * fluid + N // 8 + 16 * links
+        return 38 * s * fluid + N // 8 + 16 * links + stats
     if bc in ("ibm", "ibmc"):
-        return 38 * s * N + support * (19 * s + 12 + 3 * 36 + 12)
-    return 38 * s * N
+        return 38 * s * N + support * (19 * s + 12 + 3 * 36 + 12) + stats
+    return 38 * s * N + stats
 
 
 def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=None):
@@ -525,7 +529,8 @@ def main():
     N = n ** 3
     for (bc, st), name in zip(variants, [f"{b}-{s_}" for b, s_ in variants]):
         r = results[name]
-        b = step_bytes(bc, 4 if st == "f32" else 2, N, N - r["solid_nodes"], r["links"], r["support_nodes"])
+        b = step_bytes(bc, 4 if st == "f32" else 2, N, N - r["solid_nodes"], r["links"], r["support_nodes"],
+                       r["stats_calls_timed"] / args.steps)
         r["step_alg_bytes"] = b
         r["step_roofline_frac"] = b / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     out = {
@@ -555,7 +560,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(head_name, n, args.particles),
-                     "kernel": "k_stream_collide_seg" if hs == "f16s" and n % 2 == 0 else "k_stream_collide",
+                     "kernel": ("k_stream_collide_row" if n % 512 == 0 else "k_stream_collide_seg" if n % 2 == 0
+                                else "k_stream_collide") if hs == "f16s"
+                               else ("k_stream_collide_row32" if n % 512 == 0 else "k_stream_collide"),
                      "alg_bytes_per_launch": head["alg_bytes"],
                      "avg_launch_ms": round(head["kernel_avg_ms"], 4)},
         "step_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
@@ -563,7 +570,8 @@ def main():
                           "achieved": round(head["step_alg_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9, 1),
                           "frac": round(head["step_roofline_frac"], 4),
                           "model": "whole step: fused stream-collide over the fluid nodes plus the boundary "
-                                   "treatment's algorithmic bytes (bench.step_bytes)"},
+                                   "treatment's algorithmic bytes and the timed statistics calls' share "
+                                   "(bench.step_bytes)"},
         "stream_copy": copy,
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in results.items()},
