@@ -65,11 +65,11 @@ def test_dense_minimum_box(store):
 def test_dense_fp16_row_lengths(shape):
     # FP16 storage over row lengths around the 64-node tile: an odd row (71),
     # one node past two tiles (130), a row shorter than a wavefront (6) and
-    # exactly two tiles (128); rows of 512, 1024 and 1536 nodes take the
-    # kernel whose workgroup holds 512 nodes of a row and passes the segment
-    # ends between its wavefronts (one workgroup per row, periodic inside it;
-    # two and three per row, ends loaded at the workgroup boundaries); the
-    # x-wrap of the shifted directions is exercised at both ends of every row.
+    # exactly two tiles (128); a row of 512 nodes takes the kernel whose
+    # workgroup holds the whole row and passes the segment ends between its
+    # wavefronts (periodic inside it), rows of 1024 and 1536 the tiled one;
+    # the x-wrap of the shifted directions is exercised at both ends of every
+    # row.
     F = (2e-5, 1e-5, -1e-5)
     u0 = synth.random_velocity(shape, 0.05, seed=21)
     r0 = synth.random_density(shape, 0.01, seed=22)

@@ -1,9 +1,9 @@
 """Rows of 512 nodes take the stream-collide kernels whose workgroup holds
-512 nodes of one row (FP32 and FP16 storage) and passes the segment ends
-between its wavefronts. Parity with the FP64 oracle on thin boxes with
-512-, 1024- and 1536-node rows: the plain update, and moving spheres with
-bounce-back and with the immersed boundary (whose force lookup the kernels
-carry)."""
+the whole row (FP32 and FP16 storage) and passes the segment ends between
+its wavefronts; longer rows (1024, 1536) take the tiled kernels. Parity
+with the FP64 oracle on thin boxes: the plain update, and moving spheres
+with bounce-back and with the immersed boundary (whose force lookup the
+kernels carry)."""
 import numpy as np
 import pytest
 
