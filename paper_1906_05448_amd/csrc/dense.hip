@@ -238,13 +238,12 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   if (bad) atomicOr(err, kErrUnstable);
 }
 
-// The same update with a workgroup holding 512 nodes of one row (nx a
-// multiple of 512): its four wavefronts take consecutive 128-node segments,
-// and each hands its first and last node to its neighbours through LDS, so
-// only the workgroup's two ends are loaded from memory, and none when the
-// workgroup is the whole row (then periodic within it). Consecutive
+// The same update with a workgroup holding one whole row of 512 nodes: its
+// four wavefronts take consecutive 128-node segments, and each hands its
+// first and last node to its neighbours through LDS (periodic within the
+// workgroup), so no segment end is loaded from memory. Consecutive
 // workgroups of an XCD take consecutive rows, which share their source rows
-// in L2. 1.926 -> 1.853 ms at 512^3 (5.50 TB/s).
+// in L2. 1.926 -> 1.82-1.86 ms at 512^3 (5.5-5.6 TB/s).
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, Dims d, MrtRates r, float3 F0,
@@ -252,10 +251,8 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   __shared__ uint32_t seg_all[4][kQ][kSegRow];
   __shared__ uint16_t tail_all[4][kQ];
   const uint32_t b = blockIdx.x;
-  const uint32_t logical = (b & 7u) * d.per_xcdr + (b >> 3);
-  if (logical >= d.ntilesr) return;  // the whole workgroup
-  const uint32_t rowi = fast_div(d.div_gxr, logical);
-  const uint32_t bx = logical - rowi * d.gxr;
+  const uint32_t rowi = (b & 7u) * d.per_xcdr + (b >> 3);  // nx = 512: one workgroup per row
+  if (rowi >= d.ntilesr) return;  // the whole workgroup
   const uint32_t bz = fast_div(d.div_ny, rowi);
   const uint32_t lane = threadIdx.x & 63u;
   const int wv = (int)(threadIdx.x >> 6);
@@ -265,14 +262,10 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   uint16_t* tail = tail_all[wv];
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
-  const int x0 = (int)bx * 512 + wv * kSegW;
-  constexpr int w = kSegW;  // nx is a multiple of 512: every segment is full
-  // the row's other wavefronts: left and right neighbours in x (within the
-  // workgroup; at the workgroup's ends only when the workgroup is the whole
-  // row, which is then periodic)
-  const bool whole_row = d.gxr == 1u;
-  const int wl = wv > 0 ? wv - 1 : (whole_row ? 3 : -1);
-  const int wr = wv < 3 ? wv + 1 : (whole_row ? 0 : -1);
+  const int x0 = wv * kSegW;
+  constexpr int w = kSegW;
+  // the wavefronts of the left and right segments (periodic within the row)
+  const int wl = (wv + 3) & 3, wr = (wv + 1) & 3;
   auto row = [&](int yy, int zz) -> uint32_t { return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx; };
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
@@ -282,37 +275,20 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   // source row (y - c_iy, z - c_iz) of direction i
   const uint32_t srow[kQ] = {r00, r00, rm0, r0m, rm0, rp0, r0m, r0p, rmm, rmp,
                              r00, rp0, r0p, rp0, rm0, r0p, r0m, rpp, rpm};
-  // the node left of the segment and the one right of it (periodic)
-  const uint32_t xl = (uint32_t)(x0 == 0 ? nx - 1 : x0 - 1);
-  const uint32_t xr = (uint32_t)(x0 + w >= nx ? 0 : x0 + w);
   constexpr bool pair_live = true;
 
-  // stage: every load of the segment issued before the first LDS write;
-  // the end nodes come from the neighbouring wavefronts' segments, loaded
-  // only at the ends of a workgroup that is not the whole row
+  // stage: every load of the segment issued before the first LDS write
   uint32_t v[kQ];
-  uint16_t e[kQ];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const _Float16* rowp = A + (size_t)i * N + srow[i];
-    v[i] = __builtin_nontemporal_load((const uint32_t*)(rowp + x0 + 2 * (int)lane));
-    e[i] = 0;
-    if (cx_of(i) > 0 && wl < 0) e[i] = *(const uint16_t*)(rowp + xl);
-    if (cx_of(i) < 0 && wr < 0) e[i] = *(const uint16_t*)(rowp + xr);
-  }
+  for (int i = 0; i < kQ; ++i)
+    v[i] = __builtin_nontemporal_load((const uint32_t*)(A + (size_t)i * N + srow[i] + x0 + 2 * (int)lane));
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];  // halves 2 + 2 lane, 3 + 2 lane
     // node x0 + 127 is the right neighbour's x0 - 1; node x0 the left
     // neighbour's x0 + w
-    if (cx_of(i) > 0) {
-      if (lane == 63u && wr >= 0) ((uint16_t*)seg_all[wr][i])[1] = (uint16_t)(v[i] >> 16);
-      if (lane == 0u && wl < 0) ((uint16_t*)seg[i])[1] = e[i];
-    }
-    if (cx_of(i) < 0) {
-      if (lane == 0u && wl >= 0) ((uint16_t*)seg_all[wl][i])[2 + w] = (uint16_t)(v[i] & 0xFFFFu);
-      if (lane == 0u && wr < 0) ((uint16_t*)seg[i])[2 + w] = e[i];
-    }
+    if (cx_of(i) > 0 && lane == 63u) ((uint16_t*)seg_all[wr][i])[1] = (uint16_t)(v[i] >> 16);
+    if (cx_of(i) < 0 && lane == 0u) ((uint16_t*)seg_all[wl][i])[2 + w] = (uint16_t)(v[i] & 0xFFFFu);
   }
   __syncthreads();  // the neighbours' end nodes are in place
 
