@@ -356,19 +356,53 @@ __device__ __forceinline__ int spread_exponent(float max_dF, float dV) {
   return min(kShUnitExp, max(0, 30 - ex));
 }
 
-// Largest value of a non-negative float over the block (every thread gets it).
-__device__ __forceinline__ float block_max_nonneg(float v) {
-  __shared__ uint32_t part[kPassBlock / 64];
-  uint32_t b = __float_as_uint(v);
+// A marker of the pass: stencil base (box-local, packed 10 bits per axis)
+// and the offsets t = x_l - floor(x_l) per axis.
+struct MarkerPos {
+  uint32_t base;
+  float t[3];
+};
+
+__device__ __forceinline__ void marker_pos(const double* X, const double* dir, double r_l, const int lo[3],
+                                           MarkerPos& m) {
+  m.base = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double xl = X[k] + r_l * dir[k];
+    const double fl = floor(xl);
+    m.t[k] = (float)(xl - fl);
+    m.base |= (uint32_t)((int)fl - 1 - lo[k]) << (10 * k);
+  }
+}
+
+// The four Peskin weights of the points floor(x) - 1 .. floor(x) + 2 for the
+// offset t = x - floor(x) in [0, 1): their distances 1 + t, t, 1 - t, 2 - t
+// all take the same square root sqrt(1 + 4t - 4t^2), so one root gives all
+// four (they add up to one).
+__device__ __forceinline__ void peskin4(float t, float (&w)[4]) {
+  const float S = sqrtf(1.0f + 4.0f * t * (1.0f - t));
+  const float a = 3.0f - 2.0f * t, b = 1.0f + 2.0f * t;
+  w[0] = (a - S) * 0.125f;
+  w[1] = (a + S) * 0.125f;
+  w[2] = (b + S) * 0.125f;
+  w[3] = (b - S) * 0.125f;
+}
+
+// Slot-list entries j0 + threadIdx.x + i kPassBlock of a sphere and their
+// slots (a shared node's from the shared-node table); 0xFFFFFFFF past the
+// list.
+__device__ __forceinline__ void stage_slots(const uint32_t* __restrict__ slots, const uint32_t* __restrict__ sh_slot,
+                                            uint32_t sh_cap, uint32_t cnt, uint32_t fcap, uint32_t j0,
+                                            uint32_t (&w)[kStage], uint32_t (&s)[kStage]) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) b = max(b, (uint32_t)__shfl_xor((int)b, o, 64));
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = b;
-  __syncthreads();
-  uint32_t m = 0;
+  for (int i = 0; i < kStage; ++i) {
+    const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
+    w[i] = j < cnt && j < fcap ? slots[j] : 0xFFFFFFFFu;
+  }
 #pragma unroll
-  for (int w = 0; w < kPassBlock / 64; ++w) m = max(m, part[w]);
-  __syncthreads();
-  return __uint_as_float(m);
+  for (int i = 0; i < kStage; ++i) {
+    const uint32_t q = w[i] & ~kSlotShared;
+    s[i] = !(w[i] & kSlotShared) ? w[i] : (w[i] != 0xFFFFFFFFu && q < sh_cap ? sh_slot[q] : 0xFFFFFFFFu);
+  }
 }
 
 template <int MPT>
@@ -383,6 +417,8 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
            unsigned long long* __restrict__ sh_acc, double* __restrict__ F_ib, double* __restrict__ T_ib,
            float4* __restrict__ pu, float4* __restrict__ pf, int first, int last) {
   extern __shared__ uint32_t lds[];
+  __shared__ double red_f[kPassBlock / 64][6];  // per-wavefront force and torque sums
+  __shared__ uint32_t red_m[kPassBlock / 64];   // per-wavefront largest |dF|
   const int rows = side * side;
   uint32_t* rb = lds;
   uint32_t* rp = rb + rows;
@@ -395,6 +431,25 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   int lo[3];
   ibm_box_lo(Xp, R_b, lo);
   const uint32_t cnt = fcount[p];
+  // The marker positions first: their loads and FP64 arithmetic overlap the
+  // staging loads and the row scan below.
+  MarkerPos mk[MPT];
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    const int l = threadIdx.x + m * kPassBlock;
+    if (l < nmk) marker_pos(Xp, dirs + 3 * l, r_l, lo, mk[m]);
+  }
+  // Stage u = u* + f_IB / (2 rho) as the previous pass left it: all loads of
+  // a round are issued before any is used, the first round's slot-list
+  // entries before the row scan. A shared node's slot comes from the shared-node table. The spread
+  // force is zero before the first pass (the pre-pass cleared it). With the
+  // per-sphere copies (pu, pf non-null) the first pass gathers (u*, rho) once
+  // and keeps it in fslot order; later passes read the unshared nodes from
+  // the copies.
+  float4* const pu_p = pu ? pu + (size_t)p * fcap : nullptr;
+  float4* const pf_p = pf ? pf + (size_t)p * fcap : nullptr;
+  uint32_t w[kStage], s[kStage];
+  stage_slots(slots, sh_slot, sh_cap, cnt, fcap, 0, w, s);
   // row bits and their exclusive prefix (box raster order = slot list order)
   uint32_t base = 0;
   for (int r0 = 0; r0 < rows; r0 += kPassBlock) {
@@ -411,28 +466,9 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   // A forcing support beyond the LDS capacity was latched as an error when it
   // was built; skip the sphere rather than index past the buffers.
   if (base > fcap || base != cnt) return;
-  __syncthreads();
-  // Stage u = u* + f_IB / (2 rho) as the previous pass left it: all loads of
-  // a round are issued before any is used. A shared node's slot comes from
-  // the shared-node table. The spread force is zero before the first pass
-  // (the pre-pass cleared it). With the per-sphere copies (pu, pf non-null)
-  // the first pass gathers (u*, rho) once and keeps it in fslot order; later
-  // passes read the unshared nodes from the copies.
-  float4* const pu_p = pu ? pu + (size_t)p * fcap : nullptr;
-  float4* const pf_p = pf ? pf + (size_t)p * fcap : nullptr;
   for (uint32_t j0 = 0; j0 < cnt; j0 += kStage * kPassBlock) {
-    uint32_t w[kStage], s[kStage];
+    if (j0) stage_slots(slots, sh_slot, sh_cap, cnt, fcap, j0, w, s);
     float4 v[kStage], f[kStage];
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) {
-      const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
-      w[i] = j < cnt ? slots[j] : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) {
-      const uint32_t q = w[i] & ~kSlotShared;
-      s[i] = !(w[i] & kSlotShared) ? w[i] : (w[i] != 0xFFFFFFFFu && q < sh_cap ? sh_slot[q] : 0xFFFFFFFFu);
-    }
 #pragma unroll
     for (int i = 0; i < kStage; ++i) {
       const uint32_t j = j0 + threadIdx.x + i * kPassBlock;
@@ -470,24 +506,27 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   double fsum[6] = {0, 0, 0, 0, 0, 0};  // force and torque on the particle
   float dF[MPT][3];
   float dmax = 0.0f;
-  Stencil st[MPT];
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
     const int l = threadIdx.x + m * kPassBlock;
     dF[m][0] = dF[m][1] = dF[m][2] = 0.0f;
     if (l >= nmk) continue;
-    marker_stencil(Xp, dirs + 3 * l, r_l, lo, st[m]);
-    const uint32_t below = (1u << st[m].bx) - 1u;
+    const int bx = (int)(mk[m].base & 1023u), by = (int)((mk[m].base >> 10) & 1023u), bz = (int)(mk[m].base >> 20);
+    float wx[4], wy[4], wz[4];
+    peskin4(mk[m].t[0], wx);
+    peskin4(mk[m].t[1], wy);
+    peskin4(mk[m].t[2], wz);
+    const uint32_t below = (1u << bx) - 1u;
     float Ul[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int jy = q & 3, jz = q >> 2;
-      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+      const int row = (by + jy) + side * (bz + jz);
       const uint32_t j0 = rp[row] + __popc(rb[row] & below);
-      const float wyz = st[m].wy[jy] * st[m].wz[jz];
+      const float wyz = wy[jy] * wz[jz];
 #pragma unroll
       for (int jx = 0; jx < 4; ++jx) {
-        const float w = st[m].wx[jx] * wyz;
+        const float w = wx[jx] * wyz;
         const uint32_t j = j0 + jx;
         Ul[0] += w * uj[3 * j];
         Ul[1] += w * uj[3 * j + 1];
@@ -508,33 +547,66 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     fsum[4] -= arm[2] * f[0] - arm[0] * f[2];
     fsum[5] -= arm[0] * f[1] - arm[1] * f[0];
   }
-  // the particle's force and torque are complete once every marker has
-  // interpolated
-  block_sum_first<kPassBlock, 6>(fsum);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) {
-      F_ib[3 * p + k] = (first ? 0.0 : F_ib[3 * p + k]) + fsum[k];
-      T_ib[3 * p + k] = (first ? 0.0 : T_ib[3 * p + k]) + fsum[3 + k];
+  // Per wavefront: the six sums by a fixed butterfly that leaves sum k in
+  // lanes 8k .. 8k+7 (each exchange step halves the values a lane carries),
+  // and the largest |dF|.
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v4[4], v2[2];
+    const bool h = lane & 32, g = lane & 16, o = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double lo_v = fsum[i], hi_v = i < 2 ? fsum[4 + i] : 0.0;
+      v4[i] = (h ? hi_v : lo_v) + __shfl_xor(h ? lo_v : hi_v, 32, 64);
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) v2[i] = (g ? v4[2 + i] : v4[i]) + __shfl_xor(g ? v4[i] : v4[2 + i], 16, 64);
+    double v1 = (o ? v2[1] : v2[0]) + __shfl_xor(o ? v2[0] : v2[1], 8, 64);
+    v1 += __shfl_xor(v1, 4, 64);
+    v1 += __shfl_xor(v1, 2, 64);
+    v1 += __shfl_xor(v1, 1, 64);
+    uint32_t mb = __float_as_uint(dmax);
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) mb = max(mb, (uint32_t)__shfl_xor((int)mb, sh, 64));
+    if ((lane & 7) == 0 && (lane >> 3) < 6) red_f[wv][lane >> 3] = v1;
+    if (lane == 0) red_m[wv] = mb;
   }
-  // every marker has read uj once the maximum is known (block barriers)
-  const int e = spread_exponent(block_max_nonneg(dmax), dVf);
+  __syncthreads();  // every marker has read uj; the partials are complete
+  uint32_t mb = 0;
+#pragma unroll
+  for (int wv = 0; wv < kPassBlock / 64; ++wv) mb = max(mb, red_m[wv]);
+  const int e = spread_exponent(__uint_as_float(mb), dVf);
+  // the particle's force and torque: the wavefront partials in index order
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kPassBlock / 64; ++wv) t += red_f[wv][threadIdx.x];
+    double* out = threadIdx.x < 3 ? F_ib + 3 * p + threadIdx.x : T_ib + 3 * p + (threadIdx.x - 3);
+    *out = (first ? 0.0 : *out) + t;
+  }
   for (uint32_t j = threadIdx.x; j < 3 * cnt; j += kPassBlock) acc[j] = 0;
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
     const int l = threadIdx.x + m * kPassBlock;
     if (l >= nmk) continue;
-    const uint32_t below = (1u << st[m].bx) - 1u;
+    // the weights again from the offsets (fewer registers held across the
+    // barriers than keeping all twelve)
+    const int bx = (int)(mk[m].base & 1023u), by = (int)((mk[m].base >> 10) & 1023u), bz = (int)(mk[m].base >> 20);
+    float wx[4], wy[4], wz[4];
+    peskin4(mk[m].t[0], wx);
+    peskin4(mk[m].t[1], wy);
+    peskin4(mk[m].t[2], wz);
+    const uint32_t below = (1u << bx) - 1u;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int jy = q & 3, jz = q >> 2;
-      const int row = (st[m].by + jy) + side * (st[m].bz + jz);
+      const int row = (by + jy) + side * (bz + jz);
       const uint32_t j0 = rp[row] + __popc(rb[row] & below);
-      const float wyz = st[m].wy[jy] * st[m].wz[jz] * dVf;
+      const float wyz = wy[jy] * wz[jz] * dVf;
 #pragma unroll
       for (int jx = 0; jx < 4; ++jx) {
-        const float w = st[m].wx[jx] * wyz;
+        const float w = wx[jx] * wyz;
         const uint32_t j = j0 + jx;
         atomicAdd(&acc[3 * j], __float2int_rn(ldexpf(dF[m][0] * w, e)));
         atomicAdd(&acc[3 * j + 1], __float2int_rn(ldexpf(dF[m][1] * w, e)));
