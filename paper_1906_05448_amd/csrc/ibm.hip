@@ -787,46 +787,137 @@ k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restri
 // ---------------------------------------------------------------- kempe --
 // Sum alpha u and sum alpha (x - X) x u per sphere; u from the support
 // slots (u* + f_IB / (2 rho)) or, before the first step, a dense field.
+//
+// Only cells whose centre lies within r + sqrt(3)/2 of the centre have a
+// fraction above zero, so the box rows that reach that ball are listed
+// first (in box order), then every thread takes whole rows and visits just
+// the x range of the ball in each, kKempeBatch cells at a time with their
+// loads in flight together. A cell deeper than sqrt(3)/2 inside the surface
+// has fraction 1 from its centre distance; the others take the eight-corner
+// fraction. Rows and cells are taken in a fixed order, so the sums are
+// reproducible.
+constexpr int kKempeBatch = 4;
+constexpr int kKempeRows = 4096;  // box rows: (2 (r + 1) + 2)^2 for r <= 28
+
+// u at K cells (a[k] > 0 only); a cell outside the support gets a[k] = 0.
+template <bool DENSE, int K>
+__device__ __forceinline__ void kempe_u(const uint32_t (&n)[K], double (&a)[K], float (&u)[K][3], const Dims& d,
+                                        const uint32_t* __restrict__ bits, const uint32_t* __restrict__ rank,
+                                        const float4* __restrict__ us, const float4* __restrict__ fib, uint32_t s_cap,
+                                        const float* __restrict__ ufield) {
+  if (DENSE) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      u[k][0] = u[k][1] = u[k][2] = 0.0f;
+      if (!(a[k] > 0.0)) continue;
+      u[k][0] = ufield[n[k]];
+      u[k][1] = ufield[(size_t)d.N + n[k]];
+      u[k][2] = ufield[2 * (size_t)d.N + n[k]];
+    }
+    return;
+  }
+  uint32_t wb[K], wr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    wb[k] = wr[k] = 0u;
+    if (!(a[k] > 0.0)) continue;
+    wb[k] = bits[n[k] >> 5];
+    wr[k] = rank[n[k] >> 5];
+  }
+  float4 v[K], f[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t bit = n[k] & 31u;
+    const uint32_t slot = wr[k] + __popc(wb[k] & ((1u << bit) - 1u));
+    v[k] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    f[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (!((wb[k] >> bit) & 1u) || slot >= s_cap) {
+      a[k] = 0.0;
+      continue;
+    }
+    v[k] = us[slot];
+    f[k] = fib[slot];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float h = 0.5f / v[k].w;
+    u[k][0] = v[k].x + f[k].x * h;
+    u[k][1] = v[k].y + f[k].y * h;
+    u[k][2] = v[k].z + f[k].z * h;
+  }
+}
+
 template <bool DENSE>
 __global__ void __launch_bounds__(kBlock)
 k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, const uint32_t* __restrict__ bits,
         const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float4* __restrict__ fib,
         uint32_t s_cap, const float* __restrict__ ufield, double* __restrict__ Iu, double* __restrict__ IL) {
+  constexpr int K = kKempeBatch;
+  __shared__ uint16_t rowlist[kKempeRows];
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
   const double r = rad[p];
   const Box b = make_box(Xp, r + 1.0);
-  const BoxLin L = box_lin(b);
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (uint32_t i = threadIdx.x; i < L.count; i += kBlock) {
-    int x, y, z;
-    box_lin_node(b, L, i, d.nx, d.ny, d.nz, x, y, z);
-    const double dx = min_image((double)x - Xp[0], d.nx), dy = min_image((double)y - Xp[1], d.ny),
-                 dz = min_image((double)z - Xp[2], d.nz);
-    const double a = kempe_alpha(dx, dy, dz, r);
-    if (a <= 0.0) continue;
-    const uint32_t n = node_index(x, y, z, d.nx, d.ny);
-    double u[3];
-    if (DENSE) {
-      u[0] = ufield[n];
-      u[1] = ufield[(size_t)d.N + n];
-      u[2] = ufield[2 * (size_t)d.N + n];
-    } else {
-      uint32_t slot;
-      if (!support_slot(bits, rank, n, slot) || slot >= s_cap) continue;
-      const float4 v = us[slot];
-      const float4 f = fib[slot];
-      const float h = 0.5f / v.w;
-      u[0] = (double)(v.x + f.x * h);
-      u[1] = (double)(v.y + f.y * h);
-      u[2] = (double)(v.z + f.z * h);
+  const double ri = r - 0.8661, ro = r + 0.8661;  // the fraction's own margins
+  const double ro2 = ro * ro;
+  const int rows = min(b.side[1] * b.side[2], kKempeRows);
+  uint32_t nrows = 0;
+  for (int r0 = 0; r0 < rows; r0 += kBlock) {
+    const int row = r0 + (int)threadIdx.x;
+    bool hit = false;
+    if (row < rows) {
+      const int y = wrap1(b.lo[1] + row % b.side[1], d.ny), z = wrap1(b.lo[2] + row / b.side[1], d.nz);
+      const double dy = min_image((double)y - Xp[1], d.ny), dz = min_image((double)z - Xp[2], d.nz);
+      hit = dy * dy + dz * dz < ro2;
     }
-    s[0] += a * u[0];
-    s[1] += a * u[1];
-    s[2] += a * u[2];
-    s[3] += a * (dy * u[2] - dz * u[1]);
-    s[4] += a * (dz * u[0] - dx * u[2]);
-    s[5] += a * (dx * u[1] - dy * u[0]);
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan<kBlock>(hit ? 1u : 0u, &total);
+    if (hit) rowlist[nrows + off] = (uint16_t)row;
+    nrows += total;
+  }
+  __syncthreads();
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (uint32_t j = threadIdx.x; j < nrows; j += kBlock) {
+    const int row = rowlist[j];
+    const int y = wrap1(b.lo[1] + row % b.side[1], d.ny), z = wrap1(b.lo[2] + row / b.side[1], d.nz);
+    const double dy = min_image((double)y - Xp[1], d.ny), dz = min_image((double)z - Xp[2], d.nz);
+    // x range of the ball in this row (box-local, widened by one: the exact
+    // test below decides)
+    const double hx = sqrt(fmax(ro2 - (dy * dy + dz * dz), 0.0));
+    const int xa = max(0, (int)floor(Xp[0] - hx) - 1 - b.lo[0]);
+    const int xb = min(b.side[0] - 1, (int)ceil(Xp[0] + hx) + 1 - b.lo[0]);
+    for (int x0 = xa; x0 <= xb; x0 += K) {
+      uint32_t n[K];
+      double a[K], dx[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        a[k] = 0.0;
+        n[k] = 0u;
+        dx[k] = 0.0;
+        if (x0 + k > xb) continue;
+        const int x = wrap1(b.lo[0] + x0 + k, d.nx);
+        dx[k] = min_image((double)x - Xp[0], d.nx);
+        n[k] = node_index(x, y, z, d.nx, d.ny);
+        const double d2 = dist2(dx[k], dy, dz);
+        if (ri > 0.0 && d2 < ri * ri)
+          a[k] = 1.0;
+        else if (d2 < ro2)
+          a[k] = kempe_alpha(dx[k], dy, dz, r);
+      }
+      float u[K][3];
+      kempe_u<DENSE, K>(n, a, u, d, bits, rank, us, fib, s_cap, ufield);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!(a[k] > 0.0)) continue;
+        const double ux = (double)u[k][0], uy = (double)u[k][1], uz = (double)u[k][2];
+        s[0] += a[k] * ux;
+        s[1] += a[k] * uy;
+        s[2] += a[k] * uz;
+        s[3] += a[k] * (dy * uz - dz * uy);
+        s[4] += a[k] * (dz * ux - dx[k] * uz);
+        s[5] += a[k] * (dx[k] * uy - dy * ux);
+      }
+    }
   }
   block_sum_n<kBlock, 6>(s);
   if (threadIdx.x == 0)
