@@ -343,8 +343,10 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // with 64-bit atomics: exact, so the order of the spheres does not matter
 // either.
 constexpr int kPassBlock = 1024;
-constexpr int kStage = 3;  // support nodes per thread per staging round
-constexpr int kWrite = 4;  // support nodes per thread per write-back round
+// A sphere of radius 8 has about 4 050 - 4 110 forcing-support nodes: one
+// staging round (4 096) covers most, one write-back round (5 120) all.
+constexpr int kStage = 4;  // support nodes per thread per staging round
+constexpr int kWrite = 5;  // support nodes per thread per write-back round
 constexpr float kSpreadBound = 8.0f;
 constexpr int kShUnitExp = 50;  // shared accumulators: units of 2^-50
 
