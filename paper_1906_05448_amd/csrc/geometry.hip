@@ -20,7 +20,7 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kCand = 2048;     // shell candidates buffered in LDS per flush
+constexpr int kCand = 4096;     // shell candidates buffered in LDS per round of rows
 constexpr int kRowList = 4096;  // nodes listed per round of rows in the owner passes
 
 __device__ __forceinline__ bool inside_sphere(int x, int y, int z, const double* X, double r, double Lx, double Ly,
