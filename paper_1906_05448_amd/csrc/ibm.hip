@@ -791,16 +791,18 @@ k_ibm_wall_fold(const uint32_t* __restrict__ count, unsigned long long* __restri
 // slots (u* + f_IB / (2 rho)) or, before the first step, a dense field.
 //
 // Only cells whose centre lies within r + sqrt(3)/2 of the centre have a
-// fraction above zero, so the box rows that reach that ball are listed
-// first (in box order), then every thread takes whole rows and visits just
-// the x range of the ball in each, kKempeBatch cells at a time with their
-// loads in flight together. A cell deeper than sqrt(3)/2 inside the surface
-// has fraction 1 from its centre distance; the others take the eight-corner
-// fraction. Rows and cells are taken in a fixed order, so the sums are
-// reproducible.
-constexpr int kKempeBatch = 4;
-constexpr int kKempeRows = 4096;  // box rows: (2 (r + 1) + 2)^2 for r <= 28
-
+// fraction above zero; those deeper than sqrt(3)/2 inside the surface have
+// fraction 1 from the centre distance alone, the rest (the surface cells)
+// take the eight-corner fraction. Per round, one thread per box row counts
+// the row's inner and surface cells (two intervals of the ball's x range),
+// and the cells are listed in LDS, inner ones first, each group in box
+// order. The list is then taken kKempeBatch cells per thread with
+// consecutive lanes on consecutive cells: the slot loads of a row coalesce,
+// and the wavefronts on surface cells evaluate the fraction with every lane
+// busy. Rounds take as many rows as the list holds. Rows and cells are
+// taken in a fixed order, so the sums are reproducible.
+constexpr int kKempeBatch = 2;
+constexpr int kKempeCells = 4096;  // listed cells per round
 // u at K cells (a[k] > 0 only); a cell outside the support gets a[k] = 0.
 template <bool DENSE, int K>
 __device__ __forceinline__ void kempe_u(const uint32_t (&n)[K], double (&a)[K], float (&u)[K][3], const Dims& d,
@@ -855,56 +857,82 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
         const uint32_t* __restrict__ rank, const float4* __restrict__ us, const float4* __restrict__ fib,
         uint32_t s_cap, const float* __restrict__ ufield, double* __restrict__ Iu, double* __restrict__ IL) {
   constexpr int K = kKempeBatch;
-  __shared__ uint16_t rowlist[kKempeRows];
+  __shared__ uint32_t cells[kKempeCells];  // box-local x | y << 8 | z << 16
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
   const double r = rad[p];
-  const Box b = make_box(Xp, r + 1.0);
+  const Box b = make_box(Xp, r + 1.0);  // side <= 2 r + 4 < 256
   const double ri = r - 0.8661, ro = r + 0.8661;  // the fraction's own margins
-  const double ro2 = ro * ro;
-  const int rows = min(b.side[1] * b.side[2], kKempeRows);
-  uint32_t nrows = 0;
-  for (int r0 = 0; r0 < rows; r0 += kBlock) {
-    const int row = r0 + (int)threadIdx.x;
-    bool hit = false;
+  const double ri2 = ri > 0.0 ? ri * ri : -1.0, ro2 = ro * ro;
+  const int rows = b.side[1] * b.side[2];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  int row0 = 0;
+  while (row0 < rows) {  // uniform: every thread sees the same row0
+    // this thread's row: the ball's x range [xa, xb] and inside it the inner
+    // cells [ia, ib] (both box-local; empty ranges have b < a)
+    const int row = row0 + (int)threadIdx.x;
+    int xa = 0, xb = -1, ia = 0, ib = -1;
     if (row < rows) {
       const int y = wrap1(b.lo[1] + row % b.side[1], d.ny), z = wrap1(b.lo[2] + row / b.side[1], d.nz);
       const double dy = min_image((double)y - Xp[1], d.ny), dz = min_image((double)z - Xp[2], d.nz);
-      hit = dy * dy + dz * dz < ro2;
+      if (dy * dy + dz * dz < ro2) {
+        // widened by one around the root; the exact test below decides
+        const double hx = sqrt(fmax(ro2 - (dy * dy + dz * dz), 0.0));
+        const int lo = max(0, (int)floor(Xp[0] - hx) - 1 - b.lo[0]);
+        const int hi = min(b.side[0] - 1, (int)ceil(Xp[0] + hx) + 1 - b.lo[0]);
+        xa = hi + 1;
+        for (int lx = lo; lx <= hi; ++lx) {
+          const int x = wrap1(b.lo[0] + lx, d.nx);
+          const double d2 = dist2(min_image((double)x - Xp[0], d.nx), dy, dz);
+          if (d2 < ro2) {
+            xa = min(xa, lx);
+            xb = lx;
+          }
+          if (d2 < ri2) {
+            if (ib < ia) ia = lx;
+            ib = lx;
+          }
+        }
+      }
     }
+    const uint32_t ni = ib >= ia ? (uint32_t)(ib - ia + 1) : 0u;
+    const uint32_t nall = xb >= xa ? (uint32_t)(xb - xa + 1) : 0u;
+    // the rows of this round: as many as the list holds (at least one)
     uint32_t total;
-    const uint32_t off = block_exclusive_scan<kBlock>(hit ? 1u : 0u, &total);
-    if (hit) rowlist[nrows + off] = (uint16_t)row;
-    nrows += total;
-  }
-  __syncthreads();
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (uint32_t j = threadIdx.x; j < nrows; j += kBlock) {
-    const int row = rowlist[j];
-    const int y = wrap1(b.lo[1] + row % b.side[1], d.ny), z = wrap1(b.lo[2] + row / b.side[1], d.nz);
-    const double dy = min_image((double)y - Xp[1], d.ny), dz = min_image((double)z - Xp[2], d.nz);
-    // x range of the ball in this row (box-local, widened by one: the exact
-    // test below decides)
-    const double hx = sqrt(fmax(ro2 - (dy * dy + dz * dz), 0.0));
-    const int xa = max(0, (int)floor(Xp[0] - hx) - 1 - b.lo[0]);
-    const int xb = min(b.side[0] - 1, (int)ceil(Xp[0] + hx) + 1 - b.lo[0]);
-    for (int x0 = xa; x0 <= xb; x0 += K) {
+    const uint32_t before = block_exclusive_scan<kBlock>(row < rows ? nall : 0u, &total);
+    const bool take = row < rows && (before + nall <= (uint32_t)kKempeCells || threadIdx.x == 0);
+    const uint32_t ti = take ? ni : 0u, ts = take ? nall - ni : 0u;
+    uint32_t n_in, n_surf;
+    const uint32_t oi = block_exclusive_scan<kBlock>(ti, &n_in);
+    const uint32_t os = block_exclusive_scan<kBlock>(ts, &n_surf);
+    uint32_t taken;
+    (void)block_exclusive_scan<kBlock>(take ? 1u : 0u, &taken);
+    if (take) {
+      const uint32_t yz = (uint32_t)(row % b.side[1]) << 8 | (uint32_t)(row / b.side[1]) << 16;
+      for (uint32_t k = 0; k < ni; ++k) cells[min(oi + k, (uint32_t)kKempeCells - 1u)] = (uint32_t)(ia + (int)k) | yz;
+      uint32_t o = n_in + os;
+      for (int lx = xa; lx <= xb; ++lx)
+        if (lx < ia || lx > ib) cells[min(o++, (uint32_t)kKempeCells - 1u)] = (uint32_t)lx | yz;
+    }
+    __syncthreads();
+    const uint32_t n_cells = min(n_in + n_surf, (uint32_t)kKempeCells);
+    for (uint32_t f0 = 0; f0 < n_cells; f0 += K * kBlock) {
       uint32_t n[K];
-      double a[K], dx[K];
+      double a[K], dx[K], dy[K], dz[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        a[k] = 0.0;
+        const uint32_t f = f0 + (uint32_t)(k * kBlock) + threadIdx.x;
+        a[k] = dx[k] = dy[k] = dz[k] = 0.0;
         n[k] = 0u;
-        dx[k] = 0.0;
-        if (x0 + k > xb) continue;
-        const int x = wrap1(b.lo[0] + x0 + k, d.nx);
+        if (f >= n_cells) continue;
+        const uint32_t e = cells[f];
+        const int x = wrap1(b.lo[0] + (int)(e & 0xFFu), d.nx), y = wrap1(b.lo[1] + (int)((e >> 8) & 0xFFu), d.ny),
+                  z = wrap1(b.lo[2] + (int)(e >> 16), d.nz);
         dx[k] = min_image((double)x - Xp[0], d.nx);
+        dy[k] = min_image((double)y - Xp[1], d.ny);
+        dz[k] = min_image((double)z - Xp[2], d.nz);
         n[k] = node_index(x, y, z, d.nx, d.ny);
-        const double d2 = dist2(dx[k], dy, dz);
-        if (ri > 0.0 && d2 < ri * ri)
-          a[k] = 1.0;
-        else if (d2 < ro2)
-          a[k] = kempe_alpha(dx[k], dy, dz, r);
+        a[k] = f < n_in ? 1.0 : kempe_alpha(dx[k], dy[k], dz[k], r);
       }
       float u[K][3];
       kempe_u<DENSE, K>(n, a, u, d, bits, rank, us, fib, s_cap, ufield);
@@ -915,11 +943,13 @@ k_kempe(const double* __restrict__ X, const double* __restrict__ rad, Dims d, co
         s[0] += a[k] * ux;
         s[1] += a[k] * uy;
         s[2] += a[k] * uz;
-        s[3] += a[k] * (dy * uz - dz * uy);
-        s[4] += a[k] * (dz * ux - dx[k] * uz);
-        s[5] += a[k] * (dx[k] * uy - dy * ux);
+        s[3] += a[k] * (dy[k] * uz - dz[k] * uy);
+        s[4] += a[k] * (dz[k] * ux - dx[k] * uz);
+        s[5] += a[k] * (dx[k] * uy - dy[k] * ux);
       }
     }
+    __syncthreads();  // the list is refilled by the next round
+    row0 += (int)taken;
   }
   block_sum_n<kBlock, 6>(s);
   if (threadIdx.x == 0)
