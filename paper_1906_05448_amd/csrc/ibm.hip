@@ -45,29 +45,35 @@ __device__ __forceinline__ void ibm_box_lo(const double* X, int R_b, int lo[3]) 
   for (int k = 0; k < 3; ++k) lo[k] = (int)floor(X[k]) - R_b;
 }
 
-// Marker l of a sphere: stencil base (box-local, 0 .. side-4) and the 4x3
-// Peskin weights.
-struct Stencil {
-  int bx, by, bz;
-  float wx[4], wy[4], wz[4];
+// A marker of a sphere: stencil base (box-local, packed 10 bits per axis)
+// and the offsets t = x_l - floor(x_l) per axis.
+struct MarkerPos {
+  uint32_t base;
+  float t[3];
 };
 
-__device__ __forceinline__ void marker_stencil(const double* X, const double* dir, double r_l, const int lo[3],
-                                               Stencil& s) {
-  double xl[3];
-  int b[3];
+__device__ __forceinline__ void marker_pos(const double* X, const double* dir, double r_l, const int lo[3],
+                                           MarkerPos& m) {
+  m.base = 0;
   for (int k = 0; k < 3; ++k) {
-    xl[k] = X[k] + r_l * dir[k];
-    b[k] = (int)floor(xl[k]) - 1;
+    const double xl = X[k] + r_l * dir[k];
+    const double fl = floor(xl);
+    m.t[k] = (float)(xl - fl);
+    m.base |= (uint32_t)((int)fl - 1 - lo[k]) << (10 * k);
   }
-  for (int j = 0; j < 4; ++j) {
-    s.wx[j] = peskin((float)(xl[0] - (double)(b[0] + j)));
-    s.wy[j] = peskin((float)(xl[1] - (double)(b[1] + j)));
-    s.wz[j] = peskin((float)(xl[2] - (double)(b[2] + j)));
-  }
-  s.bx = b[0] - lo[0];
-  s.by = b[1] - lo[1];
-  s.bz = b[2] - lo[2];
+}
+
+// The four Peskin weights of the points floor(x) - 1 .. floor(x) + 2 for the
+// offset t = x - floor(x) in [0, 1): their distances 1 + t, t, 1 - t, 2 - t
+// all take the same square root sqrt(1 + 4t - 4t^2), so one root gives all
+// four (they add up to one).
+__device__ __forceinline__ void peskin4(float t, float (&w)[4]) {
+  const float S = sqrtf(1.0f + 4.0f * t * (1.0f - t));
+  const float a = 3.0f - 2.0f * t, b = 1.0f + 2.0f * t;
+  w[0] = (a - S) * 0.125f;
+  w[1] = (a + S) * 0.125f;
+  w[2] = (b + S) * 0.125f;
+  w[3] = (b - S) * 0.125f;
 }
 
 // ---------------------------------------------------------------- build --
@@ -91,24 +97,43 @@ k_ibm_mark(const double* __restrict__ X, const double* __restrict__ rad, const d
   for (int i = threadIdx.x; i < rows; i += kBlock) fb[i] = ab[i] = 0u;
   __syncthreads();
   for (int l = threadIdx.x; l < nmk; l += kBlock) {
-    Stencil s;
-    marker_stencil(Xp, dirs + 3 * l, r_l, lo, s);
-    const uint32_t m = 0xFu << s.bx;
+    MarkerPos mp;
+    marker_pos(Xp, dirs + 3 * l, r_l, lo, mp);
+    const int bx = (int)(mp.base & 1023u), by = (int)((mp.base >> 10) & 1023u), bz = (int)(mp.base >> 20);
+    const uint32_t m = 0xFu << bx;
     for (int jz = 0; jz < 4; ++jz)
-      for (int jy = 0; jy < 4; ++jy) atomicOr(&fb[(s.by + jy) + side * (s.bz + jz)], m);
+      for (int jy = 0; jy < 4; ++jy) atomicOr(&fb[(by + jy) + side * (bz + jz)], m);
   }
+  // Kempe cells, one thread per row: the candidates are the ball's x range
+  // widened by one, the exact test (the Kempe kernel's) decides.
   const double ra = r + kAlphaReach;
   const double ra2 = ra * ra;
-  for (int rb = 0; rb < rows; rb += kBlock / 32) {
-    const int row = rb + (threadIdx.x >> 5), lx = threadIdx.x & 31;
-    if (row >= rows || lx >= side) continue;
+  for (int row = threadIdx.x; row < rows; row += kBlock) {
     const int ly = row % side, lz = row / side;
-    const int x = wrap1(lo[0] + lx, d.nx), y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
-    const double d2 = dist2(min_image((double)x - Xp[0], d.nx), min_image((double)y - Xp[1], d.ny),
-                            min_image((double)z - Xp[2], d.nz));
-    if (d2 < ra2) atomicOr(&ab[row], 1u << lx);
+    const int y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+    const double dy = min_image((double)y - Xp[1], d.ny), dz = min_image((double)z - Xp[2], d.nz);
+    const double e2 = dist2(0.0, dy, dz);
+    uint32_t mrow = 0u;
+    if (e2 < ra2) {
+      const double hx = sqrt(ra2 - e2);
+      const int c0 = max(0, (int)floor(Xp[0] - hx) - 1 - lo[0]);
+      const int c1 = min(side - 1, (int)ceil(Xp[0] + hx) + 1 - lo[0]);
+      for (int lx = c0; lx <= c1; ++lx) {
+        const int x = wrap1(lo[0] + lx, d.nx);
+        if (dist2(min_image((double)x - Xp[0], d.nx), dy, dz) < ra2) mrow |= 1u << lx;
+      }
+    }
+    ab[row] = mrow;
   }
   __syncthreads();
+  // The row's nodes are consecutive unless the box wraps around x: then the
+  // mask goes out in two shifted words at most.
+  const bool xwrap = lo[0] < 0 || lo[0] + side > d.nx;
+  auto put = [&](uint32_t word, uint32_t wm) {
+    if (!wm) return;
+    const uint32_t old = atomicOr(bits + word, wm);
+    if (old & wm) atomicOr(shared + word, old & wm);
+  };
   uint32_t cnt = 0;
   for (int row = threadIdx.x; row < rows; row += kBlock) {
     const uint32_t f = fb[row];
@@ -118,25 +143,26 @@ k_ibm_mark(const double* __restrict__ X, const double* __restrict__ rad, const d
     if (!m) continue;
     const int ly = row % side, lz = row / side;
     const int y = wrap1(lo[1] + ly, d.ny), z = wrap1(lo[2] + lz, d.nz);
+    if (!xwrap) {
+      const uint32_t n0 = node_index(lo[0], y, z, d.nx, d.ny);
+      const uint64_t M = (uint64_t)m << (n0 & 31u);
+      put(n0 >> 5, (uint32_t)M);
+      put((n0 >> 5) + 1u, (uint32_t)(M >> 32));
+      continue;
+    }
     uint32_t word = 0xFFFFFFFFu, wm = 0u;
     while (m) {
       const int lx = __ffs(m) - 1;
       m &= m - 1u;
       const uint32_t n = node_index(wrap1(lo[0] + lx, d.nx), y, z, d.nx, d.ny);
       if ((n >> 5) != word) {
-        if (wm) {
-          const uint32_t old = atomicOr(bits + word, wm);
-          if (old & wm) atomicOr(shared + word, old & wm);
-        }
+        put(word, wm);
         word = n >> 5;
         wm = 0u;
       }
       wm |= 1u << (n & 31u);
     }
-    if (wm) {
-      const uint32_t old = atomicOr(bits + word, wm);
-      if (old & wm) atomicOr(shared + word, old & wm);
-    }
+    put(word, wm);
   }
   const double tot = block_sum<kBlock>((double)cnt);
   if (threadIdx.x == 0) {
@@ -356,37 +382,6 @@ __device__ __forceinline__ int spread_exponent(float max_dF, float dV) {
   int ex;
   (void)frexpf(B, &ex);                // B < 2^ex
   return min(kShUnitExp, max(0, 30 - ex));
-}
-
-// A marker of the pass: stencil base (box-local, packed 10 bits per axis)
-// and the offsets t = x_l - floor(x_l) per axis.
-struct MarkerPos {
-  uint32_t base;
-  float t[3];
-};
-
-__device__ __forceinline__ void marker_pos(const double* X, const double* dir, double r_l, const int lo[3],
-                                           MarkerPos& m) {
-  m.base = 0;
-  for (int k = 0; k < 3; ++k) {
-    const double xl = X[k] + r_l * dir[k];
-    const double fl = floor(xl);
-    m.t[k] = (float)(xl - fl);
-    m.base |= (uint32_t)((int)fl - 1 - lo[k]) << (10 * k);
-  }
-}
-
-// The four Peskin weights of the points floor(x) - 1 .. floor(x) + 2 for the
-// offset t = x - floor(x) in [0, 1): their distances 1 + t, t, 1 - t, 2 - t
-// all take the same square root sqrt(1 + 4t - 4t^2), so one root gives all
-// four (they add up to one).
-__device__ __forceinline__ void peskin4(float t, float (&w)[4]) {
-  const float S = sqrtf(1.0f + 4.0f * t * (1.0f - t));
-  const float a = 3.0f - 2.0f * t, b = 1.0f + 2.0f * t;
-  w[0] = (a - S) * 0.125f;
-  w[1] = (a + S) * 0.125f;
-  w[2] = (b + S) * 0.125f;
-  w[3] = (b - S) * 0.125f;
 }
 
 // Slot-list entries j0 + threadIdx.x + i kPassBlock of a sphere and their
