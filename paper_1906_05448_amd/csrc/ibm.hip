@@ -211,28 +211,38 @@ __global__ void __launch_bounds__(1024) k_scan_top(uint32_t* __restrict__ block_
   if (threadIdx.x == 0) *count = carry;
 }
 
+// Adds the block offsets to the word ranks, then lists the set bits' nodes
+// by slot: each wavefront expands two words per step with one lane per bit,
+// so a dense word's 32 slots are written by 32 consecutive lanes.
 __global__ void __launch_bounds__(kBlock) k_scan_add(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                     uint32_t* __restrict__ rank,
                                                     const uint32_t* __restrict__ block_sums,
                                                     uint32_t* __restrict__ list, uint32_t s_cap,
                                                     uint32_t* __restrict__ err) {
-  const uint32_t w0 = blockIdx.x * kScanWords + threadIdx.x * kScanPer;
+  __shared__ uint32_t wb[kScanWords], wr[kScanWords];
+  const uint32_t base = blockIdx.x * kScanWords;
   const uint32_t add = block_sums[blockIdx.x];
   for (int k = 0; k < kScanPer; ++k) {
-    const uint32_t w = w0 + k;
-    if (w >= nwords) break;
-    const uint32_t rk = rank[w] + add;
-    rank[w] = rk;
-    uint32_t m = bits[w], j = 0;
-    while (m) {
-      const int b = __ffs(m) - 1;
-      m &= m - 1u;
-      const uint32_t slot = rk + j++;
-      if (slot < s_cap)
-        list[slot] = w * 32u + (uint32_t)b;
-      else
-        atomicOr(err, kErrCapacity);
+    const uint32_t i = threadIdx.x + (uint32_t)(k * kBlock), w = base + i;
+    uint32_t m = 0u, rk = 0u;
+    if (w < nwords) {
+      rk = rank[w] + add;
+      rank[w] = rk;
+      m = bits[w];
     }
+    wb[i] = m;
+    wr[i] = rk;
+  }
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, bit = lane & 31u;
+  for (uint32_t i = (threadIdx.x >> 6) * 2u + (lane >> 5); i < (uint32_t)kScanWords; i += kBlock / 32) {
+    const uint32_t m = wb[i];
+    if (!((m >> bit) & 1u)) continue;
+    const uint32_t slot = wr[i] + __popc(m & ((1u << bit) - 1u));
+    if (slot < s_cap)
+      list[slot] = (base + i) * 32u + bit;
+    else
+      atomicOr(err, kErrCapacity);
   }
 }
 
@@ -977,13 +987,32 @@ hipError_t launch_bits_compact(hipStream_t st, const uint32_t* bits, uint32_t nw
   return hipGetLastError();
 }
 
+// Clears the support and shared bitmasks (16-byte stores; the runtime's
+// fill took about 40 us for each 16.8 MB mask at 512^3). With a static wall
+// the support starts as the wall's support instead.
+__global__ void __launch_bounds__(kBlock)
+k_masks_reset(uint32_t* __restrict__ bits, uint32_t* __restrict__ shared, const uint32_t* __restrict__ wall,
+              uint32_t words) {
+  const uint32_t n4 = words / 4u;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n4; i += gridDim.x * kBlock) {
+    ((uint4*)bits)[i] = wall ? ((const uint4*)wall)[i] : make_uint4(0u, 0u, 0u, 0u);
+    ((uint4*)shared)[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < words % 4u) {
+    const uint32_t w = n4 * 4u + threadIdx.x;
+    bits[w] = wall ? wall[w] : 0u;
+    shared[w] = 0u;
+  }
+}
+
 hipError_t launch_ibm_support_build(Ctx& c, int buf, const double* X) {
   const uint32_t words = mask_words(c.dims.N);
   IbmBufs& m = c.ibm;
   // the static wall support, if any, is part of every support set
-  hipError_t e = m.n_wall ? hipMemcpyAsync(m.bits[buf], m.wsup, (size_t)words * 4, hipMemcpyDeviceToDevice, c.stream)
-                          : hipMemsetAsync(m.bits[buf], 0, (size_t)words * 4, c.stream);
-  if (e == hipSuccess) e = hipMemsetAsync(m.shared, 0, (size_t)words * 4, c.stream);
+  const uint32_t blocks = std::min<uint32_t>(std::max<uint32_t>((words / 4u + kBlock - 1) / kBlock, 1u), 2048u);
+  hipLaunchKernelGGL(k_masks_reset, dim3(blocks), dim3(kBlock), 0, c.stream, m.bits[buf], m.shared,
+                     m.n_wall ? (const uint32_t*)m.wsup : nullptr, words);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (c.np > 0) {
     const size_t lds = (size_t)m.side * m.side * 8;
