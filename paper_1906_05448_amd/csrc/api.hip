@@ -461,9 +461,7 @@ hipError_t step_ibb(Ctx& c) {
       const int on = 1 - c.ocur;
       e = timed(c, LBM_K_GEOMETRY, [&] {
         hipError_t r = launch_owner_clear(c, c.ibb.owner[on], c.P.Xown[on], c.np);
-        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.P.X[pn]);
-        if (r == hipSuccess)
-          r = hipMemcpyAsync(c.P.Xown[on], c.P.X[pn], pvec_bytes(c), hipMemcpyDeviceToDevice, c.stream);
+        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.P.X[pn], c.P.Xown[on]);
         if (r == hipSuccess) r = launch_links_build(c, c.ibb.owner[on], c.P.X[pn]);
         return r;
       });

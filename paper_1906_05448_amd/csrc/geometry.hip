@@ -92,10 +92,13 @@ __global__ void __launch_bounds__(kBlock) k_owner_clear(uint32_t* __restrict__ o
   });
 }
 
+// Xown (optional) receives the positions the map was set with.
 __global__ void __launch_bounds__(kBlock) k_owner_set(uint32_t* __restrict__ owner, const double* __restrict__ X,
-                                                      const double* __restrict__ rad, Dims d) {
+                                                      const double* __restrict__ rad, Dims d,
+                                                      double* __restrict__ Xown) {
   __shared__ uint32_t list[kRowList];
   const uint32_t p = blockIdx.x;
+  if (Xown && threadIdx.x < 3) Xown[3 * p + threadIdx.x] = X[3 * p + threadIdx.x];
   for_sphere_nodes(X + 3 * p, rad[p], d, list, [&](uint32_t n) { atomicMin(owner + n, p); });
 }
 
@@ -353,9 +356,9 @@ hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold,
   return hipGetLastError();
 }
 
-hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X) {
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X, double* Xown) {
   if (c.np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_owner_set, dim3(c.np), dim3(kBlock), 0, c.stream, owner, X, c.P.r, c.dims);
+  hipLaunchKernelGGL(k_owner_set, dim3(c.np), dim3(kBlock), 0, c.stream, owner, X, c.P.r, c.dims, Xown);
   return hipGetLastError();
 }
 

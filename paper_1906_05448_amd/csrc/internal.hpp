@@ -348,7 +348,8 @@ hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float*
 // Geometry (geometry.hip).
 hipError_t launch_owner_fill(const Ctx& c, uint32_t* owner);
 hipError_t launch_owner_clear(const Ctx& c, uint32_t* owner, const double* Xold, int32_t np_old);
-hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X);
+// Xown (optional): receives X, the positions the map is set with.
+hipError_t launch_owner_set(const Ctx& c, uint32_t* owner, const double* X, double* Xown = nullptr);
 hipError_t launch_count_solid(const Ctx& c, const uint32_t* owner, unsigned long long* out);
 size_t links_build_lds_bytes(double max_radius);  // dynamic LDS of the link build
 size_t links_build_lds_total(double max_radius);  // its dynamic plus static LDS
