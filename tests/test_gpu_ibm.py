@@ -87,8 +87,8 @@ def test_moving_spheres_release_ibm(store):
 @pytest.mark.parametrize("store,rd", [(0, 0.0), (0, 0.4), (1, 0.0), (1, 0.4)])
 def test_r8_spheres_sharing_support(store, rd):
     """Radius 8, the production spheres: the forcing support of one sphere
-    (about 3300 nodes at r_d = 0) takes two staging rounds of the pass
-    kernel. Three released spheres, two of them 2 spacings apart so that
+    (about 4 500 nodes at r_d = 0, 4 100 at r_d = 0.4) takes one or two
+    staging rounds of 4 096 nodes in the pass kernel. Three released spheres, two of them 2 spacings apart so that
     their supports share nodes, one across a periodic face; density ratio 4
     as in the paper's particle-laden case."""
     shape = (56, 48, 44)
@@ -118,6 +118,46 @@ def test_r8_spheres_sharing_support(store, rd):
         Fo, To, _ = o.forces()
         assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
         assert rel_l2(Tg, To) < (1e-3 if store == 0 else 5e-2)
+    g.close()
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_r10_spheres_two_markers_per_thread(store):
+    """Radius 10 at r_d = 0.4: 1159 markers per sphere, so the pass kernel
+    takes two markers per thread (one 1024-thread workgroup per compute
+    unit), the forcing support of a sphere (about 6 500 nodes) two staging
+    rounds, and the Kempe integral (about 5 400 cells within r + sqrt(3)/2)
+    two rounds of its LDS cell list. Two released spheres whose supports
+    share nodes, one of them across a periodic face."""
+    shape = (52, 48, 44)
+    spec = synth.hit_spectrum(seed=12, u_rms=0.03, kcut=8)
+    u0 = synth.hit_field(spec, shape)
+    X = np.array([[5.3, 22.2, 20.9], [27.4, 23.1, 22.6]])
+    r = np.full(2, 10.0)
+    rho_p = np.full(2, 4.0)
+    o, g = _pair(shape, tau=0.52, store=store, rd=0.4, max_np=2, max_r=10.0)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, r=r, rho_p=rho_p, mode=RELEASE)
+    g.set_particles(X, r, rho_p=rho_p, mode=1)
+    tol = 1e-5 if store == 0 else 2e-3
+    for chunk in (1, 4, 10):
+        o.step(chunk)
+        g.step(chunk)
+        ug, _ = g.get_fields()
+        uo, _ = o.fields()
+        assert rel_l2(ug, uo) < tol, o.state.step
+        Xg, Ug, Wg = g.get_particles()
+        P = o.state.P
+        assert np.abs(Xg - P.X).max() < (1e-6 if store == 0 else 2e-4)
+        assert rel_l2(Ug, P.U) < (1e-4 if store == 0 else 1e-2)
+        assert rel_l2(Wg, P.Om) < (1e-3 if store == 0 else 5e-2)
+        Fg, Tg, _ = g.forces()
+        Fo, To, _ = o.forces()
+        assert rel_l2(Fg, Fo) < (1e-4 if store == 0 else 2e-2)
+        assert rel_l2(Tg, To) < (1e-3 if store == 0 else 5e-2)
+    support, shared = g.ibm_support()
+    assert support > 2 * 6000 and shared > 0
     g.close()
 
 
