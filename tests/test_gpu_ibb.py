@@ -190,6 +190,28 @@ def test_r8_spheres_release_quadratic_ibb(store):
     g.close()
 
 
+@pytest.mark.parametrize("store", [0, 1])
+def test_release_velocity_large_sphere(store):
+    """The release velocity (Sec. 3.1: the fluid velocity averaged over the
+    particle volume with the cells' solid fractions) of a radius-20 sphere
+    across a periodic face: about 37 000 cells within r + sqrt(3)/2, so the
+    Kempe-weighted average takes about ten rounds of its LDS cell list."""
+    shape = (48, 48, 48)
+    spec = synth.hit_spectrum(seed=4, u_rms=0.03, kcut=8)
+    u0 = synth.hit_field(spec, shape)
+    X = np.array([[23.7, 24.2, 1.9]])
+    o, g = _pair(shape, tau=0.55, store=store, max_np=1, max_r=20.0)
+    o.set_fields(u0)
+    g.set_fields(u0)
+    o.set_particles(X, r=[20.0], rho_p=[2.0], mode=RELEASE)
+    g.set_particles(X, [20.0], rho_p=[2.0], mode=1)
+    _, Ug, Wg = g.get_particles()
+    assert np.abs(o.state.P.U).max() > 1e-4
+    assert rel_l2(Ug, o.state.P.U) < (1e-6 if store == 0 else 2e-3)
+    assert np.all(Wg == 0.0)
+    g.close()
+
+
 def test_overlap_latch():
     """Soft-sphere contact (Sec. 3.1) keeps spheres apart; an overlap deeper
     than half a radius is reported as LBM_E_OVERLAP by the next syncing call
