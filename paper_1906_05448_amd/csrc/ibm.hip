@@ -357,7 +357,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 
 // --------------------------------------------------------------- passes --
 // One 1024-thread workgroup per sphere, MPT markers per thread.
-// LDS: rows u32 (forcing row bits), rows u32 (row prefix), then fcap x 12
+// LDS: rows x (u32 forcing row bits, u32 row prefix), then fcap x 12
 // bytes holding first the staged velocities (float3 per node) and, once every
 // marker has interpolated, the spread sums of the three components (int32
 // per component and node), then fcap u32 (the nodes' slot-list entries, kept
@@ -427,10 +427,9 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   __shared__ double red_f[kPassBlock / 64][6];  // per-wavefront force and torque sums
   __shared__ uint32_t red_m[kPassBlock / 64];   // per-wavefront largest |dF|
   const int rows = side * side;
-  uint32_t* rb = lds;
-  uint32_t* rp = rb + rows;
-  float* uj = (float*)(rp + rows);
-  int* acc = (int*)(rp + rows);  // aliases uj once every marker has interpolated
+  uint2* rbp = (uint2*)lds;  // per row: forcing bits, exclusive prefix
+  float* uj = (float*)(rbp + rows);
+  int* acc = (int*)(rbp + rows);  // aliases uj once every marker has interpolated
   uint32_t* sl = (uint32_t*)(uj + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
@@ -465,8 +464,7 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     uint32_t total;
     const uint32_t off = block_exclusive_scan<kPassBlock>(__popc(m), &total);
     if (row < rows) {
-      rb[row] = m;
-      rp[row] = base + off;
+      rbp[row] = make_uint2(m, base + off);
     }
     base += total;
   }
@@ -529,7 +527,8 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     for (int q = 0; q < 16; ++q) {
       const int jy = q & 3, jz = q >> 2;
       const int row = (by + jy) + side * (bz + jz);
-      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+      const uint2 rw = rbp[row];
+      const uint32_t j0 = rw.y + __popc(rw.x & below);
       const float wyz = wy[jy] * wz[jz];
 #pragma unroll
       for (int jx = 0; jx < 4; ++jx) {
@@ -609,7 +608,8 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     for (int q = 0; q < 16; ++q) {
       const int jy = q & 3, jz = q >> 2;
       const int row = (by + jy) + side * (bz + jz);
-      const uint32_t j0 = rp[row] + __popc(rb[row] & below);
+      const uint2 rw = rbp[row];
+      const uint32_t j0 = rw.y + __popc(rw.x & below);
       const float wyz = wy[jy] * wz[jz] * dVf;
 #pragma unroll
       for (int jx = 0; jx < 4; ++jx) {
