@@ -361,7 +361,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // bytes holding first the staged velocities (float3 per node) and, once every
 // marker has interpolated, the spread sums of the three components (int32
 // per component and node), then fcap u32 (the nodes' slot-list entries, kept
-// for the write-back). About 64 KB for r = 8, so two spheres share a compute
+// for the write-back). About 74 KB for r = 8, so two spheres share a compute
 // unit and one's memory trips overlap the other's LDS work.
 //
 // The spread sums are 32-bit fixed point in units of 2^-e with a scale
