@@ -20,7 +20,10 @@ Prints ONE JSON line on stdout (progress goes to stderr):
                on the launch stream, against the 8 TB/s HBM peak
   cpu_baseline the FP64 oracle, single-threaded, on a bounded sample of the
                same recipe on this host
-  variants     every variant measured (boundary treatment x storage)
+  variants     every variant measured (boundary treatment x storage, and
+               the bounce-back and immersed-boundary FP16 steps with the
+               particle stage and the next geometry overlapped with the
+               stream-collide kernel on a second stream: "-ov")
   corrector    training throughput of the corrector network, MFMA
                utilisation of its kernels, and its held-out gain
   cpu_baseline also carries error_vs_fp64: relative L2 of the FP32 and FP16
@@ -101,9 +104,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--n", type=int, default=512, help="lattice edge (production: 512)")
     p.add_argument("--particles", type=int, default=6250)
-    p.add_argument("--variants", default="ibb-f16s,ibb-f32,ibm-f16s,ibmc-f16s,ibm-f32,none-f16s,none-f32",
-                   help="comma list of <bc>-<store>, bc in ibb|ibm|ibmc (immersed boundary with the learned "
-                        "corrector in the statistics)|none, store in f16s|f32; the first is the headline")
+    p.add_argument("--variants",
+                   default="ibb-f16s,ibb-f32,ibm-f16s,ibmc-f16s,ibm-f32,none-f16s,none-f32,ibb-f16s-ov,ibm-f16s-ov",
+                   help="comma list of <bc>-<store>[-ov], bc in ibb|ibm|ibmc (immersed boundary with the learned "
+                        "corrector in the statistics)|none, store in f16s|f32, -ov: the particle stage and the "
+                        "next geometry on a second stream beside the stream-collide kernel (lbm_set_overlap); "
+                        "the first is the headline")
     p.add_argument("--stats-every", type=int, default=100, help="steps between lbm_stats calls (0: none)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--pipe", action="store_true",
@@ -151,10 +157,11 @@ def step_bytes(bc, s, N, fluid, links, support, stats_per_step=0.0):
     return 38 * s * N + stats
 
 
-def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=None):
+def run_variant(torch, lbm, n, bc, store, u0_dev, X, steps, warmup, every, corr=None, overlap=False):
     cfg = lbm.Config(nx=n, ny=n, nz=n, tau=TAU, store=store, bc=bc, ibm_retraction=IBM_RD,
                      max_particles=len(X) if bc != lbm.BC_NONE else 0, max_radius=RADIUS)
     lat = lbm.Lattice(cfg)
+    lat.set_overlap(overlap)
     lat.set_fields_device(u0_dev)
     if bc != lbm.BC_NONE and len(X):
         lat.set_particles(X, RADIUS, rho_p=RHO_P, mode=lbm.RELEASE, motion=lbm.MOTION_FREE)
@@ -502,7 +509,10 @@ def main():
     n = args.n
     bcs = {"ibb": lbm.BC_IBB, "ibm": lbm.BC_IBM, "ibmc": lbm.BC_IBM, "none": lbm.BC_NONE}
     stores = {"f32": lbm.STORE_F32, "f16s": lbm.STORE_F16S}
-    variants = [v.split("-") for v in args.variants.split(",")]
+    # name = boundary-storage[-ov]; "-ov": lbm_set_overlap on
+    names = args.variants.split(",")
+    variants = [v.split("-")[:2] for v in names]
+    overlap = {v: v.endswith("-ov") for v in names}
     net, cinfo = None, None
     if any(bc == "ibmc" for bc, _ in variants):
         log("bench: training the gradient corrector on paired 64^3 runs")
@@ -514,20 +524,19 @@ def main():
     copy = copy_calibration(torch)
     log(f"bench: device copy {copy}")
     results = {}
-    for bc, st in variants:
-        name = f"{bc}-{st}"
+    for (bc, st), name in zip(variants, names):
         log(f"bench: variant {name}: warmup {args.warmup}, timed {args.steps} steps")
         results[name] = run_variant(torch, lbm, n, bcs[bc], stores[st], u0, X, args.steps, args.warmup,
-                                    args.stats_every, net if bc == "ibmc" else None)
+                                    args.stats_every, net if bc == "ibmc" else None, overlap[name])
         r = results[name]
         log(f"bench: {name}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, stream_collide "
             f"{r['kernel_avg_ms']:.3f} ms = {r['achieved_gbs']:.0f} GB/s; per step {r['kernels_ms_per_step']}")
     del u0
-    head_name = "-".join(variants[0])
+    head_name = names[0]
     head = results[head_name]
     hb, hs = variants[0]
     N = n ** 3
-    for (bc, st), name in zip(variants, [f"{b}-{s_}" for b, s_ in variants]):
+    for (bc, st), name in zip(variants, names):
         r = results[name]
         b = step_bytes(bc, 4 if st == "f32" else 2, N, N - r["solid_nodes"], r["links"], r["support_nodes"],
                        r["stats_calls_timed"] / args.steps)

@@ -14,9 +14,12 @@
  *    lbm_workspace_size() bytes, 256-byte aligned, handed to lbm_init() and
  *    kept alive until lbm_destroy(). The library never allocates device
  *    memory itself.
- *  - All GPU work is enqueued on the HIP stream given to lbm_init(). Calls
- *    marked "async" return before the work finishes; calls marked "sync"
- *    wait for the stream and report errors latched by earlier async calls.
+ *  - All GPU work is ordered on the HIP stream given to lbm_init() (with
+ *    lbm_set_overlap() on, part of a step runs on a second stream of the
+ *    context, forked from and joined back into that stream within the
+ *    step). Calls marked "async" return before the work finishes; calls
+ *    marked "sync" wait for the stream and report errors latched by earlier
+ *    async calls.
  *  - Host pointers are read or written before the call returns and are
  *    never retained.
  *  - A context is not thread-safe; distinct contexts are independent.
@@ -107,8 +110,9 @@ int lbm_workspace_size(const lbm_config* cfg, size_t* bytes);
 
 /* Creates a context on the current HIP device. workspace: device pointer,
  * 256-byte aligned, >= lbm_workspace_size() bytes, owned by the caller.
- * stream: a hipStream_t (NULL = default stream). The lattice starts at rest
- * with density 1. Errors: LBM_E_ARG, LBM_E_SIZE, LBM_E_HIP. */
+ * stream: a hipStream_t (NULL = default stream). The context creates one
+ * stream and two events of its own (released by lbm_destroy). The lattice
+ * starts at rest with density 1. Errors: LBM_E_ARG, LBM_E_SIZE, LBM_E_HIP. */
 int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes,
              void* stream, lbm_ctx** out);
 
@@ -470,6 +474,18 @@ enum {
   LBM_K_CORRECTOR = 8,      /* learned gradient corrector                    */
   LBM_NPROF = 9
 };
+
+/* Overlap (on != 0; off after lbm_init): in every step with particles the
+ * particle stage and the next step's geometry (owner map and links, or the
+ * immersed-boundary support) run on a second stream of the context, at the
+ * default priority, beside the stream-collide kernel, which reads and
+ * writes none of their data; the step joins that stream back into the
+ * context's stream before its last kernel. Results are bit-identical with
+ * and without overlap. At 512^3 with 6250 spheres it shortens a step by
+ * about 5% (bounce-back) and 3% (immersed boundary); the stream-collide
+ * kernel, sharing the device, takes longer by itself. Takes effect at the
+ * next lbm_step(). Errors: LBM_E_ARG (null context). */
+int lbm_set_overlap(lbm_ctx* ctx, int32_t on);
 
 /* Enables (on != 0) or disables per-kernel timing: every kernel that
  * lbm_step() launches is bracketed by HIP events on the context's stream,

@@ -417,6 +417,13 @@ hipError_t ibm_inner_momentum_init(Ctx& c) {
   return e;
 }
 
+// One immersed-boundary step. The particle stage (Kempe integral and the
+// update, which need the forcing result) and the next step's support build
+// (which needs the new positions) read nothing the stream-collide kernel
+// writes and write nothing it reads (it reads the current support and force
+// slots; the build fills the other buffer). With overlap on they run on the
+// side stream beside it and the step ends with both streams joined;
+// otherwise the particle stage runs before it and the build after it.
 hipError_t step_ibm(Ctx& c) {
   const int pc = c.pcur, pn = 1 - c.pcur;
   hipError_t e = timed(c, LBM_K_IBM_PREPASS, [&] { return launch_ibm_prepass(c, c.f_cur); });
@@ -425,47 +432,77 @@ hipError_t step_ibm(Ctx& c) {
     e = timed(c, LBM_K_IBM_FORCING, [&] { return launch_ibm_forcing_pass(c, c.P.X[pc], c.P.U[pc], c.P.Om[pc]); });
     if (e != hipSuccess) return e;
   }
-  if (c.np > 0) {
-    e = timed(c, LBM_K_PARTICLE, [&] {
-      hipError_t r = launch_ibm_kempe(c, c.P.X[pc], c.P.Iu_new, c.P.IL_new);
-      if (r == hipSuccess) r = launch_particle_update(c);
-      return r;
+  const bool moving = c.np > 0 && c.motion != LBM_MOTION_FIXED;
+  const bool ov = c.overlap && c.np > 0;
+  const int nb = 1 - c.ibm.cur;
+  auto particles = [&] {
+    return timed(c, LBM_K_PARTICLE, [&] {
+      hipError_t q = launch_ibm_kempe(c, c.P.X[pc], c.P.Iu_new, c.P.IL_new);
+      if (q == hipSuccess) q = launch_particle_update(c);
+      return q;
     });
-    if (e != hipSuccess) return e;
+  };
+  auto geometry = [&] {
+    return moving ? timed(c, LBM_K_GEOMETRY, [&] { return launch_ibm_support_build(c, nb, c.P.X[pn]); })
+                  : hipSuccess;
+  };
+  if (ov) {
+    if ((e = fork_side(c)) != hipSuccess) return e;
+    e = on_side(c, [&] {
+      hipError_t r = particles();
+      return r == hipSuccess ? geometry() : r;
+    });
+  } else if (c.np > 0) {
+    e = particles();
   }
+  if (e != hipSuccess) return e;
   e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide_ibm(c, c.f_cur, c.f_nxt); });
+  if (e != hipSuccess) return e;
+  e = ov ? join_side(c) : geometry();
   if (e != hipSuccess) return e;
   c.ibm.last = c.ibm.cur;
   if (c.np > 0) {
-    if (c.motion != LBM_MOTION_FIXED) {
-      const int nb = 1 - c.ibm.cur;
-      e = timed(c, LBM_K_GEOMETRY, [&] { return launch_ibm_support_build(c, nb, c.P.X[pn]); });
-      if (e != hipSuccess) return e;
-      c.ibm.cur = nb;
-    }
+    if (moving) c.ibm.cur = nb;
     c.pcur = pn;
   }
   return hipSuccess;
 }
 
+// One bounce-back step. The particle update (it needs this step's link
+// forces) and the next step's geometry (owner map and links from the new
+// positions, into the other owner buffer and the link arrays, which the link
+// pass has finished reading) do not touch what the stream-collide kernel
+// reads or writes. With overlap on they run on the side stream beside it;
+// otherwise after it. The refill needs the collision's output and the new
+// geometry, so it comes after both.
 hipError_t step_ibb(Ctx& c) {
   const int pc = c.pcur, pn = 1 - c.pcur;
   hipError_t e = timed(c, LBM_K_IBB_LINKS, [&] { return launch_ibb_links(c, c.f_cur, c.P.X[pc], c.P.U[pc], c.P.Om[pc]); });
   if (e != hipSuccess) return e;
+  const bool moving = c.np > 0 && c.motion != LBM_MOTION_FIXED;
+  const bool ov = c.overlap && c.np > 0;
+  const int on = 1 - c.ocur;
+  auto particles_and_geometry = [&] {
+    hipError_t r = timed(c, LBM_K_PARTICLE, [&] { return launch_particle_update(c); });
+    if (r == hipSuccess && moving)
+      r = timed(c, LBM_K_GEOMETRY, [&] {
+        hipError_t q = launch_owner_clear(c, c.ibb.owner[on], c.P.Xown[on], c.np);
+        if (q == hipSuccess) q = launch_owner_set(c, c.ibb.owner[on], c.P.X[pn], c.P.Xown[on]);
+        if (q == hipSuccess) q = launch_links_build(c, c.ibb.owner[on], c.P.X[pn]);
+        return q;
+      });
+    return r;
+  };
+  if (ov) {
+    if ((e = fork_side(c)) != hipSuccess) return e;
+    if ((e = on_side(c, particles_and_geometry)) != hipSuccess) return e;
+  }
   e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
   if (e != hipSuccess) return e;
   if (c.np > 0) {
-    e = timed(c, LBM_K_PARTICLE, [&] { return launch_particle_update(c); });
+    e = ov ? join_side(c) : particles_and_geometry();
     if (e != hipSuccess) return e;
-    if (c.motion != LBM_MOTION_FIXED) {
-      const int on = 1 - c.ocur;
-      e = timed(c, LBM_K_GEOMETRY, [&] {
-        hipError_t r = launch_owner_clear(c, c.ibb.owner[on], c.P.Xown[on], c.np);
-        if (r == hipSuccess) r = launch_owner_set(c, c.ibb.owner[on], c.P.X[pn], c.P.Xown[on]);
-        if (r == hipSuccess) r = launch_links_build(c, c.ibb.owner[on], c.P.X[pn]);
-        return r;
-      });
-      if (e != hipSuccess) return e;
+    if (moving) {
       e = timed(c, LBM_K_REFILL, [&] {
         return launch_cover_refill(c, c.f_nxt, c.ibb.owner[c.ocur], c.ibb.owner[on], c.P.X[pc], c.P.X[pn],
                                    c.P.U[pn], c.P.Om[pn]);
@@ -524,7 +561,7 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
   Ctx& c = h->c;
   c.cfg = *cfg;
   c.stream = (hipStream_t)stream;
-  if (hipGetDevice(&c.device) != hipSuccess) {
+  if (hipGetDevice(&c.device) != hipSuccess || c.side.create() != hipSuccess) {
     delete h;
     return LBM_E_HIP;
   }
@@ -1653,6 +1690,12 @@ int lbm_sync(lbm_ctx* h) {
 int lbm_step_count(const lbm_ctx* h, int64_t* step) {
   if (!h || !step) return LBM_E_ARG;
   *step = h->c.step;
+  return LBM_OK;
+}
+
+int lbm_set_overlap(lbm_ctx* h, int32_t on) {
+  if (!h) return LBM_E_ARG;
+  h->c.overlap = on != 0;
   return LBM_OK;
 }
 

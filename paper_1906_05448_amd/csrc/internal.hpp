@@ -276,6 +276,30 @@ struct IbmBufs {
   uint32_t* wsup;        // [mask_words] support of the wall stencils
 };
 
+// A second stream, at the default priority, for the work of a step that
+// can run beside the stream-collide kernel (the particle stage and the next
+// step's geometry): forked from the caller's stream and joined back into it
+// within the step, so every call that returns leaves all of its work ordered
+// on the caller's stream.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  SideStream() = default;
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+  hipError_t create() {
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    return e;
+  }
+  ~SideStream() {
+    if (join) (void)hipEventDestroy(join);
+    if (fork) (void)hipEventDestroy(fork);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
 struct Ctx {
   lbm_config cfg;
   hipStream_t stream;
@@ -291,6 +315,8 @@ struct Ctx {
   double* stats_part; // [kStatGrid + 1][kStatStride] statistics partial sums
   int64_t step;
   Profiler prof;
+  SideStream side;
+  bool overlap = false;  // particle stage and next geometry beside the stream-collide kernel
   // Particles.
   int32_t np;            // particles set
   int32_t motion;        // LBM_MOTION_*
@@ -327,6 +353,30 @@ hipError_t timed(Ctx& c, int cls, F&& launch) {
   if (e != hipSuccess) return e;
   c.prof.pending.push_back({a, b, cls});
   if (c.prof.pending.size() > 8192) e = c.prof.harvest();
+  return e;
+}
+
+// The side stream waits for the caller's stream up to here.
+inline hipError_t fork_side(Ctx& c) {
+  hipError_t e = hipEventRecord(c.side.fork, c.stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c.side.s, c.side.fork, 0);
+  return e;
+}
+
+// The caller's stream waits for everything launched on the side stream.
+inline hipError_t join_side(Ctx& c) {
+  hipError_t e = hipEventRecord(c.side.join, c.side.s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c.stream, c.side.join, 0);
+  return e;
+}
+
+// Runs launchers (and their timing events) on the side stream.
+template <class F>
+hipError_t on_side(Ctx& c, F&& launch) {
+  const hipStream_t main = c.stream;
+  c.stream = c.side.s;
+  const hipError_t e = launch();
+  c.stream = main;
   return e;
 }
 

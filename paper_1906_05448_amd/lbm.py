@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
         "lbm_mlp_gradient_noalloc": (ctypes.c_int, [P, P, P, I64, P, P, P]),
         "lbm_mlp_sync": (ctypes.c_int, [P]),
         "lbm_mlp_destroy": (None, [P]),
+        "lbm_set_overlap": (ctypes.c_int, [P, I32]),
         "lbm_profile_enable": (ctypes.c_int, [P, I32]),
         "lbm_profile_read": (ctypes.c_int, [P, P, P]),
         "lbm_destroy": (None, [P]),
@@ -425,6 +426,11 @@ class Lattice:
         return s.value
 
     # -- kernel timing ----------------------------------------------------
+    def set_overlap(self, on: bool = True) -> None:
+        """Particle stage and next geometry beside the stream-collide kernel
+        on a second stream (lbm_set_overlap)."""
+        _check(lib().lbm_set_overlap(self._h, 1 if on else 0), "lbm_set_overlap")
+
     def profile_enable(self, on: bool = True) -> None:
         _check(lib().lbm_profile_enable(self._h, 1 if on else 0), "lbm_profile_enable")
 

@@ -126,6 +126,7 @@ int main(void) {
   printf("spectrum_null %d\n", lbm_spectrum(NULL, 1, 8, NULL, NULL));
   printf("budget_null %d\n", lbm_pipe_budget_add(NULL));
   printf("profile_null %d\n", lbm_profile_enable(NULL, 1));
+  printf("overlap_null %d\n", lbm_set_overlap(NULL, 1));
   printf("corrector_set_null %d\n", lbm_corrector_set(NULL, NULL, 0.0, 10.0, 0.03));
   printf("mlp_size %zu\n", lbm_mlp_workspace_size());
   printf("mlp_init_null %d\n", lbm_mlp_init(NULL, 0, NULL, NULL, NULL));
