@@ -133,3 +133,34 @@ def test_rejected_blobs_leave_the_context_unchanged():
     assert other.step_count == 2
     a.close()
     other.close()
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_rejected_particles_leave_the_context_unchanged(bc):
+    """lbm_set_particles validates everything before it changes anything: a
+    rejected call (unequal radii with the immersed boundary, a radius above
+    the configured maximum, a non-finite position) leaves fields, particles,
+    forces and the following steps exactly as without it."""
+    shape = (48, 44, 40)
+    cfg = gpu_config(nx=48, ny=44, nz=40, tau=0.55, bc=bc, ibm_retraction=0.4 if bc == 2 else 0.0,
+                     max_particles=6, max_radius=5.0)
+    runs = []
+    for reject in (False, True):
+        g = gpu_lattice(cfg)
+        _sphere_setup(bc, shape)(g)
+        g.step(3)
+        before = _snap(g)
+        if reject:
+            X = np.array([[10.0, 10.0, 10.0], [30.0, 28.0, 25.0]])
+            bad = [(X, [5.0, 4.0], None), (X, [5.0, 6.0], None), (np.array([[np.nan, 1.0, 1.0]]), [5.0], None)]
+            if bc == 1:
+                bad = bad[1:]
+            for x, r, _ in bad:
+                with pytest.raises(lbm.LbmError) as e:
+                    g.set_particles(x, r, mode=lbm.RELEASE)
+                assert e.value.status == -1
+            _assert_same(_snap(g), before)
+        g.step(4)
+        runs.append(_snap(g))
+        g.close()
+    _assert_same(runs[1], runs[0])
