@@ -378,7 +378,8 @@ int lbm_mlp_get_params(lbm_mlp* mlp, float* params_host);
 /* Device address of the FP32 parameter vector (for lbm_corrector_set). */
 const float* lbm_mlp_device_params(const lbm_mlp* mlp);
 
-/* y[n][16] = network(x[n][96]) for n >= 0 samples (device buffers). Async. */
+/* y[n][16] = network(x[n][96]) for n >= 0 samples (device buffers, both
+ * 16-byte aligned, else LBM_E_ARG). Async. */
 int lbm_mlp_forward(lbm_mlp* mlp, const uint16_t* x_dev, int64_t n, float* y_dev);
 
 /* Gradient of L = mean over the n samples and 9 outputs of (y - t)^2 at the

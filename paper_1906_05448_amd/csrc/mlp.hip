@@ -37,7 +37,7 @@ constexpr int kFBlock = 768;    // forward workgroup: 12 wavefronts share one co
 
 struct FwdLds {
   MlpWeights w;
-  __bf16 h[kFBlock / 64][kFwdTiles][16][kMlpHid];
+  __bf16 h[kFBlock / 64][kFwdTiles][16][kMlpHidRow];
 };
 
 __device__ __forceinline__ void load_tile(const __bf16* __restrict__ X, int64_t n, int64_t cell, bf16x8 (&a)[3]) {
@@ -69,12 +69,10 @@ k_mlp_forward(const float* __restrict__ theta, const __bf16* __restrict__ X, int
     f32x4 y[kFwdTiles];
     mlp_forward_tiles<kFwdTiles>(a, s.w, &s.h[wave][0][0][0], y);
 #pragma unroll
-    for (int t = 0; t < kFwdTiles; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t cell = base + t * 16 + grp * 4 + e;
-        if (cell < n) Y[cell * kMlpOutPad + col] = y[t][e];
-      }
+    for (int t = 0; t < kFwdTiles; ++t) {
+      const int64_t cell = base + t * 16 + col;
+      if (cell < n) *(f32x4*)&Y[cell * kMlpOutPad + grp * 4] = y[t];
+    }
   }
 }
 

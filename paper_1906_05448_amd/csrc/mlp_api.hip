@@ -136,6 +136,8 @@ const float* lbm_mlp_device_params(const lbm_mlp* h) { return h ? h->theta : nul
 
 int lbm_mlp_forward(lbm_mlp* h, const uint16_t* x, int64_t n, float* y) {
   if (!h || n < 0 || (n > 0 && (!x || !y))) return LBM_E_ARG;
+  // rows move as 16-byte vectors
+  if (n > 0 && (((uintptr_t)x | (uintptr_t)y) & 15u)) return LBM_E_ARG;
   return lbm::launch_mlp_forward(h->stream, h->theta, x, n, y) == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 

@@ -21,6 +21,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpIn = 85, kMlpInPad = 96, kMlpHid = 64, kMlpOut = 9, kMlpOutPad = 16;
+// Row stride of the multi-tile forward's activation rows: 144 bytes (16-byte
+// aligned rows for the operand reads; the 16 rows a wavefront writes at once
+// start 4 banks apart instead of all on one bank).
+constexpr int kMlpHidRow = 72;
 constexpr int kMlpParams = 10249;
 constexpr int kOffW1 = 0, kOffB1 = 64 * 85, kOffW2 = kOffB1 + 64, kOffB2 = kOffW2 + 64 * 64, kOffW3 = kOffB2 + 64,
               kOffB3 = kOffW3 + 9 * 64;
@@ -132,15 +136,27 @@ __device__ __forceinline__ f32x4 mlp_forward_tile(const bf16x8 (&a1)[3], const M
 
 // Inference on T 16-sample tiles at once by one wavefront: each weight
 // operand is read from LDS once for the T tiles, and the T independent
-// product chains hide one another's matrix-core and LDS latency. h: this
-// wave's [T][16][64] BF16 LDS rows, holding the first hidden layer and then,
-// once every lane has read it, the second. y receives y + b3 per tile in the
-// C layout of mlp_forward_tile.
+// product chains hide one another's matrix-core and LDS latency. The
+// products are taken transposed (the weights as the A operand, a tile's
+// samples as the B operand, which is the same register content as the
+// single-tile form's operands in the other roles), so a lane's four results
+// are four consecutive neurons of one sample: one 8-byte LDS store per lane
+// and neuron block instead of four 2-byte ones. h: this wave's [T][16][64]
+// BF16 LDS rows, holding the first hidden layer and then, once every lane
+// has read it, the second. y receives y + b3 per tile: lane l holds outputs
+// 4 (l / 16) .. 4 (l / 16) + 3 of sample l % 16.
 template <int T>
 __device__ __forceinline__ void mlp_forward_tiles(const bf16x8 (&a1)[T][3], const MlpWeights& w, __bf16* h,
                                                   f32x4 (&y)[T]) {
   const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
-  constexpr int kTile = 16 * kMlpHid;
+  constexpr int kTile = 16 * kMlpHidRow;
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  auto put = [&](int t, int j, const f32x4& z, const float* bias) {
+    bf16x4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (__bf16)silu(z[e] + bias[j + e]);
+    *(bf16x4*)&h[t * kTile + col * kMlpHidRow + j] = o;
+  };
   // layer 1
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
@@ -149,25 +165,21 @@ __device__ __forceinline__ void mlp_forward_tiles(const bf16x8 (&a1)[T][3], cons
     for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 3; ++ks) {
-      const bf16x8 b = lds8(&w.W1[n * 16 + col][ks * 32 + grp * 8]);
+      const bf16x8 wop = lds8(&w.W1[n * 16 + col][ks * 32 + grp * 8]);
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma(a1[t][ks], b, acc[t]);
+      for (int t = 0; t < T; ++t) acc[t] = mfma(wop, a1[t][ks], acc[t]);
     }
-    const int j = n * 16 + col;
-    const float bj = w.b1[j];
 #pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) h[t * kTile + (grp * 4 + e) * kMlpHid + j] = (__bf16)silu(acc[t][e] + bj);
+    for (int t = 0; t < T; ++t) put(t, n * 16 + grp * 4, acc[t], w.b1);
   }
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes done
   __builtin_amdgcn_wave_barrier();
-  // layer 2: every A operand read before the outputs overwrite h
+  // layer 2: every B operand read before the outputs overwrite h
   bf16x8 a2[T][2];
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) a2[t][ks] = lds8(&h[t * kTile + col * kMlpHid + ks * 32 + grp * 8]);
+    for (int ks = 0; ks < 2; ++ks) a2[t][ks] = lds8(&h[t * kTile + col * kMlpHidRow + ks * 32 + grp * 8]);
   __builtin_amdgcn_s_waitcnt(0xc07f);
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -177,16 +189,12 @@ __device__ __forceinline__ void mlp_forward_tiles(const bf16x8 (&a1)[T][3], cons
     for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const bf16x8 b = lds8(&w.W2[n * 16 + col][ks * 32 + grp * 8]);
+      const bf16x8 wop = lds8(&w.W2[n * 16 + col][ks * 32 + grp * 8]);
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma(a2[t][ks], b, acc[t]);
+      for (int t = 0; t < T; ++t) acc[t] = mfma(wop, a2[t][ks], acc[t]);
     }
-    const int j = n * 16 + col;
-    const float bj = w.b2[j];
 #pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) h[t * kTile + (grp * 4 + e) * kMlpHid + j] = (__bf16)silu(acc[t][e] + bj);
+    for (int t = 0; t < T; ++t) put(t, n * 16 + grp * 4, acc[t], w.b2);
   }
   __builtin_amdgcn_s_waitcnt(0xc07f);
   __builtin_amdgcn_wave_barrier();
@@ -195,20 +203,19 @@ __device__ __forceinline__ void mlp_forward_tiles(const bf16x8 (&a1)[T][3], cons
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) a3[t][ks] = lds8(&h[t * kTile + col * kMlpHid + ks * 32 + grp * 8]);
+    for (int ks = 0; ks < 2; ++ks) a3[t][ks] = lds8(&h[t * kTile + col * kMlpHidRow + ks * 32 + grp * 8]);
 #pragma unroll
   for (int t = 0; t < T; ++t) y[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
-    const bf16x8 b = lds8(&w.W3[col][ks * 32 + grp * 8]);
+    const bf16x8 wop = lds8(&w.W3[col][ks * 32 + grp * 8]);
 #pragma unroll
-    for (int t = 0; t < T; ++t) y[t] = mfma(a3[t][ks], b, y[t]);
+    for (int t = 0; t < T; ++t) y[t] = mfma(wop, a3[t][ks], y[t]);
   }
-  const float b3 = w.b3[col];
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) y[t][e] += b3;
+    for (int e = 0; e < 4; ++e) y[t][e] += w.b3[grp * 4 + e];
   // h is read again by the next call's first writes: keep this call's reads
   // ahead of them
   __builtin_amdgcn_s_waitcnt(0xc07f);
