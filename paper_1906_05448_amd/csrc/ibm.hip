@@ -359,9 +359,10 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
 // One 1024-thread workgroup per sphere, MPT markers per thread.
 // LDS: rows x (u32 forcing row bits, u32 row prefix), then fcap x 12
 // bytes holding first the staged velocities (float3 per node) and, once every
-// marker has interpolated, the spread sums of the three components (int32
-// per component and node), then fcap u32 (the nodes' slot-list entries, kept
-// for the write-back). About 74 KB for r = 8, so two spheres share a compute
+// marker has interpolated, the spread sums (per node the x and y sums packed
+// in one 64-bit word, so one 64-bit LDS atomic adds both, and the z sum in
+// a 32-bit word), then fcap u32 (the nodes' slot-list entries, kept for the
+// write-back). About 74 KB for r = 8, so two spheres share a compute
 // unit and one's memory trips overlap the other's LDS work.
 //
 // The spread sums are 32-bit fixed point in units of 2^-e with a scale
@@ -392,6 +393,15 @@ __device__ __forceinline__ int spread_exponent(float max_dF, float dV) {
   int ex;
   (void)frexpf(B, &ex);                // B < 2^ex
   return min(kShUnitExp, max(0, 30 - ex));
+}
+
+// A node's x, y, z spread sums from the packed word y 2^32 + x (both
+// signed, |x|, |y| < 2^31, so the low word is x and the rest an exact
+// multiple of 2^32) and the z word.
+__device__ __forceinline__ void unpack_sums(unsigned long long xy, int z, int (&a)[3]) {
+  a[0] = (int)(uint32_t)xy;
+  a[1] = (int)(((long long)xy - (long long)a[0]) / 4294967296ll);
+  a[2] = z;
 }
 
 // Slot-list entries j0 + threadIdx.x + i kPassBlock of a sphere and their
@@ -429,7 +439,10 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
   const int rows = side * side;
   uint2* rbp = (uint2*)lds;  // per row: forcing bits, exclusive prefix
   float* uj = (float*)(rbp + rows);
-  int* acc = (int*)(rbp + rows);  // aliases uj once every marker has interpolated
+  // The spread sums alias uj once every marker has interpolated: x and y of
+  // a node packed in one 64-bit word (y * 2^32 + x, both signed), z apart.
+  unsigned long long* acc_xy = (unsigned long long*)(rbp + rows);
+  int* acc_z = (int*)(acc_xy + fcap);
   uint32_t* sl = (uint32_t*)(uj + 3 * (size_t)fcap);
   const int p = blockIdx.x;
   const double* Xp = X + 3 * p;
@@ -590,7 +603,10 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
     double* out = threadIdx.x < 3 ? F_ib + 3 * p + threadIdx.x : T_ib + 3 * p + (threadIdx.x - 3);
     *out = (first ? 0.0 : *out) + t;
   }
-  for (uint32_t j = threadIdx.x; j < 3 * cnt; j += kPassBlock) acc[j] = 0;
+  for (uint32_t j = threadIdx.x; j < cnt; j += kPassBlock) {
+    acc_xy[j] = 0ull;
+    acc_z[j] = 0;
+  }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
@@ -615,9 +631,10 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
       for (int jx = 0; jx < 4; ++jx) {
         const float w = wx[jx] * wyz;
         const uint32_t j = j0 + jx;
-        atomicAdd(&acc[3 * j], __float2int_rn(ldexpf(dF[m][0] * w, e)));
-        atomicAdd(&acc[3 * j + 1], __float2int_rn(ldexpf(dF[m][1] * w, e)));
-        atomicAdd(&acc[3 * j + 2], __float2int_rn(ldexpf(dF[m][2] * w, e)));
+        const long long ax = __float2int_rn(ldexpf(dF[m][0] * w, e));
+        const long long ay = __float2int_rn(ldexpf(dF[m][1] * w, e));
+        atomicAdd(&acc_xy[j], (unsigned long long)(ay * 4294967296ll + ax));
+        atomicAdd(&acc_z[j], __float2int_rn(ldexpf(dF[m][2] * w, e)));
       }
     }
   }
@@ -645,9 +662,11 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
       if (j >= cnt) continue;
       if (!(w[i] & kSlotShared)) {
         if (w[i] >= s_cap) continue;
-        const float4 fn = make_float4(old[i].x + (float)ldexp((double)acc[3 * j], -e),
-                                      old[i].y + (float)ldexp((double)acc[3 * j + 1], -e),
-                                      old[i].z + (float)ldexp((double)acc[3 * j + 2], -e), 0.0f);
+        int a3[3];
+        unpack_sums(acc_xy[j], acc_z[j], a3);
+        const float4 fn = make_float4(old[i].x + (float)ldexp((double)a3[0], -e),
+                                      old[i].y + (float)ldexp((double)a3[1], -e),
+                                      old[i].z + (float)ldexp((double)a3[2], -e), 0.0f);
         if (pf_p && !last)
           pf_p[j] = fn;
         else
@@ -655,8 +674,10 @@ k_ibm_pass(const double* __restrict__ X, const double* __restrict__ U, const dou
       } else {
         const uint32_t q = w[i] & ~kSlotShared;
         if (q >= sh_cap) continue;
+        int a3s[3];
+        unpack_sums(acc_xy[j], acc_z[j], a3s);
         for (int k = 0; k < 3; ++k) {
-          const int a = acc[3 * j + k];
+          const int a = a3s[k];
           if (a)
             atomicAdd(sh_acc + (size_t)k * sh_cap + q,
                       (unsigned long long)((long long)a * (1ll << (kShUnitExp - e))));
