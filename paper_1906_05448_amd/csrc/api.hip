@@ -23,10 +23,15 @@ size_t n_nodes(const lbm_config& c) { return (size_t)c.nx * (size_t)c.ny * (size
 
 int lattice_q(const lbm_config& c) { return c.lattice == LBM_LATTICE_D3Q27 ? q27::kQ : kQ; }
 
-size_t pop_bytes(const lbm_config& c) {
-  const size_t elem = c.store == LBM_STORE_F32 ? 4 : 2;
-  return align_up((size_t)lattice_q(c) * n_nodes(c) * elem);
+size_t pop_elem_bytes(const lbm_config& c) { return c.store == LBM_STORE_F32 ? 4 : 2; }
+
+// Elements from one population array to the next (the node count plus the
+// pad of make_dims).
+size_t pop_stride(const lbm_config& c) {
+  return (size_t)make_dims(c.nx, c.ny, c.nz, (uint32_t)pop_elem_bytes(c)).S;
 }
+
+size_t pop_bytes(const lbm_config& c) { return align_up((size_t)lattice_q(c) * pop_stride(c) * pop_elem_bytes(c)); }
 
 bool has_particles(const lbm_config& c) { return c.bc != LBM_BC_NONE && c.max_particles > 0; }
 
@@ -565,7 +570,7 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     delete h;
     return LBM_E_HIP;
   }
-  c.dims = make_dims(cfg->nx, cfg->ny, cfg->nz);
+  c.dims = make_dims(cfg->nx, cfg->ny, cfg->nz, (uint32_t)pop_elem_bytes(*cfg));
   c.rates.s_nu = (float)(1.0 / cfg->tau);
   c.rates.s_e = (float)cfg->s_e;
   c.rates.s_eps = (float)cfg->s_eps;
@@ -924,8 +929,21 @@ lbm_config normalized(const lbm_config& a) {
   return z;
 }
 
-size_t pop_exact_bytes(const lbm_config& c) {
-  return (size_t)lattice_q(c) * n_nodes(c) * (c.store == LBM_STORE_F32 ? 4 : 2);
+// The populations in a state blob: the Q arrays of N elements back to back
+// (without the pad between the arrays in device memory).
+size_t pop_exact_bytes(const lbm_config& c) { return (size_t)lattice_q(c) * n_nodes(c) * pop_elem_bytes(c); }
+
+// Copies the populations between a blob (arrays back to back) and device
+// memory (arrays pop_stride apart), one array per copy.
+hipError_t copy_pops(const Ctx& c, char* blob, void* dev, bool to_host) {
+  const size_t elem = pop_elem_bytes(c.cfg), n = n_nodes(c.cfg) * elem, s = pop_stride(c.cfg) * elem;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < lattice_q(c.cfg) && e == hipSuccess; ++i) {
+    char* d = (char*)dev + (size_t)i * s;
+    e = to_host ? hipMemcpyAsync(blob + (size_t)i * n, d, n, hipMemcpyDeviceToHost, c.stream)
+                : hipMemcpyAsync(d, blob + (size_t)i * n, n, hipMemcpyHostToDevice, c.stream);
+  }
+  return e;
 }
 
 size_t particle_block_bytes(int32_t np) { return (size_t)np * (3 * kStateVec3 + 2) * sizeof(double); }
@@ -1007,7 +1025,7 @@ int lbm_get_state(lbm_ctx* h, void* host, size_t bytes) {
   char* out = (char*)host;
   memcpy(out, &hd, sizeof(hd));
   size_t off = sizeof(hd);
-  hipError_t e = hipMemcpyAsync(out + off, c.f_cur, hd.pop_bytes, hipMemcpyDeviceToHost, c.stream);
+  hipError_t e = copy_pops(c, out + off, c.f_cur, true);
   off += hd.pop_bytes;
   double* v[kStateVec3 + 2];
   particle_arrays(c, v);
@@ -1081,7 +1099,7 @@ int lbm_set_state(lbm_ctx* h, const void* host, size_t bytes) {
   c.pcur = 0;
   c.ocur = 0;
   size_t off = sizeof(hd);
-  hipError_t e = hipMemcpyAsync(c.f_cur, in + off, hd.pop_bytes, hipMemcpyHostToDevice, c.stream);
+  hipError_t e = copy_pops(c, (char*)in + off, c.f_cur, false);
   off += hd.pop_bytes;
   if (e == hipSuccess && has_particles(cfg)) e = zero_particle_accumulators(c);
   double* v[kStateVec3 + 2];

@@ -3,7 +3,7 @@
 // populations; equilibrium initialisation; fields; and the links and linear
 // interpolated bounce-back of the static pipe wall (Sec. 2.1).
 //
-// Layout: 27 arrays of N FP32 shifted populations, x fastest. The fused
+// Layout: 27 arrays of N FP32 shifted populations, x fastest, S apart. The fused
 // kernel uses the D3Q19 kernel's 128 x 2 tiles in XCD-contiguous order, one
 // node per lane, the nine source row offsets in scalar registers and
 // non-temporal stores: 216 bytes of HBM traffic per node and step.
@@ -27,7 +27,7 @@ k_sc27(const float* __restrict__ A, float* __restrict__ B, Dims d, Tiles tg, Rat
   const int x = t.x, z = t.z;
   const int y = __builtin_amdgcn_readfirstlane(t.y);
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const uint32_t N = d.N;
+  const uint32_t S = d.S;  // population array stride
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - c_y for c_y = -1, 0, 1
   const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
@@ -38,36 +38,37 @@ k_sc27(const float* __restrict__ A, float* __restrict__ B, Dims d, Tiles tg, Rat
   for (int i = 0; i < q27::kQ; ++i) {
     const uint32_t src = row(ys[cy(i) + 1], zs[cz(i) + 1]);
     const uint32_t o = cx(i) > 0 ? oxm : (cx(i) < 0 ? oxp : ox);
-    g[i] = *(const float*)((const char*)(A + (size_t)i * N + src) + o);
+    g[i] = *(const float*)((const char*)(A + (size_t)i * S + src) + o);
   }
   float rho, ux, uy, uz;
   collide(g, F.x, F.y, F.z, r, rho, ux, uy, uz);
   const uint32_t r00 = row(y, z);
 #pragma unroll
-  for (int i = 0; i < q27::kQ; ++i) __builtin_nontemporal_store(g[i], (float*)((char*)(B + (size_t)i * N + r00) + ox));
+  for (int i = 0; i < q27::kQ; ++i) __builtin_nontemporal_store(g[i], (float*)((char*)(B + (size_t)i * S + r00) + ox));
   const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
   if (bad) atomicOr(err, kErrUnstable);
 }
 
 __global__ void __launch_bounds__(256)
-k_init27(const float* __restrict__ u, const float* __restrict__ rho, float* __restrict__ f, uint32_t N) {
+k_init27(const float* __restrict__ u, const float* __restrict__ rho, float* __restrict__ f, uint32_t N, uint32_t S) {
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
   const float r = rho ? rho[n] : 1.0f;
   const float ux = u[n], uy = u[(size_t)N + n], uz = u[2 * (size_t)N + n];
 #pragma unroll
-  for (int i = 0; i < q27::kQ; ++i) f[(size_t)i * N + n] = q27::geq(i, r, ux, uy, uz);
+  for (int i = 0; i < q27::kQ; ++i) f[(size_t)i * S + n] = q27::geq(i, r, ux, uy, uz);
 }
 
 // rho and u = (sum_i c_i f~_i - F/2) / rho from post-collision populations.
 __global__ void __launch_bounds__(256)
-k_fields27(const float* __restrict__ f, uint32_t N, float3 F, float* __restrict__ u, float* __restrict__ rho) {
+k_fields27(const float* __restrict__ f, uint32_t N, uint32_t S, float3 F, float* __restrict__ u,
+           float* __restrict__ rho) {
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < q27::kQ; ++i) {
-    const float g = f[(size_t)i * N + n];
+    const float g = f[(size_t)i * S + n];
     drho += g;
     jx += (float)cx(i) * g;
     jy += (float)cy(i) * g;
@@ -127,16 +128,16 @@ k_wall_bounce27(float* __restrict__ A, Dims d, uint32_t count, const uint32_t* _
   int x, y, z;
   unpack_xyz(node[k], x, y, z);
   const uint32_t n0 = node_index(x, y, z, d.nx, d.ny);
-  const size_t N = d.N;
-  const float fa0 = A[(size_t)a * N + n0];
+  const size_t S = d.S;
+  const float fa0 = A[(size_t)a * S + n0];
   float v = fa0;
   if ((meta >> 5) == kSchemeLinear) {
     if (q < 0.5f)
-      v = 2.0f * q * fa0 + (1.0f - 2.0f * q) * A[(size_t)a * N + nb27(x, y, z, -1, a, d)];
+      v = 2.0f * q * fa0 + (1.0f - 2.0f * q) * A[(size_t)a * S + nb27(x, y, z, -1, a, d)];
     else
-      v = (fa0 + (2.0f * q - 1.0f) * A[(size_t)opp(a) * N + n0]) / (2.0f * q);
+      v = (fa0 + (2.0f * q - 1.0f) * A[(size_t)opp(a) * S + n0]) / (2.0f * q);
   }
-  A[(size_t)opp(a) * N + nb27(x, y, z, 1, a, d)] = v;
+  A[(size_t)opp(a) * S + nb27(x, y, z, 1, a, d)] = v;
 }
 
 Rates rates27(const Ctx& c) {
@@ -161,13 +162,13 @@ hipError_t launch_stream_collide27(const Ctx& c, const void* A, void* B) {
 
 hipError_t launch_init_equilibrium27(const Ctx& c, const float* u, const float* rho, void* f) {
   const uint32_t N = c.dims.N;
-  hipLaunchKernelGGL(k_init27, dim3((N + 255) / 256), dim3(256), 0, c.stream, u, rho, (float*)f, N);
+  hipLaunchKernelGGL(k_init27, dim3((N + 255) / 256), dim3(256), 0, c.stream, u, rho, (float*)f, N, c.dims.S);
   return hipGetLastError();
 }
 
 hipError_t launch_fields27(const Ctx& c, const void* f, float3 F, float* u, float* rho) {
   const uint32_t N = c.dims.N;
-  hipLaunchKernelGGL(k_fields27, dim3((N + 255) / 256), dim3(256), 0, c.stream, (const float*)f, N, F, u, rho);
+  hipLaunchKernelGGL(k_fields27, dim3((N + 255) / 256), dim3(256), 0, c.stream, (const float*)f, N, c.dims.S, F, u, rho);
   return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 // equilibrium initialisation and macroscopic-field extraction.
 //
 // Memory layout: structure of arrays, population i of node n at
-// f[i * N + n], n = x + nx * (y + ny * z). The pull form
+// f[i * S + n], n = x + nx * (y + ny * z), with the array stride S the node
+// count N plus a 1 KB pad (Dims::S). The pull form
 //   f_i(x, t+1) = f~_i(x - c_i, t)
 // reads each of the 19 arrays once, shifted by c_i, and writes each once,
 // so one node update moves 19 * 2 * sizeof(store) bytes of HBM: 152 B in
@@ -69,7 +70,7 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
     add_ib_force(ib, n0, F);
   }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const uint32_t N = d.N;
+  const uint32_t S = d.S;  // population array stride
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
@@ -91,12 +92,12 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
     const uint32_t o = cx_of(i) > 0 ? oxm : (cx_of(i) < 0 ? oxp : ox);
     if (STORE == 0) {
       // uniform row base (scalar) plus one of three column offsets
-      g[i] = P::load((const T*)((const char*)(A + (size_t)i * N + srow[i]) + o));
+      g[i] = P::load((const T*)((const char*)(A + (size_t)i * S + srow[i]) + o));
     } else {
       // direction base plus one 32-bit byte offset per lane (N * sizeof(T)
       // <= 4 GiB is checked at init)
       const uint32_t src = srow[i] + (uint32_t)(cx_of(i) > 0 ? xm : (cx_of(i) < 0 ? xp : x));
-      g[i] = P::load((const T*)((const char*)(A + (size_t)i * N) + src * (uint32_t)sizeof(T)));
+      g[i] = P::load((const T*)((const char*)(A + (size_t)i * S) + src * (uint32_t)sizeof(T)));
     }
   }
 
@@ -107,9 +108,9 @@ k_stream_collide(const typename Pop<STORE>::T* __restrict__ A, typename Pop<STOR
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     if (STORE == 0)
-      P::store_stream((T*)((char*)(B + (size_t)i * N + r00) + ox), g[i]);
+      P::store_stream((T*)((char*)(B + (size_t)i * S + r00) + ox), g[i]);
     else
-      P::store_stream((T*)((char*)(B + (size_t)i * N) + noff), g[i]);
+      P::store_stream((T*)((char*)(B + (size_t)i * S) + noff), g[i]);
   }
 
   const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
@@ -157,7 +158,7 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   uint32_t(*seg)[kSegRow] = seg_all[wv];
   uint16_t* tail = tail_all[wv];
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const uint32_t N = d.N;
+  const uint32_t S = d.S;  // population array stride
   const int x0 = (int)bx * kSegW;
   const int w = min(kSegW, nx - x0);  // nodes in the segment, even
   auto row = [&](int yy, int zz) -> uint32_t { return ((uint32_t)zz * (uint32_t)ny + (uint32_t)yy) * (uint32_t)nx; };
@@ -179,7 +180,7 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   uint16_t e[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const _Float16* rowp = A + (size_t)i * N + srow[i];
+    const _Float16* rowp = A + (size_t)i * S + srow[i];
     v[i] = pair_live ? __builtin_nontemporal_load((const uint32_t*)(rowp + x0 + 2 * (int)lane)) : 0u;
     // edge node: a vector load at a uniform address (scalar loads of the
     // same nodes measured 7.5% extra HBM reads: their lines are not served
@@ -233,7 +234,7 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
     const uint32_t off = (r00 + (uint32_t)(x0 + 2 * (int)lane)) * 2u;
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      __builtin_nontemporal_store(seg[i][1 + lane], (uint32_t*)((char*)(B + (size_t)i * N) + off));
+      __builtin_nontemporal_store(seg[i][1 + lane], (uint32_t*)((char*)(B + (size_t)i * S) + off));
   }
   if (bad) atomicOr(err, kErrUnstable);
 }
@@ -261,7 +262,7 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   uint32_t(*seg)[kSegRow] = seg_all[wv];
   uint16_t* tail = tail_all[wv];
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const uint32_t N = d.N;
+  const uint32_t S = d.S;  // population array stride
   const int x0 = wv * kSegW;
   constexpr int w = kSegW;
   // the wavefronts of the left and right segments (periodic within the row)
@@ -281,7 +282,7 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   uint32_t v[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i)
-    v[i] = __builtin_nontemporal_load((const uint32_t*)(A + (size_t)i * N + srow[i] + x0 + 2 * (int)lane));
+    v[i] = __builtin_nontemporal_load((const uint32_t*)(A + (size_t)i * S + srow[i] + x0 + 2 * (int)lane));
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];  // halves 2 + 2 lane, 3 + 2 lane
@@ -330,7 +331,7 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
     const uint32_t off = (r00 + (uint32_t)(x0 + 2 * (int)lane)) * 2u;
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      __builtin_nontemporal_store(seg[i][1 + lane], (uint32_t*)((char*)(B + (size_t)i * N) + off));
+      __builtin_nontemporal_store(seg[i][1 + lane], (uint32_t*)((char*)(B + (size_t)i * S) + off));
   }
   if (bad) atomicOr(err, kErrUnstable);
 }
@@ -360,7 +361,7 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
   const int z = (int)bz;
   float(*seg)[kRow] = seg_all[wv];
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const uint32_t N = d.N;
+  const uint32_t S = d.S;  // population array stride
   const int x0 = (int)bx * 512 + wv * 64;
   const int x = x0 + lane;
   const bool whole_row = d.gxr == 1u;
@@ -379,7 +380,7 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
   float v[kQ], e[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const float* rowp = A + (size_t)i * N + srow[i];
+    const float* rowp = A + (size_t)i * S + srow[i];
     v[i] = __builtin_nontemporal_load(rowp + x);
     e[i] = 0.0f;
     if (cx_of(i) > 0 && wl < 0) e[i] = rowp[xl];
@@ -410,7 +411,7 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
   float rho, ux, uy, uz;
   mrt_collide(g, F.x, F.y, F.z, r, rho, ux, uy, uz);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) Pop<0>::store_stream(B + (size_t)i * N + n, g[i]);
+  for (int i = 0; i < kQ; ++i) Pop<0>::store_stream(B + (size_t)i * S + n, g[i]);
   const bool bad = !(rho > 0.0f) || !(ux * ux + uy * uy + uz * uz < 0.1225f);
   if (bad) atomicOr(err, kErrUnstable);
 }
@@ -418,21 +419,21 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
 template <int STORE>
 __global__ void __launch_bounds__(256)
 k_init_equilibrium(const float* __restrict__ u, const float* __restrict__ rho, typename Pop<STORE>::T* __restrict__ f,
-                   uint32_t N) {
+                   uint32_t N, uint32_t S) {
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
   const float r = rho ? rho[n] : 1.0f;
   const float ux = u[n], uy = u[(size_t)N + n], uz = u[2 * (size_t)N + n];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) Pop<STORE>::store(f + (size_t)i * N + n, geq(i, r, ux, uy, uz));
+  for (int i = 0; i < kQ; ++i) Pop<STORE>::store(f + (size_t)i * S + n, geq(i, r, ux, uy, uz));
 }
 
 // rho and u from post-collision populations: the Guo collision adds F to the
 // momentum, so sum_i c_i f~_i = rho u + F/2 and u = (sum_i c_i f~_i - F/2)/rho.
 template <int STORE, int MODE>
 __global__ void __launch_bounds__(256)
-k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F0, IbView ib, float* __restrict__ u,
-         float* __restrict__ rho) {
+k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, uint32_t S, float3 F0, IbView ib,
+         float* __restrict__ u, float* __restrict__ rho) {
   const uint32_t n = blockIdx.x * 256u + threadIdx.x;
   if (n >= N) return;
   float3 F = F0;
@@ -443,7 +444,7 @@ k_fields(const typename Pop<STORE>::T* __restrict__ f, uint32_t N, float3 F0, Ib
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const float g = Pop<STORE>::load(f + (size_t)i * N + n);
+    const float g = Pop<STORE>::load(f + (size_t)i * S + n);
     drho += g;
     jx += cx_of(i) * g;
     jy += cy_of(i) * g;
@@ -465,9 +466,9 @@ hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rh
   const uint32_t N = c.dims.N;
   const dim3 grid((N + 255) / 256), block(256);
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL(k_init_equilibrium<0>, grid, block, 0, c.stream, u, rho, (float*)f, N);
+    hipLaunchKernelGGL(k_init_equilibrium<0>, grid, block, 0, c.stream, u, rho, (float*)f, N, c.dims.S);
   else
-    hipLaunchKernelGGL(k_init_equilibrium<1>, grid, block, 0, c.stream, u, rho, (_Float16*)f, N);
+    hipLaunchKernelGGL(k_init_equilibrium<1>, grid, block, 0, c.stream, u, rho, (_Float16*)f, N, c.dims.S);
   return hipGetLastError();
 }
 
@@ -547,9 +548,9 @@ hipError_t launch_fields(const Ctx& c, const void* f, float3 F, float* u, float*
   const dim3 grid((N + 255) / 256), block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL((k_fields<0, 0>), grid, block, 0, c.stream, (const float*)f, N, F, none, u, rho);
+    hipLaunchKernelGGL((k_fields<0, 0>), grid, block, 0, c.stream, (const float*)f, N, c.dims.S, F, none, u, rho);
   else
-    hipLaunchKernelGGL((k_fields<1, 0>), grid, block, 0, c.stream, (const _Float16*)f, N, F, none, u, rho);
+    hipLaunchKernelGGL((k_fields<1, 0>), grid, block, 0, c.stream, (const _Float16*)f, N, c.dims.S, F, none, u, rho);
   return hipGetLastError();
 }
 
@@ -560,9 +561,9 @@ hipError_t launch_fields_ibm(const Ctx& c, const void* f, int buf, float* u, flo
   const dim3 grid((N + 255) / 256), block(256);
   const IbView ib{c.ibm.bits[buf], c.ibm.rank[buf], c.ibm.fib[buf], c.ibm.s_cap, ibm_body_force_mask(c)};
   if (c.cfg.store == LBM_STORE_F32)
-    hipLaunchKernelGGL((k_fields<0, 2>), grid, block, 0, c.stream, (const float*)f, N, c.body_force, ib, u, rho);
+    hipLaunchKernelGGL((k_fields<0, 2>), grid, block, 0, c.stream, (const float*)f, N, c.dims.S, c.body_force, ib, u, rho);
   else
-    hipLaunchKernelGGL((k_fields<1, 2>), grid, block, 0, c.stream, (const _Float16*)f, N, c.body_force, ib, u, rho);
+    hipLaunchKernelGGL((k_fields<1, 2>), grid, block, 0, c.stream, (const _Float16*)f, N, c.dims.S, c.body_force, ib, u, rho);
   return hipGetLastError();
 }
 

@@ -30,8 +30,8 @@ constexpr int kLinkBlock = kLinkSliceThreads;  // a slice of a sphere's links pe
 constexpr int kRefillList = 4096; // nodes listed per round of rows in the refill
 
 template <int STORE>
-__device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint32_t N, uint32_t n) {
-  return Pop<STORE>::load(f + (size_t)i * N + n);
+__device__ __forceinline__ float ld(const typename Pop<STORE>::T* f, int i, uint32_t S, uint32_t n) {
+  return Pop<STORE>::load(f + (size_t)i * S + n);
 }
 
 // Interpolated value of the entering population for one link, from the
@@ -63,14 +63,14 @@ __device__ __forceinline__ void bounce_sources(int a, float q, uint32_t nf, uint
 }
 
 template <int STORE>
-__device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, uint32_t N, uint32_t nf, uint32_t nm1,
+__device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, uint32_t S, uint32_t nf, uint32_t nm1,
                                               uint32_t nm2, int a, uint32_t scheme, float q, float delta) {
   int i1, i2;
   uint32_t n1, n2;
   bounce_sources(a, q, nf, nm1, nm2, i1, n1, i2, n2);
-  const float ga0 = ld<STORE>(A, a, N, nf);
-  const float v1 = scheme != kSchemeHalfway ? ld<STORE>(A, i1, N, n1) : 0.0f;
-  const float v2 = scheme == kSchemeQuadratic ? ld<STORE>(A, i2, N, n2) : 0.0f;
+  const float ga0 = ld<STORE>(A, a, S, nf);
+  const float v1 = scheme != kSchemeHalfway ? ld<STORE>(A, i1, S, n1) : 0.0f;
+  const float v2 = scheme == kSchemeQuadratic ? ld<STORE>(A, i2, S, n2) : 0.0f;
   return bounce_from(ga0, v1, v2, scheme, q, delta);
 }
 
@@ -128,9 +128,9 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
       int i1, i2;
       uint32_t m1, m2;
       bounce_sources(a, q[i], n0[i], nm1, nm2, i1, m1, i2, m2);
-      g0[i] = ld<STORE>(A, a, d.N, n0[i]);
-      if (scheme != kSchemeHalfway) g1[i] = ld<STORE>(A, i1, d.N, m1);
-      if (scheme == kSchemeQuadratic) g2[i] = ld<STORE>(A, i2, d.N, m2);
+      g0[i] = ld<STORE>(A, a, d.S, n0[i]);
+      if (scheme != kSchemeHalfway) g1[i] = ld<STORE>(A, i1, d.S, m1);
+      if (scheme == kSchemeQuadratic) g2[i] = ld<STORE>(A, i2, d.S, m2);
     }
 #pragma unroll
     for (int i = 0; i < kLinks; ++i) {
@@ -148,7 +148,7 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
                             Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
       const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
       const float gnew = bounce_from(g0[i], g1[i], g2[i], scheme, q[i], delta);
-      Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns[i], gnew);
+      Pop<STORE>::store(A + (size_t)opp_of(a) * d.S + ns[i], gnew);
       const double fa = (double)g0[i] + (double)w_of(a);
       const double fb = (double)gnew + (double)w_of(a);
       const double c[3] = {(double)cx, (double)cy, (double)cz};
@@ -205,8 +205,8 @@ k_wall_bounce(typename Pop<STORE>::T* A, Dims d, uint32_t count, const uint32_t*
   const uint32_t n0 = node_index(x, y, z, d.nx, d.ny);
   const uint32_t nm1 = node_index(wrap1(x - cx, d.nx), wrap1(y - cy, d.ny), wrap1(z - cz, d.nz), d.nx, d.ny);
   const uint32_t ns = node_index(wrap1(x + cx, d.nx), wrap1(y + cy, d.ny), wrap1(z + cz, d.nz), d.nx, d.ny);
-  const float gnew = bounce_value<STORE>(A, d.N, n0, nm1, nm1, a, meta >> 5, q, 0.0f);
-  Pop<STORE>::store(A + (size_t)opp_of(a) * d.N + ns, gnew);
+  const float gnew = bounce_value<STORE>(A, d.S, n0, nm1, nm1, a, meta >> 5, q, 0.0f);
+  Pop<STORE>::store(A + (size_t)opp_of(a) * d.S + ns, gnew);
 }
 
 __device__ __forceinline__ bool valid_node(const uint32_t* o_old, const uint32_t* o_new, uint32_t n) {
@@ -246,9 +246,9 @@ __device__ void refill_node(typename Pop<STORE>::T* B, const Dims& d, const uint
   float ge[kQ];
   if (ok[0] && ok[1] && ok[2]) {
     for (int i = 0; i < kQ; ++i)
-      ge[i] = 3.0f * ld<STORE>(B, i, d.N, nb[0]) - 3.0f * ld<STORE>(B, i, d.N, nb[1]) + ld<STORE>(B, i, d.N, nb[2]);
+      ge[i] = 3.0f * ld<STORE>(B, i, d.S, nb[0]) - 3.0f * ld<STORE>(B, i, d.S, nb[1]) + ld<STORE>(B, i, d.S, nb[2]);
   } else if (ok[0] && ok[1]) {
-    for (int i = 0; i < kQ; ++i) ge[i] = 2.0f * ld<STORE>(B, i, d.N, nb[0]) - ld<STORE>(B, i, d.N, nb[1]);
+    for (int i = 0; i < kQ; ++i) ge[i] = 2.0f * ld<STORE>(B, i, d.S, nb[0]) - ld<STORE>(B, i, d.S, nb[1]);
   } else {
     // equilibrium of the mean density and mean raw velocity of the valid
     // nearest neighbours, or of (1, u_w) if there are none
@@ -260,7 +260,7 @@ __device__ void refill_node(typename Pop<STORE>::T* B, const Dims& d, const uint
       if (!valid_node(o_old, o_new, m)) continue;
       float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
       for (int i = 0; i < kQ; ++i) {
-        const float g = ld<STORE>(B, i, d.N, m);
+        const float g = ld<STORE>(B, i, d.S, m);
         dr += g;
         jx += cx_of(i) * g;
         jy += cy_of(i) * g;
@@ -295,7 +295,7 @@ __device__ void refill_node(typename Pop<STORE>::T* B, const Dims& d, const uint
   mom[0] = mom[1] = mom[2] = 0.0;
   for (int i = 0; i < kQ; ++i) {
     const float g = ge[i] - geq(i, rho_e, ux, uy, uz) + geq(i, rho_e, wx, wy, wz);
-    Pop<STORE>::store(B + (size_t)i * d.N + node_index(x, y, z, d.nx, d.ny), g);
+    Pop<STORE>::store(B + (size_t)i * d.S + node_index(x, y, z, d.nx, d.ny), g);
     const double gd = (double)g;
     mom[0] += cx_of(i) * gd;
     mom[1] += cy_of(i) * gd;
@@ -381,7 +381,7 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
       if (o_new[n] != p || o_old[n] != kFluid) return;
       double mom[3] = {0, 0, 0};
       for (int k = 0; k < kQ; ++k) {
-        const double g = (double)ld<STORE>(B, k, d.N, n);
+        const double g = (double)ld<STORE>(B, k, d.S, n);
         mom[0] += cx_of(k) * g;
         mom[1] += cy_of(k) * g;
         mom[2] += cz_of(k) * g;

@@ -344,7 +344,7 @@ k_ibm_prepass(const typename Pop<STORE>::T* __restrict__ A, Dims d, float3 F0, c
   for (int i = 0; i < kQ; ++i) {
     const uint32_t src = node_index(wrap1(x - cx_of(i), d.nx), wrap1(y - cy_of(i), d.ny), wrap1(z - cz_of(i), d.nz),
                                     d.nx, d.ny);
-    const float g = Pop<STORE>::load(A + (size_t)i * d.N + src);
+    const float g = Pop<STORE>::load(A + (size_t)i * d.S + src);
     drho += g;
     jx += cx_of(i) * g;
     jy += cy_of(i) * g;

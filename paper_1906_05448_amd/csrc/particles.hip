@@ -248,9 +248,9 @@ k_release_overwrite(typename Pop<STORE>::T* f, Dims d, const uint32_t* __restric
     const float uy = (float)(U[3 * p + 1] + (W[2] * r0 - W[0] * r2));
     const float uz = (float)(U[3 * p + 2] + (W[0] * r1 - W[1] * r0));
     float dr = 0.0f;
-    for (int k = 0; k < kQ; ++k) dr += Pop<STORE>::load(f + (size_t)k * d.N + n);
+    for (int k = 0; k < kQ; ++k) dr += Pop<STORE>::load(f + (size_t)k * d.S + n);
     const float rho = 1.0f + dr;
-    for (int k = 0; k < kQ; ++k) Pop<STORE>::store(f + (size_t)k * d.N + n, geq(k, rho, ux, uy, uz));
+    for (int k = 0; k < kQ; ++k) Pop<STORE>::store(f + (size_t)k * d.S + n, geq(k, rho, ux, uy, uz));
   }
 }
 
