@@ -52,9 +52,12 @@ MIN_GAP = 2.0          # centre distance >= 2r + 2 at placement
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_traffic_512cubed.md")
-TRAFFIC_SOURCES = ("paper_1906_05448_amd/csrc/dense.hip", "paper_1906_05448_amd/csrc/d3q19.hpp")
+# the kernels and the population layout (array stride and pad) they run on
+TRAFFIC_SOURCES = ("paper_1906_05448_amd/csrc/dense.hip", "paper_1906_05448_amd/csrc/d3q19.hpp",
+                   "paper_1906_05448_amd/csrc/internal.hpp")
 PIPE27_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipe27_traffic_160x160x480.md")
-PIPE27_SOURCES = ("paper_1906_05448_amd/csrc/d3q27.hip", "paper_1906_05448_amd/csrc/d3q27.hpp")
+PIPE27_SOURCES = ("paper_1906_05448_amd/csrc/d3q27.hip", "paper_1906_05448_amd/csrc/d3q27.hpp",
+                  "paper_1906_05448_amd/csrc/internal.hpp")
 
 
 def kernel_source_hash(sources=None):
