@@ -151,6 +151,23 @@ __device__ __forceinline__ Node shfl_node(const Node& v, int src) {
   return o;
 }
 
+// Exact fixed-point form of a histogram value v: v = hi 2^-32 + lo 2^-72
+// with hi = floor(v 2^32) (two's complement) and 0 <= lo <= 2^40. Scaling by
+// powers of two, the floor and the fraction are exact in FP64; lo rounds
+// off bits below 2^-72 (below 2^-12 of an ulp of the values summed here). A
+// workgroup sums at most 2^23 values (2^31 nodes over at least 256
+// workgroups), which fits both words for |v| < 2^8.
+__device__ __forceinline__ void fixed_split(double v, unsigned long long& hi, unsigned long long& lo) {
+  const double t = v * 4294967296.0;  // 2^32
+  const double a = floor(t);
+  hi = (unsigned long long)(long long)a;
+  lo = (unsigned long long)rint((t - a) * 1099511627776.0);  // 2^40
+}
+
+__device__ __forceinline__ double fixed_join(unsigned long long hi, unsigned long long lo) {
+  return (double)(long long)hi * (1.0 / 4294967296.0) + (double)lo * (1.0 / 4722366482869645213696.0);
+}
+
 // Work of the sums pass: (64-node row segment, y) columns, each cut into
 // z runs so that there are about eight runs per wavefront (the runs are
 // dealt out in a fixed order; eight or more keep the last round short).
@@ -180,10 +197,10 @@ __global__ void __launch_bounds__(kSBlock)
 k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key,
              const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om, Dims d,
              double nu, int nbins, double* __restrict__ part, int stride, ZPlan zp, uint32_t per_xcd) {
-  extern __shared__ double hist_lds[];  // [wave][5][nbins]
+  extern __shared__ unsigned long long hist_lds[];  // [wave][5][2][nbins]: fixed-point words
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
-  double* hw = hist_lds + (size_t)wv * 5 * nbins;
-  for (int i = lane; i < 5 * nbins; i += 64) hw[i] = 0.0;
+  unsigned long long* hw = hist_lds + (size_t)wv * 10 * nbins;
+  for (int i = lane; i < 10 * nbins; i += 64) hw[i] = 0ull;
   __builtin_amdgcn_wave_barrier();
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const uint32_t N = d.N;
@@ -192,7 +209,6 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
   const uint32_t waves = gridDim.x * kSegWaves;
   double s[kStatScalars] = {};
   double umax2 = 0.0;
-  const unsigned long long lt = (1ull << lane) - 1ull;
   for (uint32_t it = logical * kSegWaves + (uint32_t)wv; it < zp.items; it += waves) {
     const uint32_t zc = it / zp.cols, col = it - zc * zp.cols;
     const uint32_t yy = col / zp.segs;
@@ -273,25 +289,20 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
       }
       zm = c0;
       c0 = cz;
-      // histograms: fluid nodes within the profile range
+      // histograms: fluid nodes within the profile range, summed exactly
+      // in fixed point (integer sums do not depend on the order)
       const bool binned = live && k0 >= kKeyFluid && k0 != kKeyFar;
-      const uint32_t bin = k0 & 0x7FFFFFFFu;
-      unsigned long long todo = __ballot(binned);
-      if (todo == 0ull) continue;
-      uint32_t rank = 0, maxrank = 0;
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
-        const unsigned long long m = __ballot(binned && bin == bb);
-        if (binned && bin == bb) rank = (uint32_t)__popcll(m & lt);
-        maxrank = max(maxrank, (uint32_t)__popcll(m) - 1u);
-        todo &= ~m;
-      }
-      const double val[5] = {1.0, ke, eps_m, vz, vz * vz};
-      for (uint32_t t = 0; t <= maxrank; ++t) {
-        if (binned && rank == t)
-          for (int c = 0; c < 5; ++c) hw[(size_t)c * nbins + bin] += val[c];
-        __builtin_amdgcn_wave_barrier();
+      if (binned) {
+        const uint32_t bin = k0 & 0x7FFFFFFFu;
+        atomicAdd(&hw[bin], 1ull);  // the node count, an integer
+        const double val[4] = {ke, eps_m, vz, vz * vz};
+#pragma unroll
+        for (int c = 1; c < 5; ++c) {
+          unsigned long long hi, lo;
+          fixed_split(val[c - 1], hi, lo);
+          atomicAdd(&hw[(size_t)(2 * c) * nbins + bin], hi);
+          atomicAdd(&hw[(size_t)(2 * c + 1) * nbins + bin], lo);
+        }
       }
     }
   }
@@ -310,11 +321,17 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
     for (int c = 0; c < kStatScalars; ++c) out[c] = s[c];
     out[kStatUmax2] = mx[0];
   }
-  // wavefront histograms added in wavefront order
+  // the wavefronts' fixed-point histograms added as integers, then one
+  // rounding to FP64 per block and bin
+  __syncthreads();
   for (int i = threadIdx.x; i < 5 * nbins; i += kSBlock) {
-    double t = 0.0;
-    for (int w = 0; w < kSegWaves; ++w) t += hist_lds[(size_t)w * 5 * nbins + i];
-    out[kStatScalars + i] = t;
+    const int c = i / nbins, bin = i - c * nbins;
+    unsigned long long hi = 0ull, lo = 0ull;
+    for (int w = 0; w < kSegWaves; ++w) {
+      hi += hist_lds[((size_t)w * 10 + 2 * c) * nbins + bin];
+      lo += hist_lds[((size_t)w * 10 + 2 * c + 1) * nbins + bin];
+    }
+    out[kStatScalars + i] = c == 0 ? (double)hi : fixed_join(hi, lo);
   }
 }
 
@@ -372,7 +389,7 @@ hipError_t launch_stats(const Ctx& c, const float* u, const float* rho, uint32_t
   // at once (whole XCD groups, at most kStatGrid blocks): no block waits for
   // another to finish. The sums then depend on the device's size but not on
   // the run.
-  const size_t lds = (size_t)kSegWaves * 5 * std::max(nbins, 1) * sizeof(double);
+  const size_t lds = (size_t)kSegWaves * 10 * std::max(nbins, 1) * sizeof(unsigned long long);
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
