@@ -21,10 +21,9 @@
 //            beside (loaded only at the segment's ends), the y neighbours
 //            from coalesced row loads; the velocity of a node inside a sphere
 //            is U + Omega x (x - X) evaluated in FP64 where needed. Histogram
-//            bins are summed per wavefront in LDS: the binned lanes are
-//            ranked among the lanes of the same bin, and rank by rank each
-//            adds its values with a plain read-modify-write, so a bin's sum
-//            follows lane order and then the wavefront's order of nodes.
+//            bins are summed per wavefront in LDS as exact two-word fixed
+//            point (integer atomics, whose order does not matter), added
+//            over the workgroup's wavefronts and rounded once to FP64.
 //   reduce   one workgroup per column adds the per-block partials in order
 #include "device_util.hpp"
 #include "internal.hpp"
