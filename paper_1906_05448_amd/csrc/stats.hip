@@ -94,21 +94,47 @@ struct Vel3 {
   double v[3];
 };
 
-// Rigid-body velocity of sphere p at node (x, y, z).
-__device__ __forceinline__ Vel3 rigid_at(uint32_t p, int x, int y, int z, const double* X, const double* U,
-                                      const double* Om, int nx, int ny, int nz) {
-  const double r[3] = {min_image((double)x - X[3 * p], nx), min_image((double)y - X[3 * p + 1], ny),
-                       min_image((double)z - X[3 * p + 2], nz)};
-  const double* w = Om + 3 * p;
+// Motion of one sphere: position, velocity, angular velocity.
+struct Rigid {
+  double X[3], U[3], W[3];
+};
+
+__device__ __forceinline__ Rigid rigid_load(uint32_t p, const double* X, const double* U, const double* Om) {
+  Rigid s;
+  for (int c = 0; c < 3; ++c) {
+    s.X[c] = X[3 * p + c];
+    s.U[c] = U[3 * p + c];
+    s.W[c] = Om[3 * p + c];
+  }
+  return s;
+}
+
+// Rigid-body velocity U + Omega x (x - X) of sphere s at node (x, y, z).
+__device__ __forceinline__ Vel3 rigid_vel(const Rigid& s, int x, int y, int z, int nx, int ny, int nz) {
+  const double r[3] = {min_image((double)x - s.X[0], nx), min_image((double)y - s.X[1], ny),
+                       min_image((double)z - s.X[2], nz)};
+  const double* w = s.W;
   Vel3 m;
-  m.v[0] = U[3 * p] + (w[1] * r[2] - w[2] * r[1]);
-  m.v[1] = U[3 * p + 1] + (w[2] * r[0] - w[0] * r[2]);
-  m.v[2] = U[3 * p + 2] + (w[0] * r[1] - w[1] * r[0]);
+  m.v[0] = s.U[0] + (w[1] * r[2] - w[2] * r[1]);
+  m.v[1] = s.U[1] + (w[2] * r[0] - w[0] * r[2]);
+  m.v[2] = s.U[2] + (w[0] * r[1] - w[1] * r[0]);
   return m;
 }
 
-__device__ __forceinline__ void masked_at(uint32_t k, const float* v, int x, int y, int z, const double* X,
-                                          const double* U, const double* Om, const Dims& d, double m[3]) {
+// Rigid-body velocity of sphere p at node (x, y, z).
+__device__ __forceinline__ Vel3 rigid_at(uint32_t p, int x, int y, int z, const double* X, const double* U,
+                                      const double* Om, int nx, int ny, int nz) {
+  return rigid_vel(rigid_load(p, X, U, Om), x, y, z, nx, ny, nz);
+}
+
+// Masked velocity of a node with key k: sphere ps's motion (already loaded
+// into s, ps = kNoSphere if none) serves the nodes inside ps; a node inside
+// another sphere loads that sphere's motion.
+constexpr uint32_t kNoSphere = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void masked_at(uint32_t k, const float* v, int x, int y, int z, uint32_t ps,
+                                          const Rigid& s, const double* X, const double* U, const double* Om,
+                                          const Dims& d, double m[3]) {
   if (k >= kKeyFluid) {
     m[0] = v[0];
     m[1] = v[1];
@@ -119,11 +145,14 @@ __device__ __forceinline__ void masked_at(uint32_t k, const float* v, int x, int
     m[0] = m[1] = m[2] = 0.0;
     return;
   }
-  const Vel3 r = rigid_at(k - 1u, x, y, z, X, U, Om, d.nx, d.ny, d.nz);
+  const Vel3 r = k - 1u == ps ? rigid_vel(s, x, y, z, d.nx, d.ny, d.nz)
+                              : rigid_at(k - 1u, x, y, z, X, U, Om, d.nx, d.ny, d.nz);
   m[0] = r.v[0];
   m[1] = r.v[1];
   m[2] = r.v[2];
 }
+
+__device__ __forceinline__ bool in_sphere_key(uint32_t k) { return k < kKeyFluid && k != kKeyWall; }
 
 constexpr int kSegWaves = kSBlock / 64;
 
@@ -192,7 +221,9 @@ __host__ __device__ inline ZPlan zplan(int nx, int ny, int nz, uint32_t waves) {
 // neighbouring columns, on the same XCD, load as well) and the density; the
 // x neighbours come from the lanes beside, the nodes beyond the segment's
 // ends from two lanes' extra loads.
-__global__ void __launch_bounds__(kSBlock)
+// Held at three wavefronts per SIMD (168 VGPRs, 8 spilled): uncapped, the
+// loaded sphere motion takes it to 180 and two wavefronts.
+__global__ void __launch_bounds__(kSBlock, 3)
 k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const uint32_t* __restrict__ key,
              const double* __restrict__ X, const double* __restrict__ U, const double* __restrict__ Om, Dims d,
              double nu, int nbins, double* __restrict__ part, int stride, ZPlan zp, uint32_t per_xcd) {
@@ -251,14 +282,22 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
         for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * ((double)nb[2 * ax]->u[c] - (double)nb[2 * ax + 1]->u[c]);
       const double eps_raw = dissipation_of(G, nu);
       double eps_m = eps_raw;
+      // the sphere of the node or of its first neighbour inside one, whose
+      // motion is loaded once for the node and its neighbours
+      uint32_t ps = in_sphere_key(c0.k) ? c0.k - 1u : kNoSphere;
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (ps == kNoSphere && in_sphere_key(nb[j]->k)) ps = nb[j]->k - 1u;
+      Rigid rs{};
+      if (ps != kNoSphere) rs = rigid_load(ps, X, U, Om);
       if (any_masked) {
         const int nxs[6] = {xr, xl, xc, xc, xc, xc}, nys[6] = {y, y, yp, ym, y, y}, nzs[6] = {z, z, z, z, zpl, zmi};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           double mp[3], mm[3];
           const int a = 2 * ax, b = 2 * ax + 1;
-          masked_at(nb[a]->k, nb[a]->u, nxs[a], nys[a], nzs[a], X, U, Om, d, mp);
-          masked_at(nb[b]->k, nb[b]->u, nxs[b], nys[b], nzs[b], X, U, Om, d, mm);
+          masked_at(nb[a]->k, nb[a]->u, nxs[a], nys[a], nzs[a], ps, rs, X, U, Om, d, mp);
+          masked_at(nb[b]->k, nb[b]->u, nxs[b], nys[b], nzs[b], ps, rs, X, U, Om, d, mm);
           for (int c = 0; c < 3; ++c) G[c][ax] = 0.5 * (mp[c] - mm[c]);
         }
         eps_m = dissipation_of(G, nu);
@@ -268,7 +307,7 @@ k_stats_sums(const float* __restrict__ u, const float* __restrict__ rho, const u
       const uint32_t k0 = c0.k;
       if (live) {
         double vm[3];
-        masked_at(k0, c0.u, xc, y, z, X, U, Om, d, vm);
+        masked_at(k0, c0.u, xc, y, z, ps, rs, X, U, Om, d, vm);
         s[kStatKeRaw] += ke;
         s[kStatEpsRaw] += eps_raw;
         s[kStatKeMasked] += 0.5 * ((vm[0] * vm[0] + vm[1] * vm[1]) + vm[2] * vm[2]);
