@@ -179,10 +179,11 @@ __device__ __forceinline__ Node shfl_node(const Node& v, int src) {
   return o;
 }
 
-// Exact fixed-point form of a histogram value v: v = hi 2^-32 + lo 2^-72
-// with hi = floor(v 2^32) (two's complement) and 0 <= lo <= 2^40. Scaling by
+// Fixed-point form of a histogram value v: v = hi 2^-32 + lo 2^-72 with
+// hi = floor(v 2^32) (two's complement) and 0 <= lo <= 2^40. Scaling by
 // powers of two, the floor and the fraction are exact in FP64; lo rounds
-// off bits below 2^-72 (below 2^-12 of an ulp of the values summed here). A
+// off the bits below 2^-72, at most 2^-73 per value, far below the FP64
+// rounding of a workgroup's sums. The integer sums themselves are exact. A
 // workgroup sums at most 2^23 values (2^31 nodes over at least 256
 // workgroups), which fits both words for |v| < 2^8.
 __device__ __forceinline__ void fixed_split(double v, unsigned long long& hi, unsigned long long& lo) {
