@@ -8,7 +8,8 @@ immersed boundary with released moving spheres in contact (FP32 and FP16
 storage), the bounce-back and immersed-boundary pipe walls and the D3Q27
 pipe solver. A restored context reports the saved fields at once; a blob of
 another configuration or a truncated one is rejected and leaves the context
-as it was."""
+as it was. The blob's populations are the arrays back to back, whatever the
+spacing of the device arrays."""
 import numpy as np
 import pytest
 
@@ -164,3 +165,32 @@ def test_rejected_particles_leave_the_context_unchanged(bc):
         runs.append(_snap(g))
         g.close()
     _assert_same(runs[1], runs[0])
+
+
+@pytest.mark.parametrize("store", [0, 1])
+def test_blob_populations_are_back_to_back_arrays(store):
+    """The blob holds the 19 population arrays of N elements back to back
+    right after its header (the device arrays are further apart than their
+    length): summed over the arrays, the shifted populations g = f - w
+    (FP16: scaled by 2^14) give rho - 1 at every node, against the density
+    the context reports."""
+    shape = (24, 20, 16)
+    N = int(np.prod(shape))
+    rng = np.random.default_rng(11)
+    u0 = (0.02 * rng.standard_normal((3,) + shape)).astype(np.float32)
+    rho0 = (1.0 + 0.01 * rng.standard_normal(shape)).astype(np.float32)
+    g = gpu_lattice(gpu_config(nx=shape[0], ny=shape[1], nz=shape[2], tau=0.6, store=store))
+    g.set_fields(u0, rho0)
+    g.step(3)
+    _, rho = g.get_fields()
+    blob = g.get_state()
+    g.close()
+    head = int(np.frombuffer(blob[12:16].tobytes(), np.uint32)[0])
+    elem = 4 if store == 0 else 2
+    raw = blob[head:head + 19 * N * elem].tobytes()
+    if store == 0:
+        pops = np.frombuffer(raw, np.float32).astype(np.float64)
+    else:
+        pops = np.frombuffer(raw, np.float16).astype(np.float64) / 16384.0
+    rho_blob = 1.0 + pops.reshape(19, N).sum(axis=0)
+    np.testing.assert_allclose(rho_blob, np.asarray(rho, np.float64).reshape(-1), rtol=0, atol=2e-6)
