@@ -203,6 +203,8 @@ struct Plan {
   size_t owner[2], solid_bits, wall_bits;
   size_t pb_acc, pb_list, pb_off;  // pipe TKE budget
   size_t link_node, link_q, link_meta, link_count, link_part;
+  size_t patch_cnt, patch;  // bounce-back patch lists (rows of 512 nodes)
+  bool patches;
   uint32_t link_slices;
   size_t wl_node, wl_q, wl_meta;
   uint32_t link_cap, wl_count;
@@ -272,6 +274,14 @@ Plan plan(const lbm_config& c) {
     p.link_count = take(P * 4 + 4);
     p.link_slices = std::max<uint32_t>((p.link_cap + kLinkSlice - 1) / kLinkSlice, 1);
     p.link_part = take(P * p.link_slices * 6 * sizeof(double) + 8);
+    // The stream-collide kernels that stage whole rows of 512 nodes take the
+    // interpolated values as per-row patches.
+    p.patches = P > 0 && c.nx == 512 && c.lattice != LBM_LATTICE_D3Q27;
+    if (p.patches) {
+      const size_t rows = (size_t)c.ny * (size_t)c.nz;
+      p.patch_cnt = take(rows * 4);
+      p.patch = take(rows * kPatchCap * 8);
+    }
     p.wl_count = wall_link_count(c);
     p.wl_node = take((size_t)p.wl_count * 4 + 4);
     p.wl_q = take((size_t)p.wl_count * 4 + 4);
@@ -502,7 +512,8 @@ hipError_t step_ibb(Ctx& c) {
     if ((e = fork_side(c)) != hipSuccess) return e;
     if ((e = on_side(c, particles_and_geometry)) != hipSuccess) return e;
   }
-  e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt); });
+  // the link pass listed this step's patches when there are particles
+  e = timed(c, LBM_K_STREAM_COLLIDE, [&] { return launch_stream_collide(c, c.f_cur, c.f_nxt, c.np > 0); });
   if (e != hipSuccess) return e;
   if (c.np > 0) {
     e = ov ? join_side(c) : particles_and_geometry();
@@ -623,7 +634,15 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     c.ibb.owner[0] = (uint32_t*)(base + p.owner[0]);
     c.ibb.owner[1] = (uint32_t*)(base + p.owner[1]);
   }
+  c.ibb.patches = false;
+  c.ibb.patch_cnt = nullptr;
+  c.ibb.patch = nullptr;
   if (cfg->bc == LBM_BC_IBB) {
+    if (p.patches) {
+      c.ibb.patches = true;
+      c.ibb.patch_cnt = (uint32_t*)(base + p.patch_cnt);
+      c.ibb.patch = (uint2*)(base + p.patch);
+    }
     c.ibb.link_node = (uint32_t*)(base + p.link_node);
     c.ibb.link_q = (float*)(base + p.link_q);
     c.ibb.link_meta = (uint8_t*)(base + p.link_meta);

@@ -176,6 +176,8 @@ template <> struct Pop<0> {
   using T = float;
   __device__ static __forceinline__ float load(const T* p) { return *p; }
   __device__ static __forceinline__ void store(T* p, float v) { *p = v; }
+  // the bits store() writes
+  __device__ static __forceinline__ uint32_t bits(float v) { return __float_as_uint(v); }
   // Streaming store (non-temporal hint): for the fused kernel's output,
   // which no one reads before the next step.
   __device__ static __forceinline__ void store_stream(T* p, float v) { __builtin_nontemporal_store(v, p); }
@@ -189,6 +191,10 @@ template <> struct Pop<1> {
   using T = _Float16;
   __device__ static __forceinline__ float load(const T* p) { return static_cast<float>(*p) * (1.0f / kHalfScale); }
   __device__ static __forceinline__ void store(T* p, float v) { *p = static_cast<_Float16>(v * kHalfScale); }
+  // the bits store() writes
+  __device__ static __forceinline__ uint32_t bits(float v) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, static_cast<_Float16>(v * kHalfScale));
+  }
   __device__ static __forceinline__ void store_stream(T* p, float v) {
     __builtin_nontemporal_store(static_cast<_Float16>(v * kHalfScale), p);
   }

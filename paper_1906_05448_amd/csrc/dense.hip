@@ -28,6 +28,16 @@ struct IbView {
   const uint32_t* nobody;  // nodes without body force (outside a pipe), or null
 };
 
+// Bounce-back patches of the current step for the row kernels (cnt null:
+// none): per row of 512 nodes, cnt[row] records (x | opposite direction <<
+// 16, stored value bits), each replacing the staged value that node x pulls
+// for that direction (its ghost slot).
+struct PatchView {
+  const uint32_t* cnt;
+  const uint2* rec;
+};
+static_assert(kPatchCap <= 256, "one patch record per thread of the row kernels");
+
 // Body force at node n: none where the mask says so.
 __device__ __forceinline__ float3 body_force_at(const IbView& v, uint32_t n, float3 F0) {
   if (v.nobody && ((v.nobody[n >> 5] >> (n & 31u)) & 1u)) return make_float3(0.0f, 0.0f, 0.0f);
@@ -248,7 +258,7 @@ k_stream_collide_seg(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, Dims d, MrtRates r, float3 F0,
-                     IbView ib, uint32_t* __restrict__ err) {
+                     IbView ib, PatchView pv, uint32_t* __restrict__ err) {
   __shared__ uint32_t seg_all[4][kQ][kSegRow];
   __shared__ uint16_t tail_all[4][kQ];
   const uint32_t b = blockIdx.x;
@@ -278,11 +288,15 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
                              r00, rp0, r0p, rp0, rm0, r0p, r0m, rpp, rpm};
   constexpr bool pair_live = true;
 
-  // stage: every load of the segment issued before the first LDS write
+  // stage: every load of the segment issued before the first LDS write;
+  // this thread's patch record (at most one: kPatchCap <= 256) with them
   uint32_t v[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i)
     v[i] = __builtin_nontemporal_load((const uint32_t*)(A + (size_t)i * S + srow[i] + x0 + 2 * (int)lane));
+  const uint32_t np = pv.cnt ? min(pv.cnt[rowi], kPatchCap) : 0u;
+  uint2 pr = make_uint2(0u, 0u);
+  if (threadIdx.x < np) pr = pv.rec[(size_t)rowi * kPatchCap + threadIdx.x];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];  // halves 2 + 2 lane, 3 + 2 lane
@@ -292,6 +306,15 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
     if (cx_of(i) < 0 && lane == 0u) ((uint16_t*)seg_all[wl][i])[2 + w] = (uint16_t)(v[i] & 0xFFFFu);
   }
   __syncthreads();  // the neighbours' end nodes are in place
+  if (np) {  // the same for the whole workgroup
+    // the slot node x pulls direction i from: half 2 + (x mod 128) - c_ix of
+    // wavefront x / 128's staged row i
+    if (threadIdx.x < np) {
+      const uint32_t x = pr.x & 0xFFFFu, i = pr.x >> 16;
+      ((uint16_t*)seg_all[x >> 7][i])[2 + (int)(x & 127u) - cx_of((int)i)] = (uint16_t)pr.y;
+    }
+    __syncthreads();
+  }
 
   bool bad = false;
   // one round at a time (unrolled, the rounds' values would all be live)
@@ -346,7 +369,7 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
 template <int MODE>
 __global__ void __launch_bounds__(512)
 k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims d, MrtRates r, float3 F0, IbView ib,
-                       uint32_t* __restrict__ err) {
+                       PatchView pv, uint32_t* __restrict__ err) {
   constexpr int kW = 8, kRow = 66;  // wavefronts per workgroup; floats per staged row: x0 - 1 .. x0 + 64
   __shared__ float seg_all[kW][kQ][kRow];
   const uint32_t b = blockIdx.x;
@@ -386,6 +409,11 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
     if (cx_of(i) > 0 && wl < 0) e[i] = rowp[xl];
     if (cx_of(i) < 0 && wr < 0) e[i] = rowp[xr];
   }
+  // this thread's patch record (at most one: kPatchCap <= 512) with the
+  // staging loads
+  const uint32_t np = pv.cnt ? min(pv.cnt[rowi], kPatchCap) : 0u;
+  uint2 pr = make_uint2(0u, 0u);
+  if (threadIdx.x < np) pr = pv.rec[(size_t)rowi * kPatchCap + threadIdx.x];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];
@@ -399,6 +427,15 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
     }
   }
   __syncthreads();  // the neighbours' end nodes are in place
+  if (np) {  // the same for the whole workgroup
+    // the slot node x pulls direction i from: 1 + (x mod 64) - c_ix of
+    // wavefront x / 64's staged row i (whole rows only: bx = 0)
+    if (threadIdx.x < np) {
+      const uint32_t xp = pr.x & 0xFFFFu, i = pr.x >> 16;
+      seg_all[xp >> 6][i][1 + (int)(xp & 63u) - cx_of((int)i)] = __uint_as_float(pr.y);
+    }
+    __syncthreads();
+  }
   const uint32_t n = r00 + (uint32_t)x;
   float3 F = F0;
   if (MODE == 2) {
@@ -502,16 +539,17 @@ hipError_t launch_one_node(const Ctx& c, const void* A, void* B, const IbView& i
   return hipGetLastError();
 }
 
-hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B) {
+hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B, bool patches) {
   if (lattice27(c)) return launch_stream_collide27(c, A, B);
   const dim3 block(256);
   const IbView none{nullptr, nullptr, nullptr, 0, nullptr};
+  const PatchView pv{patches && c.ibb.patches ? c.ibb.patch_cnt : nullptr, c.ibb.patch};
   if (use_row32_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_row32<0>), dim3(c.dims.per_xcdr * 8), dim3(512), 0, c.stream,
-                       (const float*)A, (float*)B, c.dims, c.rates, c.body_force, none, c.err);
+                       (const float*)A, (float*)B, c.dims, c.rates, c.body_force, none, pv, c.err);
   else if (use_row_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_row<0>), dim3(c.dims.per_xcdr * 8), block, 0, c.stream,
-                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, none, c.err);
+                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, none, pv, c.err);
   else if (use_seg_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_seg<0>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
                        (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, none, c.err);
@@ -526,12 +564,13 @@ hipError_t launch_stream_collide_ibm(const Ctx& c, const void* A, void* B) {
   const dim3 block(256);
   const int b = c.ibm.cur;
   const IbView ib{c.ibm.bits[b], c.ibm.rank[b], c.ibm.fib[b], c.ibm.s_cap, ibm_body_force_mask(c)};
+  const PatchView nop{nullptr, nullptr};
   if (use_row32_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_row32<2>), dim3(c.dims.per_xcdr * 8), dim3(512), 0, c.stream,
-                       (const float*)A, (float*)B, c.dims, c.rates, c.body_force, ib, c.err);
+                       (const float*)A, (float*)B, c.dims, c.rates, c.body_force, ib, nop, c.err);
   else if (use_row_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_row<2>), dim3(c.dims.per_xcdr * 8), block, 0, c.stream,
-                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, ib, c.err);
+                       (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, ib, nop, c.err);
   else if (use_seg_kernel(c))
     hipLaunchKernelGGL((k_stream_collide_seg<2>), dim3(c.dims.per_xcd2 * 8), block, 0, c.stream,
                        (const _Float16*)A, (_Float16*)B, c.dims, c.rates, c.body_force, ib, c.err);

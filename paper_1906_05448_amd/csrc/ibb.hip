@@ -6,6 +6,11 @@
 // is the solid node. That slot is read by no other node, so this kernel
 // writes the interpolated bounce-back value there before the dense kernel
 // runs, and the dense kernel stays a branch-free pull over fluid nodes.
+// Where the dense kernel stages whole 512-node rows in LDS, the value goes
+// instead into a list per row of the fluid node (patches), which that
+// kernel writes over the staged slot: one scattered 2- or 4-byte store per
+// link into the population arrays cost about 0.5 ms per step at 512^3 with
+// 28.8 M links (each a partial write of its own memory sector).
 //
 // Interpolation (Bouzidi, Firdaouss & Lallemand 2001) with the moving-wall
 // term delta = -6 w_a (c_a . u_w); coefficients of every branch sum to one
@@ -74,6 +79,29 @@ __device__ __forceinline__ float bounce_value(const typename Pop<STORE>::T* A, u
   return bounce_from(ga0, v1, v2, scheme, q, delta);
 }
 
+// Rank of each live lane's link in the list of its row: the lanes of a
+// wavefront hold consecutive links, so equal rows come in runs; the first
+// lane of each run takes the run's places with one atomic add and the
+// others count on from it (ranks per row stay distinct; their order does
+// not matter). Every lane of the wavefront must call it.
+__device__ __forceinline__ uint32_t row_rank(uint32_t* cnt, uint32_t row, bool live) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t prev = (uint32_t)__shfl_up((int)row, 1, 64);
+  const bool head = live && (lane == 0u || prev != row);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long ends = __ballot(head || !live);
+  const unsigned long long above = lane == 63u ? 0ull : (~0ull << (lane + 1u));
+  const unsigned long long later = ends & above;
+  const uint32_t next = later ? (uint32_t)__builtin_ctzll(later) : 64u;
+  uint32_t base = 0u;
+  if (head) base = atomicAdd(cnt + row, next - lane);
+  const unsigned long long upto = lane == 63u ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long mine = heads & upto;
+  const uint32_t h = mine ? 63u - (uint32_t)__builtin_clzll(mine) : lane;
+  const uint32_t b = (uint32_t)__shfl((int)base, (int)h, 64);
+  return b + (lane - h);
+}
+
 // One workgroup per slice of kLinkSlice links of a sphere (slices of one
 // sphere run side by side on different CUs): fill the ghost slots of its
 // links and reduce the slice's link forces and torques in FP64 in a fixed
@@ -83,7 +111,8 @@ __global__ void __launch_bounds__(kLinkBlock)
 k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, const double* __restrict__ U,
             const double* __restrict__ Om, uint32_t cap, uint32_t slices, const uint32_t* __restrict__ link_node,
             const float* __restrict__ link_q, const uint8_t* __restrict__ link_meta,
-            const uint32_t* __restrict__ link_count, double* __restrict__ part) {
+            const uint32_t* __restrict__ link_count, double* __restrict__ part, uint32_t* __restrict__ patch_cnt,
+            uint2* __restrict__ patch) {
   const int p = (int)(blockIdx.x / slices);
   const uint32_t g = blockIdx.x % slices;
   const uint32_t cnt = min(link_count[p], (g + 1u) * kLinkSlice);
@@ -134,32 +163,49 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
     }
 #pragma unroll
     for (int i = 0; i < kLinks; ++i) {
-      if (meta[i] == 0xFFu) continue;
-      const int a = (int)(meta[i] & 31u);
-      const uint32_t scheme = meta[i] >> 5;
-      int x, y, z;
-      unpack_xyz(nf[i], x, y, z);
-      const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
-      // lever arm x_w - X and wall velocity U + Omega x arm
-      const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q[i] * cx,
-                             min_image((double)y - Xp[1], d.ny) + (double)q[i] * cy,
-                             min_image((double)z - Xp[2], d.nz) + (double)q[i] * cz};
-      const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
-                            Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
-      const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
-      const float gnew = bounce_from(g0[i], g1[i], g2[i], scheme, q[i], delta);
-      Pop<STORE>::store(A + (size_t)opp_of(a) * d.S + ns[i], gnew);
-      const double fa = (double)g0[i] + (double)w_of(a);
-      const double fb = (double)gnew + (double)w_of(a);
-      const double c[3] = {(double)cx, (double)cy, (double)cz};
-      double Fl[3];
-      for (int k3 = 0; k3 < 3; ++k3) Fl[k3] = (c[k3] - uw[k3]) * fa + (c[k3] + uw[k3]) * fb;
-      F[0] += Fl[0];
-      F[1] += Fl[1];
-      F[2] += Fl[2];
-      T[0] += arm[1] * Fl[2] - arm[2] * Fl[1];
-      T[1] += arm[2] * Fl[0] - arm[0] * Fl[2];
-      T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
+      const bool live = meta[i] != 0xFFu;
+      float gnew = 0.0f;
+      uint32_t row = 0xFFFFFFFFu, key = 0u;
+      if (live) {
+        const int a = (int)(meta[i] & 31u);
+        const uint32_t scheme = meta[i] >> 5;
+        int x, y, z;
+        unpack_xyz(nf[i], x, y, z);
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of(a);
+        // lever arm x_w - X and wall velocity U + Omega x arm
+        const double arm[3] = {min_image((double)x - Xp[0], d.nx) + (double)q[i] * cx,
+                               min_image((double)y - Xp[1], d.ny) + (double)q[i] * cy,
+                               min_image((double)z - Xp[2], d.nz) + (double)q[i] * cz};
+        const double uw[3] = {Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]), Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]),
+                              Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0])};
+        const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
+        gnew = bounce_from(g0[i], g1[i], g2[i], scheme, q[i], delta);
+        row = (uint32_t)z * (uint32_t)d.ny + (uint32_t)y;
+        key = (uint32_t)x | ((uint32_t)opp_of(a) << 16);
+        const double fa = (double)g0[i] + (double)w_of(a);
+        const double fb = (double)gnew + (double)w_of(a);
+        const double c[3] = {(double)cx, (double)cy, (double)cz};
+        double Fl[3];
+        for (int k3 = 0; k3 < 3; ++k3) Fl[k3] = (c[k3] - uw[k3]) * fa + (c[k3] + uw[k3]) * fb;
+        F[0] += Fl[0];
+        F[1] += Fl[1];
+        F[2] += Fl[2];
+        T[0] += arm[1] * Fl[2] - arm[2] * Fl[1];
+        T[1] += arm[2] * Fl[0] - arm[0] * Fl[2];
+        T[2] += arm[0] * Fl[1] - arm[1] * Fl[0];
+      }
+      // the value listed under its fluid node's row, else (no lists, or the
+      // row's list full) stored into the ghost slot; every lane takes part
+      // in the ranking
+      bool listed = false;
+      if (patch_cnt) {
+        const uint32_t rank = row_rank(patch_cnt, row, live);
+        if (live && rank < kPatchCap) {
+          patch[(size_t)row * kPatchCap + rank] = make_uint2(key, Pop<STORE>::bits(gnew));
+          listed = true;
+        }
+      }
+      if (live && !listed) Pop<STORE>::store(A + (size_t)opp_of((int)(meta[i] & 31u)) * d.S + ns[i], gnew);
     }
   }
   double* out = part + (size_t)blockIdx.x * 6;
@@ -465,6 +511,12 @@ k_cover_refill(typename Pop<STORE>::T* B, Dims d, const uint32_t* __restrict__ o
   }
 }
 
+// Empties the per-row patch lists.
+__global__ void __launch_bounds__(256) k_patch_clear(uint32_t* __restrict__ cnt, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) cnt[i] = 0u;
+}
+
 }  // namespace
 
 hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double* U, const double* Om) {
@@ -481,15 +533,24 @@ hipError_t launch_ibb_links(const Ctx& c, void* A, const double* X, const double
     if (e != hipSuccess) return e;
   }
   if (c.np <= 0) return hipSuccess;
+  uint32_t* pcnt = nullptr;
+  if (c.ibb.patches) {
+    const uint32_t rows = (uint32_t)c.dims.ny * (uint32_t)c.dims.nz;
+    hipLaunchKernelGGL(k_patch_clear, dim3((rows + 255u) / 256u), dim3(256), 0, c.stream, c.ibb.patch_cnt, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pcnt = c.ibb.patch_cnt;
+  }
   const uint32_t slices = c.ibb.link_slices;
   const dim3 grid((uint32_t)c.np * slices);
   if (c.cfg.store == LBM_STORE_F32)
     hipLaunchKernelGGL(k_ibb_links<0>, grid, dim3(kLinkBlock), 0, c.stream, (float*)A, c.dims, X, U, Om, c.link_cap,
-                       slices, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.ibb.link_part);
+                       slices, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count, c.ibb.link_part, pcnt,
+                       c.ibb.patch);
   else
     hipLaunchKernelGGL(k_ibb_links<1>, grid, dim3(kLinkBlock), 0, c.stream, (_Float16*)A, c.dims, X, U, Om,
                        c.link_cap, slices, c.ibb.link_node, c.ibb.link_q, c.ibb.link_meta, c.ibb.link_count,
-                       c.ibb.link_part);
+                       c.ibb.link_part, pcnt, c.ibb.patch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_link_sum, dim3(((uint32_t)c.np + 63u) / 64u), dim3(64), 0, c.stream, c.np, slices,

@@ -239,7 +239,17 @@ struct IbbBufs {
   float* wl_q;
   uint8_t* wl_meta;
   uint32_t wl_count;
+  // Bounce-back patches (rows of 512 nodes, where the stream-collide
+  // kernels stage whole rows in LDS): the link pass lists each interpolated
+  // value under the row of its fluid node instead of storing it into the
+  // ghost slot, and the kernel writes it over the staged slot in LDS. A
+  // link beyond kPatchCap in its row falls back to the ghost slot.
+  bool patches;          // this context uses them
+  uint32_t* patch_cnt;   // [ny * nz] links listed per row this step
+  uint2* patch;          // [ny * nz][kPatchCap]: x | opposite direction << 16, stored value bits
 };
+
+constexpr uint32_t kPatchCap = 256;
 
 // Immersed boundary support. The support set S (marker stencils plus the
 // cells of the Kempe integrals) is a bitmask with a per-word exclusive rank,
@@ -397,7 +407,8 @@ hipError_t on_side(Ctx& c, F&& launch) {
 
 // Dense kernels (dense.hip).
 hipError_t launch_init_equilibrium(const Ctx& c, const float* u, const float* rho, void* f);
-hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B);
+// patches: apply the bounce-back patches the link pass listed this step.
+hipError_t launch_stream_collide(const Ctx& c, const void* A, void* B, bool patches = false);
 // D3Q27 pipe solver (d3q27.hip); the D3Q19 launchers dispatch to these
 // when the configuration selects that lattice.
 hipError_t launch_stream_collide27(const Ctx& c, const void* A, void* B);
