@@ -280,7 +280,7 @@ Plan plan(const lbm_config& c) {
     if (p.patches) {
       const size_t rows = (size_t)c.ny * (size_t)c.nz;
       p.patch_cnt = take(rows * 4);
-      p.patch = take(rows * kPatchCap * 8);
+      p.patch = take(rows * kPatchCap * (c.store == LBM_STORE_F16S ? 4 : 8));
     }
     p.wl_count = wall_link_count(c);
     p.wl_node = take((size_t)p.wl_count * 4 + 4);
@@ -641,7 +641,7 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t bytes, void* stream,
     if (p.patches) {
       c.ibb.patches = true;
       c.ibb.patch_cnt = (uint32_t*)(base + p.patch_cnt);
-      c.ibb.patch = (uint2*)(base + p.patch);
+      c.ibb.patch = base + p.patch;
     }
     c.ibb.link_node = (uint32_t*)(base + p.link_node);
     c.ibb.link_q = (float*)(base + p.link_q);

@@ -29,12 +29,12 @@ struct IbView {
 };
 
 // Bounce-back patches of the current step for the row kernels (cnt null:
-// none): per row of 512 nodes, cnt[row] records (x | opposite direction <<
-// 16, stored value bits), each replacing the staged value that node x pulls
-// for that direction (its ghost slot).
+// none): per row of 512 nodes, cnt[row] records of a node x, an opposite
+// direction and the stored value's bits, each replacing the staged value
+// that node x pulls for that direction (its ghost slot).
 struct PatchView {
   const uint32_t* cnt;
-  const uint2* rec;
+  const void* rec;  // FP16: one word per record, FP32: two (the link pass's layout)
 };
 static_assert(kPatchCap <= 256, "one patch record per thread of the row kernels");
 
@@ -295,8 +295,8 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
   for (int i = 0; i < kQ; ++i)
     v[i] = __builtin_nontemporal_load((const uint32_t*)(A + (size_t)i * S + srow[i] + x0 + 2 * (int)lane));
   const uint32_t np = pv.cnt ? min(pv.cnt[rowi], kPatchCap) : 0u;
-  uint2 pr = make_uint2(0u, 0u);
-  if (threadIdx.x < np) pr = pv.rec[(size_t)rowi * kPatchCap + threadIdx.x];
+  uint32_t pr = 0u;
+  if (threadIdx.x < np) pr = ((const uint32_t*)pv.rec)[(size_t)rowi * kPatchCap + threadIdx.x];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];  // halves 2 + 2 lane, 3 + 2 lane
@@ -310,8 +310,8 @@ k_stream_collide_row(const _Float16* __restrict__ A, _Float16* __restrict__ B, D
     // the slot node x pulls direction i from: half 2 + (x mod 128) - c_ix of
     // wavefront x / 128's staged row i
     if (threadIdx.x < np) {
-      const uint32_t x = pr.x & 0xFFFFu, i = pr.x >> 16;
-      ((uint16_t*)seg_all[x >> 7][i])[2 + (int)(x & 127u) - cx_of((int)i)] = (uint16_t)pr.y;
+      const uint32_t x = pr & 511u, i = (pr >> 9) & 31u;
+      ((uint16_t*)seg_all[x >> 7][i])[2 + (int)(x & 127u) - cx_of((int)i)] = (uint16_t)(pr >> 16);
     }
     __syncthreads();
   }
@@ -413,7 +413,7 @@ k_stream_collide_row32(const float* __restrict__ A, float* __restrict__ B, Dims 
   // staging loads
   const uint32_t np = pv.cnt ? min(pv.cnt[rowi], kPatchCap) : 0u;
   uint2 pr = make_uint2(0u, 0u);
-  if (threadIdx.x < np) pr = pv.rec[(size_t)rowi * kPatchCap + threadIdx.x];
+  if (threadIdx.x < np) pr = ((const uint2*)pv.rec)[(size_t)rowi * kPatchCap + threadIdx.x];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     seg[i][1 + lane] = v[i];

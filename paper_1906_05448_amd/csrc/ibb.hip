@@ -112,7 +112,7 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
             const double* __restrict__ Om, uint32_t cap, uint32_t slices, const uint32_t* __restrict__ link_node,
             const float* __restrict__ link_q, const uint8_t* __restrict__ link_meta,
             const uint32_t* __restrict__ link_count, double* __restrict__ part, uint32_t* __restrict__ patch_cnt,
-            uint2* __restrict__ patch) {
+            void* __restrict__ patch) {
   const int p = (int)(blockIdx.x / slices);
   const uint32_t g = blockIdx.x % slices;
   const uint32_t cnt = min(link_count[p], (g + 1u) * kLinkSlice);
@@ -165,7 +165,7 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
     for (int i = 0; i < kLinks; ++i) {
       const bool live = meta[i] != 0xFFu;
       float gnew = 0.0f;
-      uint32_t row = 0xFFFFFFFFu, key = 0u;
+      uint32_t row = 0xFFFFFFFFu, px = 0u, pi = 0u;
       if (live) {
         const int a = (int)(meta[i] & 31u);
         const uint32_t scheme = meta[i] >> 5;
@@ -181,7 +181,8 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
         const float delta = (float)(-6.0 * (double)w_of(a) * (cx * uw[0] + cy * uw[1] + cz * uw[2]));
         gnew = bounce_from(g0[i], g1[i], g2[i], scheme, q[i], delta);
         row = (uint32_t)z * (uint32_t)d.ny + (uint32_t)y;
-        key = (uint32_t)x | ((uint32_t)opp_of(a) << 16);
+        px = (uint32_t)x;
+        pi = (uint32_t)opp_of(a);
         const double fa = (double)g0[i] + (double)w_of(a);
         const double fb = (double)gnew + (double)w_of(a);
         const double c[3] = {(double)cx, (double)cy, (double)cz};
@@ -201,7 +202,11 @@ k_ibb_links(typename Pop<STORE>::T* A, Dims d, const double* __restrict__ X, con
       if (patch_cnt) {
         const uint32_t rank = row_rank(patch_cnt, row, live);
         if (live && rank < kPatchCap) {
-          patch[(size_t)row * kPatchCap + rank] = make_uint2(key, Pop<STORE>::bits(gnew));
+          const size_t at = (size_t)row * kPatchCap + rank;
+          if (STORE == 1)
+            ((uint32_t*)patch)[at] = px | (pi << 9) | (Pop<STORE>::bits(gnew) << 16);
+          else
+            ((uint2*)patch)[at] = make_uint2(px | (pi << 16), Pop<STORE>::bits(gnew));
           listed = true;
         }
       }

@@ -246,7 +246,10 @@ struct IbbBufs {
   // link beyond kPatchCap in its row falls back to the ghost slot.
   bool patches;          // this context uses them
   uint32_t* patch_cnt;   // [ny * nz] links listed per row this step
-  uint2* patch;          // [ny * nz][kPatchCap]: x | opposite direction << 16, stored value bits
+  // [ny * nz][kPatchCap] records of the node x, the opposite direction i and
+  // the stored value's bits: FP16 one word, x | i << 9 | bits << 16; FP32
+  // two words, x | i << 16 and the bits
+  void* patch;
 };
 
 constexpr uint32_t kPatchCap = 256;
